@@ -1,0 +1,204 @@
+/*
+ * iso.h - C ABI of the MI355X isochrone library (libiso.so).
+ *
+ * Operation (Baum, Buchhold, Dibbelt, Wagner, "Fast Computation of Isochrones
+ * in Road Networks"):
+ *   Section 3 (problem statement): given a directed graph G = (V, E) with
+ *   non-negative arc lengths, a source s and a limit tau, a vertex v is in
+ *   range iff d(s, v) <= tau; the answer is the set of isochrone edges, the
+ *   arcs (u, v) in E with exactly one endpoint in range.
+ *   Section 2 (CH, PHAST) and Section 5 (isoPHAST): the library answers it with
+ *   an upward contraction-hierarchy search from s followed by a level-ordered
+ *   downward sweep over the hierarchy - over every vertex (ISO_MODE_PLAIN) or
+ *   over the core and the active cells of a single-level partition only
+ *   (ISO_MODE_CELLS, the isoPHAST-CP query with the relaxed cell-flag rule of
+ *   the parallel-query paragraph of Section 6) - with isochrone edges
+ *   extracted during the sweep.
+ *
+ * Arithmetic is exact uint32: weights are in [0, 2^32 - 2]; ISO_INF =
+ * 2^32 - 1 marks "unreachable"; path lengths saturate at ISO_INF, so a
+ * reported distance is min(d(s, v), ISO_INF); tau must be <= 2^32 - 2, so
+ * saturation never changes which vertices are in range.
+ *
+ * Conventions for every entry point:
+ *   - Return value: ISO_OK (0) or a negative iso_status.  No call throws or
+ *     aborts across the ABI.  On error nothing is written to outputs except
+ *     that *edges is set to NULL; the graph handle stays usable.
+ *     iso_last_error() gives a thread-local message for the last failure.
+ *   - Vertex ids are the caller's original ids 0..n-1.
+ *   - Pointers named h_* / plain arrays are host memory; the library never
+ *     keeps a caller pointer after a call returns (inputs are copied).
+ *   - Arrays returned through iso_edge** are allocated by the library (host
+ *     memory) and released with iso_free().
+ *   - One iso_graph may be used by one thread at a time (ISO_EBUSY if a call
+ *     overlaps another on the same handle); distinct handles are independent.
+ */
+#ifndef ISO_H
+#define ISO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISO_INF 0xFFFFFFFFu
+#define ISO_TAU_MAX 0xFFFFFFFEu
+
+typedef enum {
+    ISO_OK = 0,
+    ISO_EINVAL = -1,    /* bad argument: NULL pointer, source >= n, tau > ISO_TAU_MAX, weight == ISO_INF, ... */
+    ISO_ENOMEM = -2,    /* host or device allocation failed, or a configured memory budget was exceeded */
+    ISO_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+    ISO_EFORMAT = -4,   /* preprocessed file missing fields, wrong version or checksum mismatch */
+    ISO_EBUSY = -6,     /* the handle is in use by another call */
+    ISO_ESTATE = -7     /* call not valid in the current state (e.g. server stopped) */
+} iso_status;
+
+typedef enum {
+    ISO_MODE_PLAIN = 0, /* sweep every vertex (PHAST one-to-all, Section 2) */
+    ISO_MODE_CELLS = 1  /* sweep the core, then the active cells only (isoPHAST-CP, Section 5) */
+} iso_mode;
+
+typedef struct iso_graph iso_graph;
+
+/* An isochrone edge: an arc (tail, head) of the input graph, original ids. */
+typedef struct {
+    uint32_t tail;
+    uint32_t head;
+} iso_edge;
+
+/*
+ * Input description for iso_load_graph.  All arrays are caller-owned host
+ * memory and are copied; self-loops are dropped and parallel arcs merged to
+ * their minimum weight (the answer is keyed on (tail, head), Section 3).
+ */
+typedef struct {
+    uint32_t n;                 /* |V| (>= 1, < 2^29: edge keys pack two ids in 29 bits each) */
+    uint64_t m;                 /* |E| (number of entries in tail/head/weight) */
+    const uint32_t *tail;       /* m tails, < n */
+    const uint32_t *head;       /* m heads, < n */
+    const uint32_t *weight;     /* m lengths, each <= 2^32 - 2 */
+    const double *xy;           /* optional, 2n coordinates (x0, y0, x1, y1, ...) for the partitioner */
+    const uint32_t *cell_of;    /* optional explicit single-level partition: a cell id < num_cells per vertex */
+    uint32_t num_cells;         /* cells of the single-level partition (Section 5); 0 = no partition:
+                                   the hierarchy is a plain CH and only ISO_MODE_PLAIN is available */
+    uint32_t max_cell_size;     /* upper bound on vertices per cell (0 = 2048); at most 4096 */
+    const char *prep_path;      /* optional: if the file exists and matches the input it is loaded instead
+                                   of preprocessing; otherwise the preprocessed data is written there */
+    int device;                 /* HIP device ordinal; -1 = host-only preprocessing (queries fail with ISO_EDEVICE) */
+    int threads;                /* host threads for preprocessing and upward searches (0 = all cores) */
+    int verbose;                /* 1 = progress lines on stderr during preprocessing */
+} iso_graph_desc;
+
+/* Sizes of a loaded graph (for reporting and tests). */
+typedef struct {
+    uint32_t n, n_core, num_cells, core_levels, max_cell_levels, max_cell_internal;
+    uint64_t m;                 /* arcs after merging parallel arcs and dropping self-loops */
+    uint64_t down_arcs;         /* entries of the downward graph incl. dummy entries (Section 5) */
+    uint64_t up_arcs;           /* arcs of the upward graph */
+    uint64_t shortcuts;         /* arcs added by contraction */
+    uint64_t device_bytes;      /* resident device memory of the graph */
+    double prep_seconds;        /* partition + contraction + layout (0 when loaded from a file) */
+} iso_graph_info;
+
+/* Per-call counters of the last query on a handle (phase times in ms). */
+typedef struct {
+    uint32_t lanes;             /* queries in the call */
+    uint32_t active_cells;      /* summed over lanes (cells swept) */
+    uint64_t swept_vertices;    /* vertices whose label was computed, summed over lanes */
+    uint64_t edges;             /* isochrone edges returned, summed over lanes */
+    uint64_t upward_settled;    /* vertices settled by the upward searches, summed over lanes */
+    double t_upward_ms, t_device_ms, t_sort_ms, t_total_ms;
+} iso_query_stats;
+
+/* Preprocess (or load) a graph and make it resident on the device. */
+int iso_load_graph(const iso_graph_desc *desc, iso_graph **out);
+void iso_free_graph(iso_graph *g);
+int iso_graph_get_info(const iso_graph *g, iso_graph_info *info);
+
+/*
+ * One isochrone query (Section 3).  *edges receives count arcs sorted by
+ * (tail, head) without duplicates; release with iso_free.  mode selects the
+ * full sweep or the cell-restricted sweep; both return the same set.
+ */
+int iso_query(iso_graph *g, uint32_t source, uint32_t tau, int mode,
+              iso_edge **edges, size_t *count);
+
+/*
+ * k queries in one call, answered by one sweep over the hierarchy with k
+ * distance labels per vertex.  offsets (caller-allocated, k + 1 entries)
+ * receives the start of each query's edges in *edges; query j's result is
+ * bit-identical to iso_query(sources[j], taus[j]).
+ */
+int iso_query_batch(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus,
+                    int mode, iso_edge **edges, size_t *offsets);
+
+/*
+ * Distance labels of one query (test hook).  dist (n entries, caller host
+ * memory) receives min(d(s, v), ISO_INF) for every vertex the sweep labelled
+ * (all vertices in ISO_MODE_PLAIN; core vertices and the vertices of active
+ * cells in ISO_MODE_CELLS) and ISO_INF elsewhere; swept (optional, n bytes)
+ * receives 1 for labelled vertices and 0 otherwise.
+ */
+int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode,
+                        uint32_t *dist, uint8_t *swept);
+
+/* Counters of the last query call on g. */
+int iso_last_query_stats(const iso_graph *g, iso_query_stats *stats);
+
+/*
+ * Tuning knobs of the device sweep (chosen by the autotuner; defaults are
+ * used when never set).  lanes_per_launch: queries per sweep in
+ * iso_query_batch (1..64); block: threads per workgroup of the level
+ * kernels (64..1024, multiple of 64); lds_top: vertices at the top of the
+ * hierarchy swept by one workgroup out of LDS (0 disables).
+ */
+typedef struct {
+    uint32_t lanes_per_launch;
+    uint32_t block;
+    uint32_t lds_top;
+    uint32_t use_graph;         /* 1 = replay level launches from a captured hipGraph */
+} iso_tuning;
+int iso_set_tuning(iso_graph *g, const iso_tuning *t);
+int iso_get_tuning(const iso_graph *g, iso_tuning *t);
+
+/*
+ * Read-only view of the preprocessed hierarchy (host memory owned by the
+ * library, valid until iso_free_graph).  Sweep positions number the vertices
+ * in sweep order: the core block [0, n_core) by descending CH level (Section
+ * 2, levels), then each cell's internal vertices by descending level.
+ * Downward entries are grouped by head position; entry e is the pair
+ * (down_arc[2e], down_arc[2e+1]) = (tail position | flags, length) with flag
+ * bit 31 = original arc tail->head exists, bit 30 = original arc head->tail
+ * exists (a length of ISO_INF marks the dummy entry of Section 5).  Works for
+ * graphs loaded with device = -1 (host only).
+ */
+typedef struct {
+    const uint32_t *perm;          /* n: position -> original id */
+    const uint32_t *cell_of;       /* n: original id -> cell (all 2^32-1 without partition) */
+    const uint32_t *down_off;      /* n + 1 */
+    const uint32_t *down_arc;      /* 2 * down_off[n] */
+    const uint32_t *up_off;        /* n + 1, upward arcs grouped by tail position */
+    const uint32_t *up_head;       /* head positions */
+    const uint32_t *up_w;          /* lengths */
+    const uint32_t *core_lvl;      /* core_lvl_len entries: level i = [core_lvl[i], core_lvl[i+1]) */
+    uint32_t core_lvl_len;
+    const uint32_t *cell_off;      /* num_cells + 1: internal positions of each cell */
+    const uint32_t *cell_lvl_ptr;  /* num_cells + 1 */
+    const uint32_t *cell_lvl;      /* level start positions of every cell, top level first */
+    uint32_t cell_lvl_len;
+    const uint32_t *core_cell;     /* n_core: cell of each core position */
+    const uint32_t *core_ecc;      /* n_core: eccentricity within the cell */
+    const uint8_t *uncovered;      /* num_cells */
+} iso_layout;
+int iso_graph_get_layout(const iso_graph *g, iso_layout *layout);
+
+void iso_free(void *p);
+const char *iso_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISO_H */

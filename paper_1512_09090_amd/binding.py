@@ -1,0 +1,241 @@
+"""ctypes binding of libiso.so (include/iso.h).  Argument marshalling only:
+every step of a query runs inside the native library and its HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiso.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "iso.h")
+
+ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_EFORMAT, ISO_EBUSY, ISO_ESTATE = 0, -1, -2, -3, -4, -6, -7
+MODE_PLAIN, MODE_CELLS = 0, 1
+INF = 0xFFFFFFFF
+TAU_MAX = 0xFFFFFFFE
+
+
+class IsoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64),
+                ("tail", C.POINTER(C.c_uint32)), ("head", C.POINTER(C.c_uint32)),
+                ("weight", C.POINTER(C.c_uint32)), ("xy", C.POINTER(C.c_double)),
+                ("cell_of", C.POINTER(C.c_uint32)), ("num_cells", C.c_uint32),
+                ("max_cell_size", C.c_uint32), ("prep_path", C.c_char_p),
+                ("device", C.c_int), ("threads", C.c_int), ("verbose", C.c_int)]
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("n_core", C.c_uint32), ("num_cells", C.c_uint32),
+                ("core_levels", C.c_uint32), ("max_cell_levels", C.c_uint32),
+                ("max_cell_internal", C.c_uint32), ("m", C.c_uint64), ("down_arcs", C.c_uint64),
+                ("up_arcs", C.c_uint64), ("shortcuts", C.c_uint64), ("device_bytes", C.c_uint64),
+                ("prep_seconds", C.c_double)]
+
+
+class QueryStats(C.Structure):
+    _fields_ = [("lanes", C.c_uint32), ("active_cells", C.c_uint32), ("swept_vertices", C.c_uint64),
+                ("edges", C.c_uint64), ("upward_settled", C.c_uint64), ("t_upward_ms", C.c_double),
+                ("t_device_ms", C.c_double), ("t_sort_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("lanes_per_launch", C.c_uint32), ("block", C.c_uint32), ("lds_top", C.c_uint32),
+                ("use_graph", C.c_uint32)]
+
+
+_U32P = C.POINTER(C.c_uint32)
+
+
+class Layout(C.Structure):
+    _fields_ = [("perm", _U32P), ("cell_of", _U32P), ("down_off", _U32P), ("down_arc", _U32P),
+                ("up_off", _U32P), ("up_head", _U32P), ("up_w", _U32P), ("core_lvl", _U32P),
+                ("core_lvl_len", C.c_uint32), ("cell_off", _U32P), ("cell_lvl_ptr", _U32P),
+                ("cell_lvl", _U32P), ("cell_lvl_len", C.c_uint32), ("core_cell", _U32P),
+                ("core_ecc", _U32P), ("uncovered", C.POINTER(C.c_uint8))]
+
+
+class Edge(C.Structure):
+    _fields_ = [("tail", C.c_uint32), ("head", C.c_uint32)]
+
+
+_lib = None
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of the functions declared in include/iso.h."""
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(iso_\w+)\s*\(", src, flags=re.M)))
+
+
+def lib():
+    """Load libiso.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    L.iso_load_graph.argtypes = [C.POINTER(GraphDesc), C.POINTER(C.c_void_p)]
+    L.iso_free_graph.argtypes = [C.c_void_p]
+    L.iso_free_graph.restype = None
+    L.iso_graph_get_info.argtypes = [C.c_void_p, C.POINTER(GraphInfo)]
+    L.iso_graph_get_layout.argtypes = [C.c_void_p, C.POINTER(Layout)]
+    L.iso_query.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.POINTER(C.POINTER(Edge)),
+                            C.POINTER(C.c_size_t)]
+    L.iso_query_batch.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.POINTER(C.POINTER(Edge)),
+                                  C.POINTER(C.c_size_t)]
+    L.iso_query_distances.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, _U32P, C.POINTER(C.c_uint8)]
+    L.iso_last_query_stats.argtypes = [C.c_void_p, C.POINTER(QueryStats)]
+    L.iso_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.iso_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.iso_free.argtypes = [C.c_void_p]
+    L.iso_free.restype = None
+    L.iso_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != ISO_OK:
+        raise IsoError(rc, lib().iso_last_error().decode(errors="replace"))
+
+
+def _u32(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    return a, a.ctypes.data_as(_U32P)
+
+
+def _edges_to_numpy(ptr, count) -> np.ndarray:
+    if count == 0:
+        out = np.zeros((0, 2), dtype=np.uint32)
+    else:
+        raw = np.ctypeslib.as_array(C.cast(ptr, _U32P), shape=(count * 2,))
+        out = raw.reshape(count, 2).copy()
+    lib().iso_free(C.cast(ptr, C.c_void_p))
+    return out
+
+
+class Graph:
+    """A preprocessed graph resident on one device (or host-only with device=-1)."""
+
+    def __init__(self, n, tail, head, weight, *, xy=None, cell_of=None, num_cells=0, max_cell_size=0,
+                 prep_path=None, device=0, threads=0, verbose=False):
+        L = lib()
+        t, tp = _u32(tail)
+        h, hp = _u32(head)
+        w, wp = _u32(weight)
+        d = GraphDesc()
+        d.n, d.m = int(n), int(t.size)
+        d.tail, d.head, d.weight = tp, hp, wp
+        keep = [t, h, w]
+        if xy is not None:
+            xyc = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+            keep.append(xyc)
+            d.xy = xyc.ctypes.data_as(C.POINTER(C.c_double))
+        if cell_of is not None:
+            co, cp = _u32(cell_of)
+            keep.append(co)
+            d.cell_of = cp
+        d.num_cells = int(num_cells)
+        d.max_cell_size = int(max_cell_size)
+        d.prep_path = prep_path.encode() if prep_path else None
+        d.device, d.threads, d.verbose = int(device), int(threads), int(bool(verbose))
+        h_out = C.c_void_p()
+        _check(L.iso_load_graph(C.byref(d), C.byref(h_out)))
+        self._h = h_out
+        self.n = int(n)
+
+    @classmethod
+    def from_synth(cls, g, num_cells=0, **kw):
+        return cls(g.n, g.tail, g.head, g.w, xy=g.xy if num_cells else None, num_cells=num_cells, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iso_free_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = GraphInfo()
+        _check(lib().iso_graph_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in GraphInfo._fields_}
+
+    def layout(self) -> dict:
+        """Copies of the preprocessed arrays (see iso_layout in include/iso.h)."""
+        Lr = Layout()
+        _check(lib().iso_graph_get_layout(self._h, C.byref(Lr)))
+        info = self.info()
+        n, nc, cells = info["n"], info["n_core"], info["num_cells"]
+
+        def arr(p, k, dt=np.uint32):
+            if k == 0 or not p:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array(p, shape=(k,)).copy()
+
+        down_off = arr(Lr.down_off, n + 1)
+        up_off = arr(Lr.up_off, n + 1)
+        return dict(perm=arr(Lr.perm, n), cell_of=arr(Lr.cell_of, n), down_off=down_off,
+                    down_arc=arr(Lr.down_arc, 2 * int(down_off[-1])).reshape(-1, 2), up_off=up_off,
+                    up_head=arr(Lr.up_head, int(up_off[-1])), up_w=arr(Lr.up_w, int(up_off[-1])),
+                    core_lvl=arr(Lr.core_lvl, Lr.core_lvl_len),
+                    cell_off=arr(Lr.cell_off, cells + 1 if cells else 0),
+                    cell_lvl_ptr=arr(Lr.cell_lvl_ptr, cells + 1 if cells else 0),
+                    cell_lvl=arr(Lr.cell_lvl, Lr.cell_lvl_len), core_cell=arr(Lr.core_cell, nc),
+                    core_ecc=arr(Lr.core_ecc, nc), uncovered=arr(Lr.uncovered, cells, np.uint8),
+                    n=n, n_core=nc, num_cells=cells)
+
+    def query(self, source: int, tau: int, mode: int = MODE_PLAIN) -> np.ndarray:
+        """Isochrone edges as an (count, 2) uint32 array sorted by (tail, head)."""
+        ptr = C.POINTER(Edge)()
+        cnt = C.c_size_t()
+        _check(lib().iso_query(self._h, int(source), int(tau), int(mode), C.byref(ptr), C.byref(cnt)))
+        return _edges_to_numpy(ptr, cnt.value)
+
+    def query_batch(self, sources, taus, mode: int = MODE_PLAIN) -> list[np.ndarray]:
+        s, sp = _u32(sources)
+        t, tp = _u32(taus)
+        k = s.size
+        offsets = (C.c_size_t * (k + 1))()
+        ptr = C.POINTER(Edge)()
+        _check(lib().iso_query_batch(self._h, k, sp, tp, int(mode), C.byref(ptr), offsets))
+        total = offsets[k]
+        flat = _edges_to_numpy(ptr, total)
+        return [flat[offsets[j]:offsets[j + 1]] for j in range(k)]
+
+    def distances(self, source: int, tau: int, mode: int = MODE_PLAIN):
+        """(dist uint32[n] with 2^32-1 where not labelled, swept bool[n])."""
+        dist = np.empty(self.n, dtype=np.uint32)
+        swept = np.empty(self.n, dtype=np.uint8)
+        _check(lib().iso_query_distances(self._h, int(source), int(tau), int(mode),
+                                         dist.ctypes.data_as(_U32P), swept.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return dist, swept.astype(bool)
+
+    def last_stats(self) -> dict:
+        s = QueryStats()
+        _check(lib().iso_last_query_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in QueryStats._fields_}
+
+    def set_tuning(self, lanes_per_launch=64, block=256, lds_top=0, use_graph=0):
+        t = Tuning(lanes_per_launch, block, lds_top, use_graph)
+        _check(lib().iso_set_tuning(self._h, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().iso_get_tuning(self._h, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}

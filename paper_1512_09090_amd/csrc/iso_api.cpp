@@ -1,0 +1,451 @@
+// iso_api.cpp - the C ABI (include/iso.h): loading, the host upward search,
+// batching of queries into device sweeps, decoding of the sorted edge keys.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/iso.h"
+#include "device.h"
+#include "prep.h"
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+namespace {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Upward CH search (Section 2: forward search on G-up; no stopping criterion, as in
+// the first phase of PHAST and of isoPHAST-CP).  Labels are exact upper bounds
+// along upward paths; the downward sweep makes them exact (Section 2, PHAST).
+struct UpwardSearch {
+    std::vector<uint32_t> dist, stamp;
+    uint32_t epoch = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> heap;
+    std::vector<uint32_t> touched;
+
+    void init(uint32_t n) { dist.assign(n, iso::INF); stamp.assign(n, 0); epoch = 0; }
+
+    // out: (position, label) pairs sorted by position; returns settled count
+    uint32_t run(const iso::Prep &P, uint32_t src_pos, std::vector<std::pair<uint32_t, uint32_t>> &out) {
+        if (++epoch == 0) { std::fill(stamp.begin(), stamp.end(), 0u); epoch = 1; }
+        heap.clear();
+        touched.clear();
+        auto get = [&](uint32_t v) { return stamp[v] == epoch ? dist[v] : iso::INF; };
+        auto cmp = [](const std::pair<uint32_t, uint32_t> &a, const std::pair<uint32_t, uint32_t> &b) {
+            return a.first > b.first;
+        };
+        stamp[src_pos] = epoch;
+        dist[src_pos] = 0;
+        touched.push_back(src_pos);
+        heap.push_back({0, src_pos});
+        uint32_t settled = 0;
+        while (!heap.empty()) {
+            std::pop_heap(heap.begin(), heap.end(), cmp);
+            auto [k, u] = heap.back();
+            heap.pop_back();
+            if (k != get(u)) continue;
+            ++settled;
+            for (uint32_t e = P.up_off[u]; e < P.up_off[u + 1]; ++e) {
+                uint32_t x = P.up_head[e];
+                uint32_t nd = iso::sat_add(k, P.up_w[e]);
+                if (nd < get(x)) {
+                    if (stamp[x] != epoch) touched.push_back(x);
+                    stamp[x] = epoch;
+                    dist[x] = nd;
+                    heap.push_back({nd, x});
+                    std::push_heap(heap.begin(), heap.end(), cmp);
+                }
+            }
+        }
+        out.clear();
+        for (uint32_t v : touched) if (dist[v] != iso::INF) out.push_back({v, dist[v]});
+        std::sort(out.begin(), out.end());
+        return settled;
+    }
+};
+
+}  // namespace
+
+struct iso_graph {
+    iso::Prep P;
+    isodev::DevGraph D;
+    bool on_device = false;
+    int threads = 1;
+    std::atomic<bool> busy{false};
+    iso_query_stats last{};
+    iso_tuning tuning{64, 256, 0, 0};
+    std::vector<UpwardSearch> up;   // one workspace per host thread
+    size_t out_cap = 1 << 20;
+};
+
+namespace {
+
+struct BusyGuard {
+    iso_graph *g;
+    bool ok;
+    explicit BusyGuard(iso_graph *g_) : g(g_) {
+        bool f = false;
+        ok = g->busy.compare_exchange_strong(f, true);
+    }
+    ~BusyGuard() { if (ok) g->busy.store(false); }
+};
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+uint32_t pow2_at_least(uint32_t x) {
+    uint32_t k = 1;
+    while (k < x) k <<= 1;
+    return k;
+}
+
+// Run `lanes` queries (<= 64) through one device sweep.  keys_out receives the
+// sorted keys; dist_out (optional) the label rows.
+int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
+              bool want_dist, isodev::RunResult &R) {
+    const iso::Prep &P = g->P;
+    isodev::RunArgs A;
+    A.lanes = lanes;
+    A.k_pow2 = pow2_at_least(lanes);
+    A.mode_plain = plain;
+    A.want_dist = want_dist;
+    const uint32_t K = A.k_pow2;
+    A.taus.assign(K, iso::INF);
+    A.src_cell.assign(K, iso::NO_CELL);
+    // upward searches, one host thread per lane (bounded by g->threads)
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> U(lanes);
+    std::vector<uint32_t> settled(lanes, 0);
+    double t0 = now_ms();
+    {
+        int T = std::min<int>(g->threads, int(lanes));
+        std::atomic<uint32_t> next{0};
+        auto work = [&](int tid) {
+            for (;;) {
+                uint32_t j = next.fetch_add(1);
+                if (j >= lanes) break;
+                settled[j] = g->up[tid].run(P, P.pos[src[j]], U[j]);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int t = 1; t < T; ++t) pool.emplace_back(work, t);
+        work(0);
+        for (auto &th : pool) th.join();
+    }
+    for (uint32_t j = 0; j < lanes; ++j) {
+        A.taus[j] = tau[j];
+        A.src_cell[j] = P.num_cells ? P.cell_of[src[j]] : iso::NO_CELL;
+    }
+    // union of touched positions and the label table
+    std::vector<uint32_t> &pos = A.upos;
+    for (auto &u : U) for (auto &pr : u) pos.push_back(pr.first);
+    std::sort(pos.begin(), pos.end());
+    pos.erase(std::unique(pos.begin(), pos.end()), pos.end());
+    A.uval.assign(pos.size() * K, iso::INF);
+    for (uint32_t j = 0; j < lanes; ++j)
+        for (auto &pr : U[j]) {
+            size_t i = std::lower_bound(pos.begin(), pos.end(), pr.first) - pos.begin();
+            A.uval[i * K + j] = pr.second;
+        }
+    double t1 = now_ms();
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        A.out_cap = g->out_cap;
+        int r = g->D.run(A, R);
+        if (r) return r;
+        if (!R.overflow) break;
+        g->out_cap = std::max<size_t>(g->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
+    }
+    if (R.overflow) return fail(ISO_ENOMEM, "edge buffer overflow");
+    double t2 = now_ms();
+    g->last.lanes += lanes;
+    g->last.active_cells += R.active_cells;
+    for (uint32_t j = 0; j < lanes; ++j) g->last.upward_settled += settled[j];
+    g->last.t_upward_ms += t1 - t0;
+    g->last.t_device_ms += t2 - t1;
+    return ISO_OK;
+}
+
+int check_query(iso_graph *g, uint32_t s, uint32_t tau, int mode) {
+    if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
+    if (s >= g->P.n) return fail(ISO_EINVAL, "source out of range");
+    if (tau > ISO_TAU_MAX) return fail(ISO_EINVAL, "tau must be <= 2^32 - 2");
+    if (mode != ISO_MODE_PLAIN && mode != ISO_MODE_CELLS) return fail(ISO_EINVAL, "unknown mode");
+    if (mode == ISO_MODE_CELLS && g->P.num_cells == 0) return fail(ISO_EINVAL, "cells mode needs a partition");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    return ISO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *iso_last_error(void) { return g_err.c_str(); }
+
+void iso_free(void *p) { std::free(p); }
+
+int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
+    if (!d || !out) return fail(ISO_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (d->n == 0 || d->n >= (1u << 29)) return fail(ISO_EINVAL, "n must be in [1, 2^29)");
+    if (d->m && (!d->tail || !d->head || !d->weight)) return fail(ISO_EINVAL, "arc arrays are NULL");
+    uint32_t maxc = d->max_cell_size ? d->max_cell_size : 2048;
+    if (maxc > 4096) return fail(ISO_EINVAL, "max_cell_size must be <= 4096");
+    for (uint64_t e = 0; e < d->m; ++e) {
+        if (d->tail[e] >= d->n || d->head[e] >= d->n) return fail(ISO_EINVAL, "arc endpoint out of range");
+        if (d->weight[e] == ISO_INF) return fail(ISO_EINVAL, "arc weight 2^32-1 is reserved");
+    }
+    if (d->cell_of) {
+        if (d->num_cells == 0) return fail(ISO_EINVAL, "cell_of given with num_cells = 0");
+        for (uint32_t v = 0; v < d->n; ++v)
+            if (d->cell_of[v] >= d->num_cells) return fail(ISO_EINVAL, "cell id out of range");
+    }
+    iso_graph *g = new (std::nothrow) iso_graph();
+    if (!g) return fail(ISO_ENOMEM, "out of host memory");
+    try {
+        g->threads = iso::resolve_threads(d->threads);
+        iso::ArcList A;
+        iso::simplify_arcs(d->n, d->m, d->tail, d->head, d->weight, A);
+        std::vector<uint32_t> cell_of;
+        uint32_t num_cells = 0;
+        if (d->cell_of) {
+            cell_of.assign(d->cell_of, d->cell_of + d->n);
+            num_cells = d->num_cells;
+        } else if (d->num_cells > 0) {
+            if (d->xy) {
+                iso::partition_bisect(d->n, d->xy, d->num_cells, cell_of);
+                num_cells = d->num_cells;
+            } else {
+                iso::partition_bfs(A, maxc, cell_of, num_cells);
+            }
+        }
+        if (num_cells) {
+            std::vector<uint32_t> sz(num_cells, 0);
+            for (uint32_t c : cell_of) sz[c]++;
+            for (uint32_t c = 0; c < num_cells; ++c)
+                if (sz[c] > maxc) {
+                    delete g;
+                    return fail(ISO_EINVAL, "a cell exceeds max_cell_size (use more cells)");
+                }
+        }
+        uint64_t h = iso::hash_input(A, cell_of, num_cells);
+        bool loaded = false;
+        if (d->prep_path && *d->prep_path) {
+            iso::LoadStatus st = iso::load_prep(d->prep_path, g->P, h);
+            if (st == iso::LOAD_CORRUPT) {
+                delete g;
+                return fail(ISO_EFORMAT, std::string("corrupt or truncated preprocessed file ") + d->prep_path);
+            }
+            loaded = st == iso::LOAD_OK;
+            if (!loaded) g->P = iso::Prep();
+        }
+        if (!loaded) {
+            iso::PrepOptions o;
+            o.num_cells = num_cells;
+            o.max_cell_size = maxc;
+            o.threads = g->threads;
+            o.verbose = d->verbose;
+            iso::build_prep(A, cell_of, num_cells, o, g->P);
+            if (d->prep_path && *d->prep_path && !iso::save_prep(d->prep_path, g->P, h)) {
+                delete g;
+                return fail(ISO_EFORMAT, std::string("cannot write ") + d->prep_path);
+            }
+        } else {
+            g->P.seconds = 0.0;
+        }
+        if (uint64_t(g->P.n_core) * isodev::MAX_LANES >= (uint64_t(1) << 32)) {
+            delete g;
+            return fail(ISO_EINVAL, "core too large for 64 interleaved lanes");
+        }
+        g->up.resize(g->threads);
+        for (auto &u : g->up) u.init(g->P.n);
+        g->out_cap = std::max<size_t>(1 << 16, std::min<size_t>(g->P.m / 4 + 1024, size_t(1) << 24));
+        if (d->device >= 0) {
+            int r = g->D.upload(g->P, d->device);
+            if (r) {
+                g->D.release();
+                delete g;
+                return r;
+            }
+            g->on_device = true;
+        }
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return fail(ISO_ENOMEM, "out of host memory during preprocessing");
+    }
+    *out = g;
+    return ISO_OK;
+}
+
+void iso_free_graph(iso_graph *g) {
+    if (!g) return;
+    g->D.release();
+    delete g;
+}
+
+int iso_graph_get_info(const iso_graph *g, iso_graph_info *info) {
+    if (!g || !info) return fail(ISO_EINVAL, "NULL argument");
+    const iso::Prep &P = g->P;
+    info->n = P.n;
+    info->n_core = P.n_core;
+    info->num_cells = P.num_cells;
+    info->core_levels = P.core_lvl.empty() ? 0 : uint32_t(P.core_lvl.size() - 1);
+    info->max_cell_levels = P.max_cell_levels;
+    info->max_cell_internal = P.max_cell_internal;
+    info->m = P.m;
+    info->down_arcs = P.down_off.empty() ? 0 : P.down_off[P.n];
+    info->up_arcs = P.up_off.empty() ? 0 : P.up_off[P.n];
+    info->shortcuts = P.shortcuts;
+    info->device_bytes = g->D.bytes;
+    info->prep_seconds = P.seconds;
+    return ISO_OK;
+}
+
+static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_t *tau, int mode,
+                      iso_edge **edges, size_t *offsets) {
+    double t0 = now_ms();
+    g->last = iso_query_stats{};
+    std::vector<iso_edge> all;
+    const uint32_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
+    offsets[0] = 0;
+    for (size_t b = 0; b < k; b += per) {
+        uint32_t lanes = uint32_t(std::min<size_t>(per, k - b));
+        isodev::RunResult R;
+        int r = run_lanes(g, src + b, tau + b, lanes, mode == ISO_MODE_PLAIN, false, R);
+        if (r) return r;
+        double ts = now_ms();
+        size_t base = all.size();
+        all.resize(base + R.keys.size());
+        std::vector<size_t> cnt(lanes + 1, 0);
+        for (size_t i = 0; i < R.keys.size(); ++i) {
+            uint64_t key = R.keys[i];
+            all[base + i] = iso_edge{uint32_t((key >> 29) & ((1u << 29) - 1)), uint32_t(key & ((1u << 29) - 1))};
+            cnt[(key >> 58) + 1]++;
+        }
+        for (uint32_t j = 0; j < lanes; ++j) offsets[b + j + 1] = offsets[b + j] + cnt[j + 1];
+        g->last.t_sort_ms += now_ms() - ts;
+    }
+    g->last.edges = all.size();
+    iso_edge *buf = (iso_edge *)std::malloc(std::max<size_t>(1, all.size()) * sizeof(iso_edge));
+    if (!buf) return fail(ISO_ENOMEM, "out of host memory for the result");
+    if (!all.empty()) std::memcpy(buf, all.data(), all.size() * sizeof(iso_edge));
+    *edges = buf;
+    g->last.t_total_ms = now_ms() - t0;
+    return ISO_OK;
+}
+
+int iso_query(iso_graph *g, uint32_t source, uint32_t tau, int mode, iso_edge **edges, size_t *count) {
+    if (edges) *edges = nullptr;
+    if (!edges || !count) return fail(ISO_EINVAL, "NULL output pointer");
+    int r = check_query(g, source, tau, mode);
+    if (r) return r;
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    size_t off[2];
+    r = query_many(g, 1, &source, &tau, mode, edges, off);
+    if (r) return r;
+    *count = off[1];
+    return ISO_OK;
+}
+
+int iso_query_batch(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus, int mode,
+                    iso_edge **edges, size_t *offsets) {
+    if (edges) *edges = nullptr;
+    if (!edges || !offsets || (k && (!sources || !taus))) return fail(ISO_EINVAL, "NULL argument");
+    if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
+    for (size_t j = 0; j < k; ++j) {
+        int r = check_query(g, sources[j], taus[j], mode);
+        if (r) return r;
+    }
+    if (k == 0) {
+        offsets[0] = 0;
+        *edges = (iso_edge *)std::malloc(sizeof(iso_edge));
+        return *edges ? ISO_OK : fail(ISO_ENOMEM, "out of host memory");
+    }
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    return query_many(g, k, sources, taus, mode, edges, offsets);
+}
+
+int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode, uint32_t *dist,
+                        uint8_t *swept) {
+    if (!dist) return fail(ISO_EINVAL, "NULL output pointer");
+    int r = check_query(g, source, tau, mode);
+    if (r) return r;
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    g->last = iso_query_stats{};
+    isodev::RunResult R;
+    r = run_lanes(g, &source, &tau, 1, mode == ISO_MODE_PLAIN, true, R);
+    if (r) return r;
+    const iso::Prep &P = g->P;
+    std::vector<uint8_t> sw(P.n, 0);
+    for (uint32_t p = 0; p < P.n_core; ++p) sw[p] = 1;
+    if (P.num_cells) {
+        auto mark = [&](uint32_t c) { for (uint32_t p = P.cell_off[c]; p < P.cell_off[c + 1]; ++p) sw[p] = 1; };
+        if (mode == ISO_MODE_PLAIN) for (uint32_t c = 0; c < P.num_cells; ++c) mark(c);
+        else for (uint32_t c : R.active_list) mark(c);
+    }
+    for (uint32_t p = 0; p < P.n; ++p) {
+        uint32_t v = P.perm[p];
+        uint32_t val = !sw[p] ? iso::INF : (p < P.n_core ? R.dcore[p] : R.dist[p]);
+        dist[v] = val;
+        if (swept) swept[v] = sw[p];
+    }
+    return ISO_OK;
+}
+
+int iso_graph_get_layout(const iso_graph *g, iso_layout *L) {
+    if (!g || !L) return fail(ISO_EINVAL, "NULL argument");
+    const iso::Prep &P = g->P;
+    L->perm = P.perm.data();
+    L->cell_of = P.cell_of.data();
+    L->down_off = P.down_off.data();
+    L->down_arc = P.down_arc.data();
+    L->up_off = P.up_off.data();
+    L->up_head = P.up_head.data();
+    L->up_w = P.up_w.data();
+    L->core_lvl = P.core_lvl.data();
+    L->core_lvl_len = uint32_t(P.core_lvl.size());
+    L->cell_off = P.cell_off.data();
+    L->cell_lvl_ptr = P.cell_lvl_ptr.data();
+    L->cell_lvl = P.cell_lvl.data();
+    L->cell_lvl_len = uint32_t(P.cell_lvl.size());
+    L->core_cell = P.core_cell.data();
+    L->core_ecc = P.core_ecc.data();
+    L->uncovered = P.uncovered.data();
+    return ISO_OK;
+}
+
+int iso_last_query_stats(const iso_graph *g, iso_query_stats *s) {
+    if (!g || !s) return fail(ISO_EINVAL, "NULL argument");
+    *s = g->last;
+    return ISO_OK;
+}
+
+int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
+    if (!g || !t) return fail(ISO_EINVAL, "NULL argument");
+    if (t->lanes_per_launch < 1 || t->lanes_per_launch > isodev::MAX_LANES) return fail(ISO_EINVAL, "lanes_per_launch out of range");
+    if (t->block < 64 || t->block > 1024 || t->block % 64) return fail(ISO_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    g->tuning = *t;
+    return ISO_OK;
+}
+
+int iso_get_tuning(const iso_graph *g, iso_tuning *t) {
+    if (!g || !t) return fail(ISO_EINVAL, "NULL argument");
+    *t = g->tuning;
+    return ISO_OK;
+}
+
+}  // extern "C"

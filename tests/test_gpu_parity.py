@@ -1,0 +1,181 @@
+"""HIP path against the CPU oracle, element by element (needs an MI355X).
+
+Every case compares, on the same seeded inputs, the isochrone-edge set (sorted
+(tail, head) pairs, bit-exact) and the uint32 distance labels of the swept
+vertices with the oracle's tau-bounded / unbounded Dijkstra.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1512_09090_amd as iso
+import synth
+from oracle import INF as OINF
+from oracle import Oracle, clamp_u32
+from tests import golden_io
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def check_query(G, orc, s, tau, modes=(iso.MODE_PLAIN, iso.MODE_CELLS), dist=True):
+    want, wdist, _ = orc.isochrone(s, tau, want_dist=True)
+    full = clamp_u32(orc.distances(s)) if dist else None
+    for mode in modes:
+        say(f"  query s={s} tau={tau} mode={mode}")
+        got = G.query(s, tau, mode)
+        np.testing.assert_array_equal(got, want, err_msg=f"edges s={s} tau={tau} mode={mode}")
+        if dist:
+            d, swept = G.distances(s, tau, mode)
+            if mode == iso.MODE_PLAIN:
+                assert swept.all()
+                np.testing.assert_array_equal(d, full)
+            else:
+                np.testing.assert_array_equal(d[swept], full[swept])
+                # both endpoints of every isochrone edge lie in swept cells or in the core
+                assert swept[want[:, 0]].all() and swept[want[:, 1]].all()
+
+
+@pytest.fixture(scope="module")
+def grid():
+    g = synth.config_graph("grid64")
+    return g, Oracle.from_graph(g)
+
+
+def test_grid64_cells(grid):
+    g, orc = grid
+    say("grid64 / 16 cells")
+    G = iso.Graph.from_synth(g, num_cells=16, device=0)
+    src, _ = synth.config_queries("grid64", 6)
+    for s in src.tolist():
+        for tau in (0, 150, 2000, 7000, 40000, iso.TAU_MAX):
+            check_query(G, orc, s, tau)
+
+
+def test_grid64_plain_hierarchy(grid):
+    g, orc = grid
+    say("grid64 / no partition")
+    G = iso.Graph.from_synth(g, num_cells=0, device=0)
+    for s in (0, 2080, 4095):
+        for tau in (0, 2000, 9000):
+            check_query(G, orc, s, tau, modes=(iso.MODE_PLAIN,))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_digraph_random_cells(seed):
+    g = synth.random_digraph(300, 900, seed=700 + seed, wmax=40, zero_frac=0.1)
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 9))
+    cells = rng.integers(0, k, size=g.n).astype(np.uint32)
+    say(f"random digraph seed={seed} cells={k}")
+    G = iso.Graph(g.n, g.tail, g.head, g.w, cell_of=cells, num_cells=k, device=0)
+    orc = Oracle.from_graph(g)
+    for s in rng.integers(0, g.n, size=3).tolist():
+        d = orc.distances(s)
+        fin = d[d != OINF]
+        for tau in {0, int(fin.max()), int(np.median(fin)), int(fin.max()) + 1}:
+            check_query(G, orc, s, tau)
+
+
+@pytest.mark.parametrize("name", ["fig2_right.txt", "fig2_left_mountain.txt"])
+def test_golden_instances(name):
+    f = golden_io.load(name)
+    say(f"golden {name}")
+    G = iso.Graph(f["n"], f["tail"], f["head"], f["w"], cell_of=f["cells"],
+                  num_cells=int(f["cells"].max()) + 1, device=0)
+    for mode in (iso.MODE_PLAIN, iso.MODE_CELLS):
+        np.testing.assert_array_equal(G.query(f["source"], f["tau"], mode), f["expect"])
+    d, _ = G.distances(f["source"], f["tau"], iso.MODE_PLAIN)
+    np.testing.assert_array_equal(d, f["dist"].astype(np.uint32))
+
+
+@pytest.fixture(scope="module")
+def road50k():
+    g = synth.road_graph(50_000, 31)
+    say("road50k / 256 cells")
+    return g, Oracle.from_graph(g), iso.Graph.from_synth(g, num_cells=256, device=0)
+
+
+def test_road50k(road50k):
+    g, orc, G = road50k
+    rng = np.random.default_rng(4)
+    for s in rng.integers(0, g.n, size=4).tolist():
+        for tau in (0, 60_000, 600_000, 3_600_000, 40_000_000):
+            check_query(G, orc, s, tau)
+
+
+def test_road_oneway_uncovered_cells():
+    g = synth.road_graph(30_000, 32, oneway_frac=0.3)
+    say("road30k one-way / 128 cells")
+    G = iso.Graph.from_synth(g, num_cells=128, device=0)
+    assert G.layout()["uncovered"].sum() > 0
+    orc = Oracle.from_graph(g)
+    rng = np.random.default_rng(5)
+    for s in rng.integers(0, g.n, size=4).tolist():
+        for tau in (300_000, 1_800_000, 12_000_000):
+            check_query(G, orc, s, tau)
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 64, 70])
+def test_batch_equals_singles(road50k, k):
+    g, orc, G = road50k
+    src, tau = synth.batch_queries(g.n, k, seed=100 + k, lo_min=1, hi_min=90)
+    for mode in (iso.MODE_PLAIN, iso.MODE_CELLS):
+        say(f"batch k={k} mode={mode}")
+        out = G.query_batch(src, tau, mode)
+        assert len(out) == k
+        for j in range(k):
+            single = G.query(int(src[j]), int(tau[j]), mode)
+            np.testing.assert_array_equal(out[j], single, err_msg=f"lane {j}")
+        for j in range(0, k, max(1, k // 4)):
+            want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
+            np.testing.assert_array_equal(out[j], want)
+
+
+def test_batch_lanes_per_launch(road50k):
+    g, orc, G = road50k
+    src, tau = synth.batch_queries(g.n, 40, seed=9, lo_min=1, hi_min=90)
+    ref = G.query_batch(src, tau, iso.MODE_CELLS)
+    for lanes in (1, 5, 16, 32):
+        say(f"lanes_per_launch={lanes}")
+        G.set_tuning(lanes_per_launch=lanes)
+        out = G.query_batch(src, tau, iso.MODE_CELLS)
+        for j in range(len(src)):
+            np.testing.assert_array_equal(out[j], ref[j])
+    G.set_tuning(lanes_per_launch=64)
+
+
+def test_degenerate_graphs():
+    say("degenerate graphs")
+    one = iso.Graph(1, np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint32), device=0)
+    assert one.query(0, 5).shape == (0, 2)
+    d, _ = one.distances(0, 5)
+    assert d.tolist() == [0]
+    # isolated source inside a graph with a partition
+    g = synth.road_graph(5_000, 33)
+    t = np.concatenate([g.tail, np.array([5000], np.uint32)])
+    h = np.concatenate([g.head, np.array([0], np.uint32)])
+    w = np.concatenate([g.w, np.array([7], np.uint32)])
+    xy = np.vstack([g.xy, [[0.0, 0.0]]])
+    G = iso.Graph(5001, t, h, w, xy=xy, num_cells=32, device=0)
+    orc = Oracle(5001, t, h, w)
+    check_query(G, orc, 5000, 100)       # source with an out-arc only
+    check_query(G, orc, 0, 10_000_000)   # the extra vertex is unreachable
+    with pytest.raises(iso.IsoError) as e:
+        G.query(5001, 10)
+    assert e.value.code == iso.ISO_EINVAL
+
+
+@pytest.mark.slow
+def test_road1m_config():
+    g = synth.config_graph("road1m")
+    say("road1m / 4096 cells")
+    G = iso.Graph.from_synth(g, num_cells=synth.CONFIGS["road1m"]["cells"], device=0)
+    orc = Oracle.from_graph(g)
+    src, taus = synth.config_queries("road1m", 3)
+    for s, tau in zip(src.tolist(), taus.tolist()):
+        check_query(G, orc, s, tau)
