@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of batched isochrone queries on the 18M-vertex synthetic road graph.
+
+One step = one batch of `--lanes` queries (source, tau) answered by
+iso_query_batch in the cell-restricted mode: host upward searches, core sweep
+with cell flags, active-cell selection, per-cell sweeps with isochrone-edge
+extraction, radix sort of the edges, copy back.  Inputs are resident on the
+device before the timed region.  Also reported: single-query latency p50/p99
+(both sweep modes), the plain-sweep batched throughput, the live roofline of
+the dominant kernel phase (HIP events on the library's stream, algorithmic
+bytes from the graph structure), and the CPU oracle timed on this host.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload road18m]
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "isochrone queries/s + p50/p99 ms on 18M-vertex graph; sweep HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def load_workload(name, cache_dir):
+    import paper_1512_09090_amd as iso
+    import synth
+
+    cfg = synth.CONFIGS[name]
+    t0 = time.time()
+    g = synth.config_graph(name)
+    log(f"graph {name}: n={g.n} m={g.m} ({time.time() - t0:.1f}s)")
+    os.makedirs(cache_dir, exist_ok=True)
+    prep = os.path.join(cache_dir, f"{name}-c{cfg['cells']}-v1.prep")
+    t0 = time.time()
+    G = iso.Graph.from_synth(g, num_cells=cfg["cells"], device=0, prep_path=prep, verbose=True)
+    log(f"loaded on device ({time.time() - t0:.1f}s): {G.info()}")
+    return g, G
+
+
+def run_batches(G, src, tau, lanes, steps, mode, start=0):
+    n = len(src)
+    times = []
+    for i in range(steps):
+        b = (start + i * lanes) % n
+        idx = (np.arange(lanes) + b) % n
+        t0 = time.perf_counter()
+        G.query_batch(src[idx], tau[idx], mode)
+        times.append(time.perf_counter() - t0)
+    return times
+
+
+def cpu_baseline(g, src, tau, seconds, threads):
+    """The oracle (tau-bounded Dijkstra + edge rule) on this host, one query per thread."""
+    import oracle
+
+    t0 = time.time()
+    orc = oracle.Oracle.from_graph(g)
+    workers = [oracle.OracleWorker(orc) for _ in range(threads)]
+    log(f"cpu baseline: oracle graph built ({time.time() - t0:.1f}s), {threads} threads, ~{seconds}s budget")
+    nxt = [0]
+    done = []
+    lock = threading.Lock()
+    deadline = time.perf_counter() + seconds
+
+    def work(wk):
+        while True:
+            with lock:
+                if time.perf_counter() > deadline or nxt[0] >= len(src):
+                    return
+                j = nxt[0]
+                nxt[0] += 1
+            wk.isochrone(int(src[j]), int(tau[j]))
+            with lock:
+                done.append(j)
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=work, args=(w,)) for w in workers]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    return {"value": len(done) / el, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(done)} queries of the benchmark list (tau uniform 10-240 min), "
+                      f"one query per thread, {el:.1f}s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="road18m")
+    ap.add_argument("--lanes", type=int, default=64)
+    ap.add_argument("--latency-queries", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cache-dir", default=os.environ.get("ISO_CACHE", "/tmp/iso_cache"))
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "queries are independent, so more GPUs would each hold a replica of the graph - not measured here",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import paper_1512_09090_amd as iso
+    import synth
+
+    g, G = load_workload(args.workload, args.cache_dir)
+    info = G.info()
+    src, tau = synth.config_queries(args.workload, 1000)
+    lanes = args.lanes
+    G.set_tuning(lanes_per_launch=lanes)
+
+    # warmup (also grows the library's device buffers to their steady size)
+    log(f"warmup {args.warmup} steps of {lanes} queries")
+    run_batches(G, src, tau, lanes, max(1, args.warmup), iso.MODE_CELLS)
+    # timed region: cells mode, batches of `lanes`
+    G.profile_enable(True)
+    log(f"timed {args.steps} steps")
+    t0 = time.perf_counter()
+    times = run_batches(G, src, tau, lanes, args.steps, iso.MODE_CELLS, start=args.warmup * lanes)
+    total = time.perf_counter() - t0
+    prof = G.profile_read()
+    G.profile_enable(False)
+    qps = args.steps * lanes / total
+    log(f"cells batched: {qps:.1f} queries/s, {1000 * total / args.steps:.2f} ms/step; profile {prof}")
+
+    # plain sweep, same batches
+    run_batches(G, src, tau, lanes, 1, iso.MODE_PLAIN)
+    G.profile_enable(True)
+    t0 = time.perf_counter()
+    run_batches(G, src, tau, lanes, max(2, args.steps // 4), iso.MODE_PLAIN, start=args.warmup * lanes)
+    total_p = time.perf_counter() - t0
+    prof_plain = G.profile_read()
+    G.profile_enable(False)
+    qps_plain = max(2, args.steps // 4) * lanes / total_p
+    log(f"plain batched: {qps_plain:.1f} queries/s; profile {prof_plain}")
+
+    # single-query latency (one query per call)
+    lat = {}
+    single_qps = {}
+    for name, mode in (("cells", iso.MODE_CELLS), ("plain", iso.MODE_PLAIN)):
+        G.query(int(src[0]), int(tau[0]), mode)
+        ts = []
+        t0 = time.perf_counter()
+        for j in range(args.latency_queries):
+            a = time.perf_counter()
+            G.query(int(src[j]), int(tau[j]), mode)
+            ts.append(1000.0 * (time.perf_counter() - a))
+        single_qps[name] = args.latency_queries / (time.perf_counter() - t0)
+        lat[name] = {"p50": percentile(ts, 50), "p99": percentile(ts, 99), "mean": float(np.mean(ts))}
+        log(f"single {name}: {lat[name]}")
+
+    # roofline of the dominant device phase in the timed region
+    phases = {"core_sweep": (prof["core_ms"], prof["core_bytes"], prof["core_launches"]),
+              "cell_sweep": (prof["cell_ms"], prof["cell_bytes"], prof["cell_launches"])}
+    dom = max(phases, key=lambda k: phases[k][0])
+    ms, byts, launches = phases[dom]
+    achieved = (byts / 1e9) / (ms / 1e3) if ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_ms": round(ms / max(1, launches), 4),
+                "algorithmic_bytes_per_launch": int(byts / max(1, launches)),
+                "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()}}
+
+    cpu = None
+    if not args.no_cpu:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        cpu = cpu_baseline(g, src, tau, args.cpu_seconds, threads)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * total / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {info['n']}-vertex road-like kNN graph, {info['m']} arcs, "
+                               f"{info['num_cells']} cells; batches of {lanes} queries, cell-restricted sweep, "
+                               "tau uniform 10-240 min",
+                   "n": info["n"], "m": info["m"], "cells": info["num_cells"], "core": info["n_core"],
+                   "core_levels": info["core_levels"], "down_arcs": info["down_arcs"], "lanes": lanes,
+                   "mode": "cells"},
+        "latency_ms": lat,
+        "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
+        "batched_plain_qps": round(qps_plain, 2),
+        "step_ms_p50": round(1000 * percentile(times, 50), 3),
+        "step_ms_p99": round(1000 * percentile(times, 99), 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

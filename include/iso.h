@@ -195,6 +195,26 @@ typedef struct {
 } iso_layout;
 int iso_graph_get_layout(const iso_graph *g, iso_layout *layout);
 
+/*
+ * Device-side phase profile (for roofline reporting).  While enabled, each
+ * query call records HIP events on the library's stream around its device
+ * phases and accumulates their durations, launch counts and algorithmic HBM
+ * bytes: the downward-graph entries and offsets the phase reads, the
+ * per-lane label writes and reads it must make (core labels written once and
+ * read once; cell-internal labels never leave LDS; each cell reads its
+ * distinct core tails once), and the per-vertex cell ids and eccentricities
+ * of the flag rule.  Enabling resets the accumulators.
+ */
+typedef struct {
+    double core_ms, active_ms, cell_ms, sort_ms;        /* summed event durations */
+    uint64_t core_launches, cell_launches, calls;       /* kernel launches; query sweeps */
+    uint64_t core_bytes, cell_bytes;                    /* summed algorithmic bytes */
+    uint64_t core_entries, cell_entries;                /* downward entries swept */
+    uint64_t cell_vertices, cells_swept;                /* internal vertices and cells swept */
+} iso_profile;
+int iso_profile_enable(iso_graph *g, int enable);
+int iso_profile_read(const iso_graph *g, iso_profile *out);
+
 void iso_free(void *p);
 const char *iso_last_error(void);
 

@@ -142,6 +142,29 @@ class Oracle:
         return _take_edges(self._L, ptr, cnt), int(settled)
 
 
+class OracleWorker:
+    """A second workspace over an existing Oracle's graph (one per host thread)."""
+
+    def __init__(self, parent: "Oracle"):
+        self._parent = parent
+        self._L = parent._L
+        self._g = parent._g
+        self._ws = self._L.orc_ws_new(parent.n)
+        if not self._ws:
+            raise MemoryError("oracle workspace allocation failed")
+
+    def isochrone(self, s: int, tau: int):
+        ptr, cnt = _U64P(), C.c_uint64()
+        settled = self._L.orc_isochrone(self._g, self._ws, int(s), int(tau), None, C.byref(ptr), C.byref(cnt))
+        return _take_edges(self._L, ptr, cnt), int(settled)
+
+    def __del__(self):
+        try:
+            self._L.orc_ws_free(self._ws)
+        except Exception:
+            pass
+
+
 def clamp_u32(dist: np.ndarray) -> np.ndarray:
     """Distances as the 32-bit interface reports them: min(d, 2^32 - 1)."""
     return np.minimum(dist, np.uint64(0xFFFFFFFF)).astype(np.uint32)

@@ -64,6 +64,14 @@ class Layout(C.Structure):
                 ("core_ecc", _U32P), ("uncovered", C.POINTER(C.c_uint8))]
 
 
+class Profile(C.Structure):
+    _fields_ = [("core_ms", C.c_double), ("active_ms", C.c_double), ("cell_ms", C.c_double),
+                ("sort_ms", C.c_double), ("core_launches", C.c_uint64), ("cell_launches", C.c_uint64),
+                ("calls", C.c_uint64), ("core_bytes", C.c_uint64), ("cell_bytes", C.c_uint64),
+                ("core_entries", C.c_uint64), ("cell_entries", C.c_uint64), ("cell_vertices", C.c_uint64),
+                ("cells_swept", C.c_uint64)]
+
+
 class Edge(C.Structure):
     _fields_ = [("tail", C.c_uint32), ("head", C.c_uint32)]
 
@@ -99,6 +107,8 @@ def lib():
     L.iso_last_query_stats.argtypes = [C.c_void_p, C.POINTER(QueryStats)]
     L.iso_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.iso_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
+    L.iso_profile_enable.argtypes = [C.c_void_p, C.c_int]
+    L.iso_profile_read.argtypes = [C.c_void_p, C.POINTER(Profile)]
     L.iso_free.argtypes = [C.c_void_p]
     L.iso_free.restype = None
     L.iso_last_error.restype = C.c_char_p
@@ -234,6 +244,14 @@ class Graph:
     def set_tuning(self, lanes_per_launch=64, block=256, lds_top=0, use_graph=0):
         t = Tuning(lanes_per_launch, block, lds_top, use_graph)
         _check(lib().iso_set_tuning(self._h, C.byref(t)))
+
+    def profile_enable(self, enable: bool = True):
+        _check(lib().iso_profile_enable(self._h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        p = Profile()
+        _check(lib().iso_profile_read(self._h, C.byref(p)))
+        return {f: getattr(p, f) for f, _ in Profile._fields_}
 
     def get_tuning(self) -> dict:
         t = Tuning()

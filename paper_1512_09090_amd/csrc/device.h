@@ -48,6 +48,14 @@ struct QueryBufs {
     void release();
 };
 
+struct Profile {
+    bool on = false;
+    double core_ms = 0, active_ms = 0, cell_ms = 0, sort_ms = 0;
+    uint64_t core_launches = 0, cell_launches = 0, calls = 0, core_bytes = 0, cell_bytes = 0;
+    uint64_t core_entries = 0, cell_entries = 0, cell_vertices = 0, cells_swept = 0;
+    hipEvent_t ev[6] = {};
+};
+
 struct DevGraph {
     int device = -1;
     hipStream_t stream = nullptr;
@@ -60,6 +68,11 @@ struct DevGraph {
     uint8_t *d_uncovered = nullptr;
     uint64_t bytes = 0;
     QueryBufs bufs;
+    Profile prof;
+    // per-cell sizes for the byte accounting: internal vertices, entries, levels, distinct core tails
+    std::vector<uint32_t> cell_cnt, cell_levels, cell_core_refs;
+    std::vector<uint64_t> cell_entries;
+    uint64_t core_entries = 0;
 
     int upload(const iso::Prep &P, int device);
     int run(const RunArgs &A, RunResult &R);

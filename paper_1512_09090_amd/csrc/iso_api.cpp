@@ -428,6 +428,29 @@ int iso_graph_get_layout(const iso_graph *g, iso_layout *L) {
     return ISO_OK;
 }
 
+int iso_profile_enable(iso_graph *g, int enable) {
+    if (!g) return fail(ISO_EINVAL, "NULL argument");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    auto &P = g->D.prof;
+    hipEvent_t ev[6];
+    std::copy(std::begin(P.ev), std::end(P.ev), ev);
+    P = isodev::Profile();
+    std::copy(ev, ev + 6, P.ev);
+    P.on = enable != 0;
+    return ISO_OK;
+}
+
+int iso_profile_read(const iso_graph *g, iso_profile *o) {
+    if (!g || !o) return fail(ISO_EINVAL, "NULL argument");
+    const auto &P = g->D.prof;
+    o->core_ms = P.core_ms; o->active_ms = P.active_ms; o->cell_ms = P.cell_ms; o->sort_ms = P.sort_ms;
+    o->core_launches = P.core_launches; o->cell_launches = P.cell_launches; o->calls = P.calls;
+    o->core_bytes = P.core_bytes; o->cell_bytes = P.cell_bytes;
+    o->core_entries = P.core_entries; o->cell_entries = P.cell_entries;
+    o->cell_vertices = P.cell_vertices; o->cells_swept = P.cells_swept;
+    return ISO_OK;
+}
+
 int iso_last_query_stats(const iso_graph *g, iso_query_stats *s) {
     if (!g || !s) return fail(ISO_EINVAL, "NULL argument");
     *s = g->last;

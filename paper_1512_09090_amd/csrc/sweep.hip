@@ -288,6 +288,26 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_uncovered, P.uncovered, bytes))) return r;
     std::vector<uint32_t> slots(n, NO_SLOT);
     if ((r = dev_alloc_copy(&d_uslot, slots, bytes))) return r;
+    // sizes for the algorithmic byte accounting of the profile
+    core_entries = P.down_off[n_core];
+    cell_cnt.assign(num_cells, 0);
+    cell_levels.assign(num_cells, 0);
+    cell_core_refs.assign(num_cells, 0);
+    cell_entries.assign(num_cells, 0);
+    std::vector<uint32_t> mark(std::max<uint32_t>(1, n_core), 0xFFFFFFFFu);
+    for (uint32_t c = 0; c < num_cells; ++c) {
+        uint32_t b = P.cell_off[c], e = P.cell_off[c + 1];
+        cell_cnt[c] = e - b;
+        cell_levels[c] = P.cell_lvl_ptr[c + 1] - P.cell_lvl_ptr[c];
+        cell_entries[c] = uint64_t(P.down_off[e]) - P.down_off[b];
+        uint32_t refs = 0;
+        for (uint64_t k = P.down_off[b]; k < P.down_off[e]; ++k) {
+            uint32_t t = P.down_arc[2 * k] & TAIL_MASK;
+            if (t < n_core && mark[t] != c) { mark[t] = c; ++refs; }
+        }
+        cell_core_refs[c] = refs;
+    }
+    for (auto &e : prof.ev) HIPCHK(hipEventCreate(&e));
     return 0;
 }
 
@@ -298,6 +318,7 @@ void DevGraph::release() {
                     d_cell_lvl, d_uncovered, d_uslot};
     for (void *p : ptrs) if (p) hipFree(p);
     bufs.release();
+    for (auto &e : prof.ev) if (e) hipEventDestroy(e);
     if (stream) hipStreamDestroy(stream);
     stream = nullptr;
     device = -1;
@@ -375,6 +396,8 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
     if (nu) k_uslot_set<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(d_uslot, B.d_upos, nu, 0);
     uint32_t *fl_in = B.d_flags, *fl_out = B.d_flags + size_t(flag_words) * K;
     uint32_t *out_count = B.d_counters, *list_len = B.d_counters + 1;
+    const bool prof_on = prof.on;
+    if (prof_on) HIPCHK(hipEventRecord(prof.ev[0], s));
     // core levels, top first
     const uint32_t blk = 256;
     for (size_t l = 0; l + 1 < core_lvl.size(); ++l) {
@@ -386,6 +409,7 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
                                                       flag_words, B.d_keys, out_count, uint32_t(cap),
                                                       A.lane_base, lk, vb, ve);
     }
+    if (prof_on) HIPCHK(hipEventRecord(prof.ev[1], s));
     if (num_cells > 0) {
         k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(
             fl_in, fl_out, flag_words, d_uncovered, d_cell_off, B.d_src_cell, A.lanes, num_cells,
@@ -397,11 +421,13 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
         if (lds > 65536) HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
         uint32_t groups = K >> lg;
+        if (prof_on) HIPCHK(hipEventRecord(prof.ev[2], s));
         k_cell_sweep<<<dim3(num_cells * groups), dim3(256), lds, s>>>(
             B.d_list, list_len, d_cell_off, d_cell_lvl_ptr, d_cell_lvl, d_down_off, d_down_arc, B.d_dcore,
             d_uslot, B.d_uval, d_perm, B.d_taus, B.d_src_cell, A.want_dist ? B.d_dist : nullptr, B.d_keys,
             out_count, uint32_t(cap), A.lane_base, lk, lg);
     }
+    if (prof_on) HIPCHK(hipEventRecord(prof.ev[3], s));
     HIPCHK(hipGetLastError());
     if (nu) k_uslot_set<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(d_uslot, B.d_upos, nu, 1);
     uint32_t counters[2] = {0, 0};
@@ -419,6 +445,38 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
         if (!R.active_list.empty())
             HIPCHK(hipMemcpy(R.active_list.data(), B.d_list, R.active_list.size() * 4, hipMemcpyDeviceToHost));
     }
+    if (prof_on) {
+        float ms = 0;
+        prof.calls++;
+        HIPCHK(hipEventElapsedTime(&ms, prof.ev[0], prof.ev[1]));
+        prof.core_ms += ms;
+        prof.core_launches += core_lvl.size() - 1;
+        prof.core_entries += core_entries;
+        prof.core_bytes += 4ull * (n_core + 1) + 8ull * core_entries + 12ull * n_core +
+                           uint64_t(K) * 8ull * n_core;
+        if (num_cells > 0) {
+            HIPCHK(hipEventElapsedTime(&ms, prof.ev[1], prof.ev[2]));
+            prof.active_ms += ms;
+            HIPCHK(hipEventElapsedTime(&ms, prof.ev[2], prof.ev[3]));
+            prof.cell_ms += ms;
+            prof.cell_launches++;
+            std::vector<uint32_t> lst;
+            if (A.mode_plain) {
+                for (uint32_t c = 0; c < num_cells; ++c) if (cell_cnt[c]) lst.push_back(c);
+            } else {
+                lst.resize(counters[1]);
+                if (!lst.empty())
+                    HIPCHK(hipMemcpy(lst.data(), B.d_list, lst.size() * 4, hipMemcpyDeviceToHost));
+            }
+            for (uint32_t c : lst) {
+                prof.cells_swept++;
+                prof.cell_vertices += cell_cnt[c];
+                prof.cell_entries += cell_entries[c];
+                prof.cell_bytes += 4ull * (cell_cnt[c] + 1) + 8ull * cell_entries[c] + 4ull * (cell_levels[c] + 3) +
+                                   uint64_t(K) * 4ull * cell_core_refs[c];
+            }
+        }
+    }
     if (R.overflow) return 0;   // caller grows the buffer and repeats
     // sort keys: lane bits above 58, then tail, then head
     uint32_t cnt = counters[0];
@@ -430,10 +488,17 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
         HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
                                                  int(cnt), 0, end_bit, s));
         if ((r = ensure((void **)&B.d_sort_tmp, B.sz_sort_tmp, tmp))) return r;
+        if (prof_on) HIPCHK(hipEventRecord(prof.ev[4], s));
         HIPCHK(hipcub::DeviceRadixSort::SortKeys(B.d_sort_tmp, tmp, (const uint64_t *)B.d_keys,
                                                  B.d_keys_sorted, int(cnt), 0, end_bit, s));
+        if (prof_on) HIPCHK(hipEventRecord(prof.ev[5], s));
         HIPCHK(hipMemcpyAsync(R.keys.data(), B.d_keys_sorted, size_t(cnt) * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (prof_on) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, prof.ev[4], prof.ev[5]));
+            prof.sort_ms += ms;
+        }
     }
     return 0;
 }
