@@ -13,7 +13,9 @@ void set_error(const std::string &msg);   // thread-local message behind iso_las
 
 namespace isodev {
 
-constexpr size_t LDS_BUDGET = 128 * 1024;   // dynamic LDS per cell workgroup (gfx950 has 160 KB per CU)
+constexpr size_t LDS_MAX = 160 * 1024;      // LDS of one gfx950 compute unit
+constexpr size_t CELL_LDS_BUDGET = 80 * 1024;   // per cell workgroup: two workgroups per CU
+constexpr size_t TOP_LDS_BUDGET = 144 * 1024;   // the single top-block workgroup
 constexpr uint32_t MAX_LANES = 64;
 
 struct RunArgs {
@@ -25,8 +27,8 @@ struct RunArgs {
     size_t out_cap = 0;          // capacity of the edge-key buffer
     std::vector<uint32_t> taus;      // k_pow2 (padding lanes: INF)
     std::vector<uint32_t> src_cell;  // k_pow2 (padding lanes: NO_CELL)
-    std::vector<uint32_t> upos;      // union of upward-search positions, ascending
-    std::vector<uint32_t> uval;      // upos.size() * k_pow2 labels (INF where a lane did not reach)
+    // upward-search labels of every lane, one entry each: position, lane, label
+    std::vector<uint32_t> upos, ulane, uval;
 };
 
 struct RunResult {
@@ -38,12 +40,12 @@ struct RunResult {
 };
 
 struct QueryBufs {
-    uint32_t *d_dcore = nullptr, *d_uval = nullptr, *d_upos = nullptr, *d_taus = nullptr,
+    uint32_t *d_dcore = nullptr, *d_uval = nullptr, *d_uin = nullptr, *d_taus = nullptr,
              *d_src_cell = nullptr, *d_flags = nullptr, *d_list = nullptr, *d_counters = nullptr,
              *d_dist = nullptr;
     uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
-    size_t sz_dcore = 0, sz_uval = 0, sz_upos = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
+    size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
            sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0;
     void release();
 };
@@ -59,18 +61,25 @@ struct Profile {
 struct DevGraph {
     int device = -1;
     hipStream_t stream = nullptr;
-    uint32_t n = 0, n_core = 0, num_cells = 0, max_internal = 0;
-    std::vector<uint32_t> core_lvl;   // host copy of the core level boundaries
+    uint32_t n = 0, n_core = 0, num_cells = 0;
+    // core levels (host copy), and prefix sums used to size the LDS top block
+    std::vector<uint32_t> core_lvl;
+    std::vector<uint32_t> core_lvl_entries;   // down_off at each core level boundary
     uint32_t *d_down_off = nullptr;
     uint2 *d_down_arc = nullptr;
     uint32_t *d_perm = nullptr, *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr,
-             *d_cell_lvl_ptr = nullptr, *d_cell_lvl = nullptr, *d_uslot = nullptr;
+             *d_uslot = nullptr, *d_top_lvl = nullptr;
     uint8_t *d_uncovered = nullptr;
+    // per-cell blobs for the cell sweep: [offsets][level bounds][core refs][entries]
+    uint32_t *d_blob = nullptr;
+    uint32_t *d_cblob = nullptr;   // word offset of each cell's blob
+    uint4 *d_cmeta = nullptr;      // (internal count, levels, core refs, entries)
+    uint32_t max_blob_words = 0, max_cell_labels = 0;
     uint64_t bytes = 0;
     QueryBufs bufs;
     Profile prof;
-    // per-cell sizes for the byte accounting: internal vertices, entries, levels, distinct core tails
-    std::vector<uint32_t> cell_cnt, cell_levels, cell_core_refs;
+    // per-cell sizes for the byte accounting
+    std::vector<uint32_t> cell_cnt, cell_words, cell_core_refs;
     std::vector<uint64_t> cell_entries;
     uint64_t core_entries = 0;
 

@@ -148,16 +148,19 @@ int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t l
         A.taus[j] = tau[j];
         A.src_cell[j] = P.num_cells ? P.cell_of[src[j]] : iso::NO_CELL;
     }
-    // union of touched positions and the label table
-    std::vector<uint32_t> &pos = A.upos;
-    for (auto &u : U) for (auto &pr : u) pos.push_back(pr.first);
-    std::sort(pos.begin(), pos.end());
-    pos.erase(std::unique(pos.begin(), pos.end()), pos.end());
-    A.uval.assign(pos.size() * K, iso::INF);
+    // upward labels as (position, lane, label) entries; the device builds the slot table
+    size_t total = 0;
+    for (auto &u : U) total += u.size();
+    A.upos.resize(total);
+    A.ulane.resize(total);
+    A.uval.resize(total);
+    size_t o = 0;
     for (uint32_t j = 0; j < lanes; ++j)
         for (auto &pr : U[j]) {
-            size_t i = std::lower_bound(pos.begin(), pos.end(), pr.first) - pos.begin();
-            A.uval[i * K + j] = pr.second;
+            A.upos[o] = pr.first;
+            A.ulane[o] = j;
+            A.uval[o] = pr.second;
+            ++o;
         }
     double t1 = now_ms();
     for (int attempt = 0; attempt < 8; ++attempt) {
