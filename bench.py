@@ -6,7 +6,8 @@ iso_query_batch in the cell-restricted mode: host upward searches, core sweep
 with cell flags, active-cell selection, per-cell sweeps with isochrone-edge
 extraction, radix sort of the edges, copy back.  Inputs are resident on the
 device before the timed region.  Also reported: single-query latency p50/p99
-(both sweep modes), the plain-sweep batched throughput, the live roofline of
+(both sweep modes), the plain-sweep batched throughput, latency percentiles of the
+serving loop under Poisson arrivals at several offered rates, the live roofline of
 the dominant kernel phase (HIP events on the library's stream, algorithmic
 bytes from the graph structure), and the CPU oracle timed on this host.
 
@@ -64,6 +65,75 @@ def run_batches(G, src, tau, lanes, steps, mode, start=0):
     return times
 
 
+def serving(G, n, rates, duration, lanes, inflight):
+    """Poisson arrivals at each offered rate through the continuous-batching server
+    (iso_server_*): submit at the trace's arrival times, collect every result, report the
+    completed rate and the per-request latency (submit to result ready) p50/p99."""
+    import queue
+
+    import paper_1512_09090_amd as iso
+    import synth
+
+    out = []
+    for rate in rates:
+        t, src, tau = synth.serving_trace(n, rate, duration, seed=15)
+        srv = iso.Server(G, max_lanes=lanes, max_inflight=inflight, mode=iso.MODE_CELLS)
+        q = queue.Queue()
+        lat, batch, done_at = [], [], [0.0]
+
+        def collect():
+            while True:
+                tk = q.get()
+                if tk is None:
+                    return
+                _, st = srv.wait(tk)
+                lat.append(st["t_total_ms"])
+                batch.append(st["batch_lanes"])
+                done_at[0] = time.perf_counter()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        try:
+            for i in range(len(t)):
+                dt = t0 + t[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                q.put(srv.submit(int(src[i]), int(tau[i])))
+        finally:
+            q.put(None)
+            th.join()
+            stats = srv.stats()
+            srv.close()
+        span = max(done_at[0] - t0, 1e-9)
+        r = {"offered_hz": rate, "requests": len(t), "completed_qps": round(len(lat) / span, 1),
+             "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+             "mean_batch": round(float(np.mean(batch)), 2), "sweeps": stats["sweeps"]}
+        log(f"serving {r}")
+        out.append(r)
+    return out
+
+
+def copy_probe(mib):
+    """A device-to-device hipMemcpy of `mib` MiB, three times: the runtime's copy kernel reads and
+    writes a known number of bytes, which calibrates the HBM byte counters of a profiler run."""
+    import ctypes as C
+
+    hip = C.CDLL("libamdhip64.so")
+    nbytes = int(mib) << 20
+    a, b = C.c_void_p(), C.c_void_p()
+    for p in (a, b):
+        if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
+            raise RuntimeError("hipMalloc failed in the copy probe")
+    hip.hipMemset(a, 1, C.c_size_t(nbytes))
+    for _ in range(3):
+        hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3)      # hipMemcpyDeviceToDevice
+    hip.hipDeviceSynchronize()
+    hip.hipFree(a)
+    hip.hipFree(b)
+    log(f"copy probe: 3 x {mib} MiB device-to-device")
+
+
 def cpu_baseline(g, src, tau, seconds, threads):
     """The oracle (tau-bounded Dijkstra + edge rule) on this host, one query per thread."""
     import oracle
@@ -111,6 +181,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose lanes per launch, block size and cell LDS budget on a query sample first")
+    ap.add_argument("--tuning", default="", help="JSON file written by the autotuner to apply")
+    ap.add_argument("--serve-rates", default="250,1000,2000,3000",
+                    help="offered Poisson rates (queries/s) for the serving section; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device (calibrates profiler byte counters)")
     ap.add_argument("--cache-dir", default=os.environ.get("ISO_CACHE", "/tmp/iso_cache"))
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,10 +202,26 @@ def main():
     import synth
 
     g, G = load_workload(args.workload, args.cache_dir)
+    if args.copy_probe_mb:
+        copy_probe(args.copy_probe_mb)
     info = G.info()
     src, tau = synth.config_queries(args.workload, 1000)
     lanes = args.lanes
     G.set_tuning(lanes_per_launch=lanes)
+    tuning_note = "defaults"
+    if args.autotune or args.tuning:
+        from paper_1512_09090_amd import autotune
+
+        if args.tuning:
+            best = autotune.apply(G, args.tuning)
+            tuning_note = f"from {args.tuning}"
+        else:
+            ts, tt = autotune.sample(256, src, tau, seed=1)
+            res = autotune.tune(G, ts, tt, log=log)
+            best = res["best"]
+            tuning_note = "autotuned on 256 queries"
+        lanes = best["lanes_per_launch"]
+        log(f"tuning: {best} ({tuning_note})")
 
     # warmup (also grows the library's device buffers to their steady size)
     log(f"warmup {args.warmup} steps of {lanes} queries")
@@ -167,6 +261,8 @@ def main():
             ts.append(1000.0 * (time.perf_counter() - a))
         single_qps[name] = args.latency_queries / (time.perf_counter() - t0)
         lat[name] = {"p50": percentile(ts, 50), "p99": percentile(ts, 99), "mean": float(np.mean(ts))}
+        st = G.last_stats()
+        lat[name]["last_query"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
         log(f"single {name}: {lat[name]}")
 
     # roofline of the dominant device phase in the timed region
@@ -180,6 +276,14 @@ def main():
                 "avg_launch_ms": round(ms / max(1, launches), 4),
                 "algorithmic_bytes_per_launch": int(byts / max(1, launches)),
                 "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()}}
+
+    serve = None
+    if args.serve_rates:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        serve = {"mode": "cells", "max_lanes": lanes, "max_inflight": 2,
+                 "trace": f"Poisson arrivals, {args.serve_seconds:g}s per rate, uniform sources, "
+                          "tau log-uniform 5-300 min",
+                 "rates": serving(G, info["n"], rates, args.serve_seconds, lanes, 2)}
 
     cpu = None
     if not args.no_cpu:
@@ -197,12 +301,13 @@ def main():
                                "tau uniform 10-240 min",
                    "n": info["n"], "m": info["m"], "cells": info["num_cells"], "core": info["n_core"],
                    "core_levels": info["core_levels"], "down_arcs": info["down_arcs"], "lanes": lanes,
-                   "mode": "cells"},
+                   "mode": "cells", "tuning": dict(G.get_tuning(), source=tuning_note)},
         "latency_ms": lat,
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
         "step_ms_p50": round(1000 * percentile(times, 50), 3),
         "step_ms_p99": round(1000 * percentile(times, 99), 3),
+        "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -53,7 +53,8 @@ typedef enum {
     ISO_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
     ISO_EFORMAT = -4,   /* preprocessed file missing fields, wrong version or checksum mismatch */
     ISO_EBUSY = -6,     /* the handle is in use by another call */
-    ISO_ESTATE = -7     /* call not valid in the current state (e.g. server stopped) */
+    ISO_ESTATE = -7,    /* call not valid in the current state (e.g. server stopped) */
+    ISO_EAGAIN = -8     /* result not ready within the given timeout */
 } iso_status;
 
 typedef enum {
@@ -82,8 +83,9 @@ typedef struct {
     const uint32_t *weight;     /* m lengths, each <= 2^32 - 2 */
     const double *xy;           /* optional, 2n coordinates (x0, y0, x1, y1, ...) for the partitioner */
     const uint32_t *cell_of;    /* optional explicit single-level partition: a cell id < num_cells per vertex */
-    uint32_t num_cells;         /* cells of the single-level partition (Section 5); 0 = no partition:
-                                   the hierarchy is a plain CH and only ISO_MODE_PLAIN is available */
+    uint32_t num_cells;         /* cells of the single-level partition (Section 5), at most 2^24; 0 = no
+                                   partition: the hierarchy is a plain CH and only ISO_MODE_PLAIN is
+                                   available */
     uint32_t max_cell_size;     /* upper bound on vertices per cell (0 = 2048); at most 4096 */
     const char *prep_path;      /* optional: if the file exists and matches the input it is loaded instead
                                    of preprocessing; otherwise the preprocessed data is written there */
@@ -151,15 +153,20 @@ int iso_last_query_stats(const iso_graph *g, iso_query_stats *stats);
 /*
  * Tuning knobs of the device sweep (chosen by the autotuner; defaults are
  * used when never set).  lanes_per_launch: queries per sweep in
- * iso_query_batch (1..64); block: threads per workgroup of the level
- * kernels (64..1024, multiple of 64); lds_top: vertices at the top of the
- * hierarchy swept by one workgroup out of LDS (0 disables).
+ * iso_query_batch (1..64); block: threads per workgroup of the core level
+ * kernel (64..1024, multiple of 64); cell_lds_kb: LDS budget of one cell
+ * workgroup in KiB (16..160), which sets how many queries' labels a cell
+ * workgroup holds (more lanes per workgroup = fewer re-reads of the cell's
+ * arcs, fewer resident workgroups per compute unit).
  */
 typedef struct {
     uint32_t lanes_per_launch;
     uint32_t block;
-    uint32_t lds_top;
-    uint32_t use_graph;         /* 1 = replay level launches from a captured hipGraph */
+    uint32_t cell_lds_kb;
+    uint32_t use_graph;         /* 1 = capture the device sweep of a context once (per shape and buffers)
+                                   into a hipGraph and replay it */
+    uint32_t core_mode;         /* must be 0 (one launch per core level); other values are reserved and
+                                   rejected with ISO_EINVAL */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);
@@ -211,9 +218,56 @@ typedef struct {
     uint64_t core_bytes, cell_bytes;                    /* summed algorithmic bytes */
     uint64_t core_entries, cell_entries;                /* downward entries swept */
     uint64_t cell_vertices, cells_swept;                /* internal vertices and cells swept */
+    uint64_t cell_lanes;        /* (cell, query) pairs swept: each cell counts its active lanes */
+    uint64_t cell_items;        /* cell-sweep work items (a cell and up to G of its lanes) */
 } iso_profile;
 int iso_profile_enable(iso_graph *g, int enable);
 int iso_profile_read(const iso_graph *g, iso_profile *out);
+
+/*
+ * Serving loop: continuous batching of isochrone queries on a resident graph.
+ * Requests are queued by iso_server_submit and answered by device sweeps of up
+ * to max_lanes queries each; whenever a sweep context is free, the queued
+ * requests (oldest first) are taken into the next sweep, whose host upward
+ * searches and device work overlap the sweeps already in flight on other
+ * streams.  Contexts and lanes per sweep are admitted by device memory: a
+ * context for k lanes needs about n_core*k*4 + n*4 bytes plus its edge and
+ * label buffers; if device_budget cannot hold max_inflight contexts of
+ * max_lanes lanes, fewer contexts and then fewer lanes are used
+ * (ISO_ENOMEM if not even one lane fits).  Every result equals iso_query's
+ * for the same (source, tau).  While a server runs on a graph, direct query
+ * calls on that graph return ISO_EBUSY.  One server per graph.
+ */
+typedef struct iso_server iso_server;
+typedef struct {
+    uint32_t max_lanes;         /* queries per sweep, 1..64 (0 = 64) */
+    uint32_t max_inflight;      /* sweeps in flight at once, 1..4 (0 = 2) */
+    uint64_t device_budget;     /* device bytes for the sweep contexts (0 = no limit) */
+    int mode;                   /* ISO_MODE_PLAIN or ISO_MODE_CELLS */
+} iso_server_config;
+typedef struct {
+    double t_queue_ms;          /* submit -> its sweep was launched */
+    double t_total_ms;          /* submit -> result ready */
+    uint32_t batch_lanes;       /* queries in the sweep that answered it */
+} iso_request_stats;
+typedef struct {
+    uint64_t submitted, completed, sweeps, lanes_total;
+    uint32_t contexts, lanes_cap, queue_depth, inflight;
+    uint64_t ctx_bytes;         /* device bytes reserved per context */
+} iso_server_stats;
+int iso_server_start(iso_graph *g, const iso_server_config *cfg, iso_server **out);
+/* Non-blocking; *ticket identifies the request.  ISO_ESTATE after iso_server_stop. */
+int iso_server_submit(iso_server *s, uint32_t source, uint32_t tau, uint64_t *ticket);
+/* Waits up to timeout_ms (< 0: forever) for a request; on ISO_OK *edges (release with
+ * iso_free) holds its sorted edges and the request is forgotten; ISO_EAGAIN if not ready;
+ * ISO_EINVAL for an unknown ticket; the request's own error code if its sweep failed. */
+int iso_server_wait(iso_server *s, uint64_t ticket, int timeout_ms, iso_edge **edges, size_t *count,
+                    iso_request_stats *stats);
+int iso_server_get_stats(iso_server *s, iso_server_stats *out);
+/* Stops admission, completes every submitted request (results stay collectable with
+ * iso_server_wait), releases the sweep contexts and the graph. */
+int iso_server_stop(iso_server *s);
+void iso_server_free(iso_server *s);   /* stops if needed and frees the handle */
 
 void iso_free(void *p);
 const char *iso_last_error(void);

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiso.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "iso.h")
 
-ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_EFORMAT, ISO_EBUSY, ISO_ESTATE = 0, -1, -2, -3, -4, -6, -7
+ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_EFORMAT, ISO_EBUSY, ISO_ESTATE, ISO_EAGAIN = 0, -1, -2, -3, -4, -6, -7, -8
 MODE_PLAIN, MODE_CELLS = 0, 1
 INF = 0xFFFFFFFF
 TAU_MAX = 0xFFFFFFFE
@@ -49,8 +49,8 @@ class QueryStats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("lanes_per_launch", C.c_uint32), ("block", C.c_uint32), ("lds_top", C.c_uint32),
-                ("use_graph", C.c_uint32)]
+    _fields_ = [("lanes_per_launch", C.c_uint32), ("block", C.c_uint32), ("cell_lds_kb", C.c_uint32),
+                ("use_graph", C.c_uint32), ("core_mode", C.c_uint32)]
 
 
 _U32P = C.POINTER(C.c_uint32)
@@ -69,11 +69,26 @@ class Profile(C.Structure):
                 ("sort_ms", C.c_double), ("core_launches", C.c_uint64), ("cell_launches", C.c_uint64),
                 ("calls", C.c_uint64), ("core_bytes", C.c_uint64), ("cell_bytes", C.c_uint64),
                 ("core_entries", C.c_uint64), ("cell_entries", C.c_uint64), ("cell_vertices", C.c_uint64),
-                ("cells_swept", C.c_uint64)]
+                ("cells_swept", C.c_uint64), ("cell_lanes", C.c_uint64), ("cell_items", C.c_uint64)]
 
 
 class Edge(C.Structure):
     _fields_ = [("tail", C.c_uint32), ("head", C.c_uint32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("max_lanes", C.c_uint32), ("max_inflight", C.c_uint32), ("device_budget", C.c_uint64),
+                ("mode", C.c_int)]
+
+
+class RequestStats(C.Structure):
+    _fields_ = [("t_queue_ms", C.c_double), ("t_total_ms", C.c_double), ("batch_lanes", C.c_uint32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("sweeps", C.c_uint64),
+                ("lanes_total", C.c_uint64), ("contexts", C.c_uint32), ("lanes_cap", C.c_uint32),
+                ("queue_depth", C.c_uint32), ("inflight", C.c_uint32), ("ctx_bytes", C.c_uint64)]
 
 
 _lib = None
@@ -109,6 +124,14 @@ def lib():
     L.iso_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.iso_profile_enable.argtypes = [C.c_void_p, C.c_int]
     L.iso_profile_read.argtypes = [C.c_void_p, C.POINTER(Profile)]
+    L.iso_server_start.argtypes = [C.c_void_p, C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
+    L.iso_server_submit.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint64)]
+    L.iso_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.POINTER(C.POINTER(Edge)),
+                                  C.POINTER(C.c_size_t), C.POINTER(RequestStats)]
+    L.iso_server_get_stats.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+    L.iso_server_stop.argtypes = [C.c_void_p]
+    L.iso_server_free.argtypes = [C.c_void_p]
+    L.iso_server_free.restype = None
     L.iso_free.argtypes = [C.c_void_p]
     L.iso_free.restype = None
     L.iso_last_error.restype = C.c_char_p
@@ -241,8 +264,8 @@ class Graph:
         _check(lib().iso_last_query_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in QueryStats._fields_}
 
-    def set_tuning(self, lanes_per_launch=64, block=256, lds_top=0, use_graph=0):
-        t = Tuning(lanes_per_launch, block, lds_top, use_graph)
+    def set_tuning(self, lanes_per_launch=64, block=256, cell_lds_kb=40, use_graph=0, core_mode=0):
+        t = Tuning(lanes_per_launch, block, cell_lds_kb, use_graph, core_mode)
         _check(lib().iso_set_tuning(self._h, C.byref(t)))
 
     def profile_enable(self, enable: bool = True):
@@ -257,3 +280,48 @@ class Graph:
         t = Tuning()
         _check(lib().iso_get_tuning(self._h, C.byref(t)))
         return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+
+class Server:
+    """Serving loop with continuous batching on a resident graph (iso_server_* in include/iso.h)."""
+
+    def __init__(self, graph: Graph, max_lanes=64, max_inflight=2, device_budget=0, mode=MODE_CELLS):
+        cfg = ServerConfig(int(max_lanes), int(max_inflight), int(device_budget), int(mode))
+        h = C.c_void_p()
+        _check(lib().iso_server_start(graph._h, C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._graph = graph
+
+    def submit(self, source: int, tau: int) -> int:
+        t = C.c_uint64()
+        _check(lib().iso_server_submit(self._h, int(source), int(tau), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(edges (count, 2) uint32, stats dict); raises IsoError (code ISO_EAGAIN if not ready)."""
+        ptr = C.POINTER(Edge)()
+        cnt = C.c_size_t()
+        st = RequestStats()
+        _check(lib().iso_server_wait(self._h, int(ticket), int(timeout_ms), C.byref(ptr), C.byref(cnt),
+                                     C.byref(st)))
+        return _edges_to_numpy(ptr, cnt.value), {f: getattr(st, f) for f, _ in RequestStats._fields_}
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().iso_server_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            _check(lib().iso_server_stop(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().iso_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,157 @@
+// api_internal.h - internals shared by the C ABI (iso_api.cpp) and the serving loop
+// (server.cpp): the graph handle, the host upward search, marshalling of queries into a
+// device sweep.
+#pragma once
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/iso.h"
+#include "device.h"
+#include "prep.h"
+
+inline double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Upward CH search (Section 2: forward search on G-up; no stopping criterion, as in
+// the first phase of PHAST and of isoPHAST-CP).  In the sweep layout every upward arc
+// goes to a strictly smaller position (a higher level, or from a cell's internal
+// vertex to the core), so the search space is a DAG in position order: visiting the
+// reached vertices from the largest position down finalises each label before it is
+// used, which gives exactly the labels of Dijkstra's algorithm on G-up without a
+// priority queue.  Reached vertices are kept in a two-level bitmap (words, and a
+// summary bit per non-zero word); labels live in a small open-addressing table,
+// since the search space is a few thousand vertices.
+struct UpwardGraph {
+    static constexpr uint32_t INLINE = 4;   // arcs stored in the vertex's own 32-byte slot
+    std::vector<uint64_t> inl;   // n * INLINE: head << 32 | length (length INF = empty)
+    std::vector<uint32_t> off;   // n + 1: further arcs of each vertex in `more`
+    std::vector<uint64_t> more;
+    bool dag_ok = true;          // every arc goes to a smaller position
+    void build(const iso::Prep &P) {
+        inl.assign(size_t(P.n) * INLINE, uint64_t(iso::INF));
+        off.assign(size_t(P.n) + 1, 0);
+        for (uint32_t u = 0; u < P.n; ++u) {
+            uint32_t d = P.up_off[u + 1] - P.up_off[u];
+            off[u + 1] = off[u] + (d > INLINE ? d - INLINE : 0);
+        }
+        more.resize(off[P.n]);
+        for (uint32_t u = 0; u < P.n; ++u)
+            for (uint32_t e = P.up_off[u], k = 0; e < P.up_off[u + 1]; ++e, ++k) {
+                uint64_t a = (uint64_t(P.up_head[e]) << 32) | P.up_w[e];
+                if (k < INLINE) inl[size_t(u) * INLINE + k] = a;
+                else more[off[u] + k - INLINE] = a;
+                if (P.up_head[e] >= u) dag_ok = false;
+            }
+    }
+};
+
+struct UpwardSearch {
+    static constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+    std::vector<uint32_t> key, val;   // open addressing, power-of-two capacity
+    uint32_t mask = 0;
+    std::vector<uint32_t> used;       // occupied slots (for clearing)
+    std::vector<uint64_t> bits, sum;  // reached positions; summary bit per non-zero word
+
+    void init(uint32_t n) {
+        rehash(1u << 14);
+        bits.assign((size_t(n) + 63) / 64, 0);
+        sum.assign((bits.size() + 63) / 64, 0);
+    }
+    void rehash(uint32_t cap) {
+        std::vector<std::pair<uint32_t, uint32_t>> keep;
+        for (uint32_t s : used) keep.push_back({key[s], val[s]});
+        key.assign(cap, EMPTY);
+        val.assign(cap, iso::INF);
+        mask = cap - 1;
+        used.clear();
+        for (auto &kv : keep) *slot(kv.first) = kv.second;
+    }
+    static uint32_t hash(uint32_t v) { return (v * 0x9E3779B1u) ^ (v >> 15); }
+    uint32_t *slot(uint32_t v) {   // label slot of v (inserted with INF if absent)
+        uint32_t h = hash(v) & mask;
+        while (key[h] != EMPTY && key[h] != v) h = (h + 1) & mask;
+        if (key[h] == EMPTY) {
+            key[h] = v;
+            used.push_back(h);
+        }
+        return &val[h];
+    }
+    void mark(const UpwardGraph &G, uint32_t x) {
+        __builtin_prefetch(&G.inl[size_t(x) * UpwardGraph::INLINE]);
+        size_t w = x >> 6;
+        bits[w] |= 1ull << (x & 63);
+        sum[w >> 6] |= 1ull << (w & 63);
+    }
+
+    // out: (position, label) pairs sorted by position; returns the number of reached vertices.
+    // Vertices at positions below `stop` (the top-of-hierarchy table) are recorded but not
+    // expanded: the table covers every path continuing inside that set.
+    uint32_t run(const UpwardGraph &G, uint32_t src_pos, std::vector<std::pair<uint32_t, uint32_t>> &out,
+                 uint32_t stop = 0) {
+        for (uint32_t s : used) { key[s] = EMPTY; val[s] = iso::INF; }
+        used.clear();
+        out.clear();
+        *slot(src_pos) = 0;
+        mark(G, src_pos);
+        uint32_t settled = 0;
+        // summary words from the source's down to 0; inside them, words and bits high to low
+        for (int64_t si = int64_t(src_pos >> 12); si >= 0; --si) {
+            while (sum[si]) {
+                int wb = 63 - __builtin_clzll(sum[si]);
+                size_t wi = size_t(si) * 64 + wb;
+                while (bits[wi]) {
+                    int b = 63 - __builtin_clzll(bits[wi]);
+                    uint32_t u = uint32_t(wi * 64 + b);
+                    bits[wi] &= ~(1ull << b);
+                    uint32_t du = *slot(u);
+                    out.push_back({u, du});
+                    ++settled;
+                    if (u < stop) continue;
+                    auto relax = [&](uint64_t a) {
+                        uint32_t x = uint32_t(a >> 32);
+                        uint32_t nd = iso::sat_add(du, uint32_t(a));
+                        if (used.size() * 2 >= key.size()) rehash(uint32_t(key.size()) * 2);
+                        uint32_t *d = slot(x);
+                        if (nd < *d) *d = nd;
+                        mark(G, x);
+                    };
+                    const uint64_t *il = &G.inl[size_t(u) * UpwardGraph::INLINE];
+                    for (uint32_t k = 0; k < UpwardGraph::INLINE && uint32_t(il[k]) != iso::INF; ++k) relax(il[k]);
+                    for (uint32_t e = G.off[u]; e < G.off[u + 1]; ++e) relax(G.more[e]);
+                }
+                sum[si] &= ~(1ull << wb);
+            }
+        }
+        std::reverse(out.begin(), out.end());   // ascending positions
+        return settled;
+    }
+};
+
+struct iso_graph {
+    iso::Prep P;
+    isodev::DevGraph D;
+    bool on_device = false;
+    int threads = 1;
+    std::atomic<bool> busy{false};
+    iso_query_stats last{};
+    iso_tuning tuning{64, 256, 40, 0};
+    UpwardGraph upg;                // packed upward graph
+    std::vector<UpwardSearch> up;   // one workspace per host thread
+    size_t out_cap = 1 << 20;
+};
+
+
+// Upward searches of `lanes` queries (up to g->threads host threads) and the device inputs
+// of one sweep.  settled (optional, lanes entries) receives the upward search sizes.
+void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
+                    bool want_dist, isodev::RunArgs &A, uint32_t *settled);
+// Sorted keys of one sweep -> per-lane edge lists (original ids).
+void decode_keys(const std::vector<uint64_t> &keys, uint32_t lanes, std::vector<std::vector<iso_edge>> &out);
+int api_fail(int code, const std::string &msg);

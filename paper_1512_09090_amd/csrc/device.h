@@ -13,15 +13,18 @@ void set_error(const std::string &msg);   // thread-local message behind iso_las
 
 namespace isodev {
 
-constexpr size_t LDS_MAX = 160 * 1024;      // LDS of one gfx950 compute unit
-constexpr size_t CELL_LDS_BUDGET = 80 * 1024;   // per cell workgroup: two workgroups per CU
-constexpr size_t TOP_LDS_BUDGET = 144 * 1024;   // the single top-block workgroup
+constexpr size_t LDS_MAX = 160 * 1024;          // LDS of one gfx950 compute unit
+constexpr uint32_t TABLE_MAX = 4096;            // vertices of the top-of-hierarchy distance table
 constexpr uint32_t MAX_LANES = 64;
+constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a 6-bit lane chunk
 
 struct RunArgs {
     uint32_t lanes = 1;          // real queries in this launch (<= k_pow2)
     uint32_t k_pow2 = 1;         // label row width (power of two >= lanes)
     uint32_t lane_base = 0;
+    uint32_t block = 256;            // threads per workgroup of the core level kernel
+    uint32_t use_graph = 0;          // 1: replay the captured device sweep
+    size_t cell_lds_bytes = 40 * 1024;
     bool mode_plain = true;
     bool want_dist = false;
     size_t out_cap = 0;          // capacity of the edge-key buffer
@@ -40,6 +43,10 @@ struct RunResult {
 };
 
 struct QueryBufs {
+    uint32_t *d_xin = nullptr;   // per-lane upward labels inside the table: ptr (k+1), pos, val
+    size_t sz_xin = 0;
+    uint32_t *d_uslot = nullptr; // n entries: slot of a position in the upward-label table, or none
+    size_t sz_uslot = 0;
     uint32_t *d_dcore = nullptr, *d_uval = nullptr, *d_uin = nullptr, *d_taus = nullptr,
              *d_src_cell = nullptr, *d_flags = nullptr, *d_list = nullptr, *d_counters = nullptr,
              *d_dist = nullptr;
@@ -54,37 +61,73 @@ struct Profile {
     bool on = false;
     double core_ms = 0, active_ms = 0, cell_ms = 0, sort_ms = 0;
     uint64_t core_launches = 0, cell_launches = 0, calls = 0, core_bytes = 0, cell_bytes = 0;
-    uint64_t core_entries = 0, cell_entries = 0, cell_vertices = 0, cells_swept = 0;
+    uint64_t core_entries = 0, cell_entries = 0, cell_vertices = 0, cells_swept = 0, cell_lanes = 0,
+             cell_items = 0;
     hipEvent_t ev[6] = {};
+};
+
+// Everything the captured sweep sequence depends on (kernel arguments and grid shapes).
+struct GraphSig {
+    uint32_t K, plain, dist, block, cell_lds, xcap;
+    uint64_t cap;
+    uint64_t ptr[10];
+};
+
+// One sweep in flight: its stream, buffers, profile and the state kept between launch and
+// finish.  Several contexts over one DevGraph run concurrently (the serving loop).
+struct SweepCtx {
+    hipGraphExec_t graph_exec = nullptr;   // captured device sweep (use_graph)
+    GraphSig sig{};
+    uint32_t xcap = 0;                     // capacity of the per-lane table lists
+    int device = -1;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    QueryBufs bufs;
+    Profile prof;
+    bool pending = false;
+    uint32_t K = 1, lk = 0, lg = 0, lanes = 0, lane_base = 0, nlev = 0, top = 0;
+    size_t cap = 0;
+    bool mode_plain = true, want_dist = false;
+    uint32_t *h_counters = nullptr;   // pinned: keys produced, active cells
+    int create(int device);
+    void release();
 };
 
 struct DevGraph {
     int device = -1;
-    hipStream_t stream = nullptr;
     uint32_t n = 0, n_core = 0, num_cells = 0;
     // core levels (host copy), and prefix sums used to size the LDS top block
     std::vector<uint32_t> core_lvl;
     std::vector<uint32_t> core_lvl_entries;   // down_off at each core level boundary
     uint32_t *d_down_off = nullptr;
     uint2 *d_down_arc = nullptr;
-    uint32_t *d_perm = nullptr, *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr,
-             *d_uslot = nullptr, *d_top_lvl = nullptr;
+    uint32_t *d_perm = nullptr, *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
+    // top-of-hierarchy table: X = core positions [0, TX) covering the first nlev_table levels;
+    // d_table[y * TX + x] = shortest downward path y -> x inside X
+    uint32_t TX = 0, nlev_table = 0;
+    uint32_t *d_table = nullptr;
     uint8_t *d_uncovered = nullptr;
     // per-cell blobs for the cell sweep: [offsets][level bounds][core refs][entries]
     uint32_t *d_blob = nullptr;
     uint32_t *d_cblob = nullptr;   // word offset of each cell's blob
     uint4 *d_cmeta = nullptr;      // (internal count, levels, core refs, entries)
-    uint32_t max_blob_words = 0, max_cell_labels = 0;
+    uint32_t max_blob_words = 0, max_cell_labels = 0, max_cell_cnt = 0, max_cell_levels = 0;
     uint64_t bytes = 0;
-    QueryBufs bufs;
-    Profile prof;
+    SweepCtx main;   // context of the direct query calls
     // per-cell sizes for the byte accounting
     std::vector<uint32_t> cell_cnt, cell_words, cell_core_refs;
     std::vector<uint64_t> cell_entries;
     uint64_t core_entries = 0;
 
     int upload(const iso::Prep &P, int device);
-    int run(const RunArgs &A, RunResult &R);
+    // launch: copies the inputs and enqueues the whole sweep on C.stream (asynchronous);
+    // finish: waits for it, sorts the edge keys and copies them back.  A result with
+    // overflow set must be launched again with a larger capacity.
+    int launch(SweepCtx &C, const RunArgs &A);
+    int finish(SweepCtx &C, RunResult &R);
+    int run(SweepCtx &C, const RunArgs &A, RunResult &R);
+    // device bytes a context needs for k lanes and an edge capacity (admission control)
+    size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const;
     void release();
 };
 

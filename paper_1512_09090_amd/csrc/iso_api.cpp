@@ -11,83 +11,10 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/iso.h"
-#include "device.h"
-#include "prep.h"
+#include "api_internal.h"
 
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
-
-namespace {
-
-double now_ms() {
-    using namespace std::chrono;
-    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
-
-// Upward CH search (Section 2: forward search on G-up; no stopping criterion, as in
-// the first phase of PHAST and of isoPHAST-CP).  Labels are exact upper bounds
-// along upward paths; the downward sweep makes them exact (Section 2, PHAST).
-struct UpwardSearch {
-    std::vector<uint32_t> dist, stamp;
-    uint32_t epoch = 0;
-    std::vector<std::pair<uint32_t, uint32_t>> heap;
-    std::vector<uint32_t> touched;
-
-    void init(uint32_t n) { dist.assign(n, iso::INF); stamp.assign(n, 0); epoch = 0; }
-
-    // out: (position, label) pairs sorted by position; returns settled count
-    uint32_t run(const iso::Prep &P, uint32_t src_pos, std::vector<std::pair<uint32_t, uint32_t>> &out) {
-        if (++epoch == 0) { std::fill(stamp.begin(), stamp.end(), 0u); epoch = 1; }
-        heap.clear();
-        touched.clear();
-        auto get = [&](uint32_t v) { return stamp[v] == epoch ? dist[v] : iso::INF; };
-        auto cmp = [](const std::pair<uint32_t, uint32_t> &a, const std::pair<uint32_t, uint32_t> &b) {
-            return a.first > b.first;
-        };
-        stamp[src_pos] = epoch;
-        dist[src_pos] = 0;
-        touched.push_back(src_pos);
-        heap.push_back({0, src_pos});
-        uint32_t settled = 0;
-        while (!heap.empty()) {
-            std::pop_heap(heap.begin(), heap.end(), cmp);
-            auto [k, u] = heap.back();
-            heap.pop_back();
-            if (k != get(u)) continue;
-            ++settled;
-            for (uint32_t e = P.up_off[u]; e < P.up_off[u + 1]; ++e) {
-                uint32_t x = P.up_head[e];
-                uint32_t nd = iso::sat_add(k, P.up_w[e]);
-                if (nd < get(x)) {
-                    if (stamp[x] != epoch) touched.push_back(x);
-                    stamp[x] = epoch;
-                    dist[x] = nd;
-                    heap.push_back({nd, x});
-                    std::push_heap(heap.begin(), heap.end(), cmp);
-                }
-            }
-        }
-        out.clear();
-        for (uint32_t v : touched) if (dist[v] != iso::INF) out.push_back({v, dist[v]});
-        std::sort(out.begin(), out.end());
-        return settled;
-    }
-};
-
-}  // namespace
-
-struct iso_graph {
-    iso::Prep P;
-    isodev::DevGraph D;
-    bool on_device = false;
-    int threads = 1;
-    std::atomic<bool> busy{false};
-    iso_query_stats last{};
-    iso_tuning tuning{64, 256, 0, 0};
-    std::vector<UpwardSearch> up;   // one workspace per host thread
-    size_t out_cap = 1 << 20;
-};
 
 namespace {
 
@@ -112,23 +39,24 @@ uint32_t pow2_at_least(uint32_t x) {
     return k;
 }
 
-// Run `lanes` queries (<= 64) through one device sweep.  keys_out receives the
-// sorted keys; dist_out (optional) the label rows.
-int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
-              bool want_dist, isodev::RunResult &R) {
+}  // namespace
+
+void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
+                    bool want_dist, isodev::RunArgs &A, uint32_t *settled) {
     const iso::Prep &P = g->P;
-    isodev::RunArgs A;
+    A = isodev::RunArgs();
+    A.block = g->tuning.block;
+    A.cell_lds_bytes = size_t(g->tuning.cell_lds_kb) * 1024;
+    A.use_graph = g->tuning.use_graph;
     A.lanes = lanes;
     A.k_pow2 = pow2_at_least(lanes);
     A.mode_plain = plain;
     A.want_dist = want_dist;
     const uint32_t K = A.k_pow2;
-    A.taus.assign(K, iso::INF);
+    A.taus.assign(K, 0u);   // padding lanes: every label INF > 0, so they activate no cell and emit nothing
     A.src_cell.assign(K, iso::NO_CELL);
     // upward searches, one host thread per lane (bounded by g->threads)
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> U(lanes);
-    std::vector<uint32_t> settled(lanes, 0);
-    double t0 = now_ms();
     {
         int T = std::min<int>(g->threads, int(lanes));
         std::atomic<uint32_t> next{0};
@@ -136,7 +64,8 @@ int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t l
             for (;;) {
                 uint32_t j = next.fetch_add(1);
                 if (j >= lanes) break;
-                settled[j] = g->up[tid].run(P, P.pos[src[j]], U[j]);
+                uint32_t st = g->up[tid].run(g->upg, P.pos[src[j]], U[j], g->D.TX);
+                if (settled) settled[j] = st;
             }
         };
         std::vector<std::thread> pool;
@@ -162,10 +91,35 @@ int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t l
             A.uval[o] = pr.second;
             ++o;
         }
+}
+
+void decode_keys(const std::vector<uint64_t> &keys, uint32_t lanes, std::vector<std::vector<iso_edge>> &out) {
+    out.assign(lanes, {});
+    for (uint64_t key : keys) {
+        uint32_t j = uint32_t(key >> 58);
+        if (j < lanes)
+            out[j].push_back(iso_edge{uint32_t((key >> 29) & ((1u << 29) - 1)), uint32_t(key & ((1u << 29) - 1))});
+    }
+}
+
+int api_fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+namespace {
+
+// Run `lanes` queries (<= 64) through one device sweep of the graph's own context.
+int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
+              bool want_dist, isodev::RunResult &R) {
+    isodev::RunArgs A;
+    std::vector<uint32_t> settled(lanes, 0);
+    double t0 = now_ms();
+    build_run_args(g, src, tau, lanes, plain, want_dist, A, settled.data());
     double t1 = now_ms();
     for (int attempt = 0; attempt < 8; ++attempt) {
         A.out_cap = g->out_cap;
-        int r = g->D.run(A, R);
+        int r = g->D.run(g->D.main, A, R);
         if (r) return r;
         if (!R.overflow) break;
         g->out_cap = std::max<size_t>(g->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
@@ -233,6 +187,10 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
                 iso::partition_bfs(A, maxc, cell_of, num_cells);
             }
         }
+        if (num_cells > isodev::MAX_CELLS) {
+            delete g;
+            return fail(ISO_EINVAL, "more than 2^24 cells");
+        }
         if (num_cells) {
             std::vector<uint32_t> sz(num_cells, 0);
             for (uint32_t c : cell_of) sz[c]++;
@@ -270,6 +228,11 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
         if (uint64_t(g->P.n_core) * isodev::MAX_LANES >= (uint64_t(1) << 32)) {
             delete g;
             return fail(ISO_EINVAL, "core too large for 64 interleaved lanes");
+        }
+        g->upg.build(g->P);
+        if (!g->upg.dag_ok) {
+            delete g;
+            return fail(ISO_EFORMAT, "upward arcs must lead to smaller sweep positions");
         }
         g->up.resize(g->threads);
         for (auto &u : g->up) u.init(g->P.n);
@@ -434,7 +397,7 @@ int iso_graph_get_layout(const iso_graph *g, iso_layout *L) {
 int iso_profile_enable(iso_graph *g, int enable) {
     if (!g) return fail(ISO_EINVAL, "NULL argument");
     if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
-    auto &P = g->D.prof;
+    auto &P = g->D.main.prof;
     hipEvent_t ev[6];
     std::copy(std::begin(P.ev), std::end(P.ev), ev);
     P = isodev::Profile();
@@ -445,12 +408,13 @@ int iso_profile_enable(iso_graph *g, int enable) {
 
 int iso_profile_read(const iso_graph *g, iso_profile *o) {
     if (!g || !o) return fail(ISO_EINVAL, "NULL argument");
-    const auto &P = g->D.prof;
+    const auto &P = g->D.main.prof;
     o->core_ms = P.core_ms; o->active_ms = P.active_ms; o->cell_ms = P.cell_ms; o->sort_ms = P.sort_ms;
     o->core_launches = P.core_launches; o->cell_launches = P.cell_launches; o->calls = P.calls;
     o->core_bytes = P.core_bytes; o->cell_bytes = P.cell_bytes;
     o->core_entries = P.core_entries; o->cell_entries = P.cell_entries;
     o->cell_vertices = P.cell_vertices; o->cells_swept = P.cells_swept;
+    o->cell_lanes = P.cell_lanes; o->cell_items = P.cell_items;
     return ISO_OK;
 }
 
@@ -464,6 +428,11 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (!g || !t) return fail(ISO_EINVAL, "NULL argument");
     if (t->lanes_per_launch < 1 || t->lanes_per_launch > isodev::MAX_LANES) return fail(ISO_EINVAL, "lanes_per_launch out of range");
     if (t->block < 64 || t->block > 1024 || t->block % 64) return fail(ISO_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    if (t->cell_lds_kb < 16 || t->cell_lds_kb > 160) return fail(ISO_EINVAL, "cell_lds_kb must be in [16, 160]");
+    if (t->use_graph > 1) return fail(ISO_EINVAL, "use_graph must be 0 or 1");
+    if (t->core_mode != 0)
+        return fail(ISO_EINVAL, "core_mode must be 0: the single-launch core sweep with a grid barrier "
+                                "is disabled");
     g->tuning = *t;
     return ISO_OK;
 }

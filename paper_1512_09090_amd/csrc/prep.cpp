@@ -921,7 +921,7 @@ LoadStatus load_prep(const std::string &path, Prep &p, uint64_t input_hash) {
             for (uint32_t e = p.down_off[v]; ok && e < p.down_off[v + 1]; ++e)
                 ok = (p.down_arc[2 * uint64_t(e)] & TAIL_MASK) < v;
         for (uint32_t v = 0; ok && v < p.n; ++v)
-            for (uint32_t e = p.up_off[v]; ok && e < p.up_off[v + 1]; ++e) ok = p.up_head[e] < p.n;
+            for (uint32_t e = p.up_off[v]; ok && e < p.up_off[v + 1]; ++e) ok = p.up_head[e] < v;
         for (uint32_t v = 0; ok && v < p.n; ++v) ok = p.perm[v] < p.n && p.pos[p.perm[v]] == v;
     }
     return ok ? LOAD_OK : LOAD_CORRUPT;

@@ -9,14 +9,16 @@
 //      i (label <= tau) and o (label + ecc > tau) - the relaxed rule of the
 //      parallel-query paragraph of Section 6 - and tests the flagged original
 //      arcs at it for isochrone edges (Section 5, output during the sweep).
-//      The top levels, where the hierarchy narrows to a chain, run in one
-//      workgroup with labels and arcs in LDS; the rest runs one launch per level.
+//      The top levels, where the hierarchy narrows to a near-clique chain, are
+//      answered from a precomputed table of downward distances (one (min,+)
+//      product per query); the rest runs one launch per level.
 //   2. active cells: i and (o or uncovered), plus the source's cell (Section 4
 //      definition of an active cell; Section 5 source-cell case).
 //   3. cell sweep: one workgroup per active cell (cells are independent,
-//      Section 5 parallelisation).  The cell's downward arcs, level bounds and
-//      referenced core labels are staged in LDS first, then its levels run
-//      between workgroup barriers and isochrone edges are extracted from LDS.
+//      Section 5 parallelisation).  Labels of the cell and of the core vertices
+//      it references live in LDS; each level's arcs are prefetched while the
+//      previous level is relaxed; levels are separated by workgroup barriers and
+//      isochrone edges are extracted as soon as a label is final.
 // In the plain mode step 2 selects every cell (a PHAST one-to-all sweep).
 //
 // k queries share one sweep: labels are stored k-interleaved (row of k uint32
@@ -29,12 +31,16 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
+#include <thread>
 
 #include "device.h"
 
 namespace isodev {
+
 
 constexpr uint32_t INF = 0xFFFFFFFFu;
 constexpr uint32_t TAIL_MASK = 0x3FFFFFFFu;
@@ -95,11 +101,11 @@ __global__ void k_uset_clear(uint32_t *__restrict__ uslot, const uint32_t *__res
 
 // Flags of core vertex v in its cell for lane j (relaxed rule: d <= tau sets i, d + ecc > tau sets o).
 __device__ __forceinline__ void set_cell_flags(uint32_t c, uint32_t ecc, uint32_t dv, uint32_t tau, uint32_t j,
-                                               uint32_t flag_words, uint32_t *__restrict__ fl_in,
+                                               uint32_t K, uint32_t *__restrict__ fl_in,
                                                uint32_t *__restrict__ fl_out) {
     if (c == NO_CELL) return;
     uint32_t bit = 1u << (c & 31u);
-    uint32_t w = j * flag_words + (c >> 5);
+    uint32_t w = (c >> 5) * K + j;   // the k lanes' words of one cell group are contiguous
     if (dv <= tau && !(fl_in[w] & bit)) atomicOr(&fl_in[w], bit);
     if (sat_add(dv, ecc) > tau && !(fl_out[w] & bit)) atomicOr(&fl_out[w], bit);
 }
@@ -127,18 +133,19 @@ __device__ __forceinline__ uint32_t relax_group(ARC arc, LAB lab, uint32_t beg, 
                                                 bool &any_in, bool &any_out) {
     uint32_t m = INF;
     uint32_t e = beg + sub;
-    for (; e + S < end; e += 2 * S) {
-        uint2 a0 = arc(e), a1 = arc(e + S);
+    auto see = [&](uint2 a, uint32_t l) {
+        m = min(m, sat_add(l, a.y));
+        if (a.x & FLAGS) { if (l <= tau) any_in = true; else any_out = true; }
+    };
+    for (; e + 3 * S < end; e += 4 * S) {
+        uint2 a0 = arc(e), a1 = arc(e + S), a2 = arc(e + 2 * S), a3 = arc(e + 3 * S);
         uint32_t l0 = lab(a0.x & TAIL_MASK), l1 = lab(a1.x & TAIL_MASK);
-        m = min(m, min(sat_add(l0, a0.y), sat_add(l1, a1.y)));
-        if (a0.x & FLAGS) { if (l0 <= tau) any_in = true; else any_out = true; }
-        if (a1.x & FLAGS) { if (l1 <= tau) any_in = true; else any_out = true; }
+        uint32_t l2 = lab(a2.x & TAIL_MASK), l3 = lab(a3.x & TAIL_MASK);
+        see(a0, l0); see(a1, l1); see(a2, l2); see(a3, l3);
     }
-    if (e < end) {
+    for (; e < end; e += S) {
         uint2 a0 = arc(e);
-        uint32_t l0 = lab(a0.x & TAIL_MASK);
-        m = min(m, sat_add(l0, a0.y));
-        if (a0.x & FLAGS) { if (l0 <= tau) any_in = true; else any_out = true; }
+        see(a0, lab(a0.x & TAIL_MASK));
     }
     for (uint32_t o = K; o < K * S; o <<= 1) m = min(m, (uint32_t)__shfl_xor((int)m, (int)o));
     return min(init, m);
@@ -166,58 +173,75 @@ __device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &
     }
 }
 
-// Top of the core: positions [0, T), levels given by top_lvl[0..nl] (top first), one
-// workgroup, labels (T rows of K) and the arcs of these vertices in LDS.
-__global__ void __launch_bounds__(1024)
-k_core_top(CoreArgs A, const uint32_t *__restrict__ top_lvl, uint32_t nl, uint32_t T, uint32_t ET) {
-    extern __shared__ uint32_t smem[];
-    const uint32_t lk = A.lk, K = 1u << lk;
-    uint2 *s_arc = reinterpret_cast<uint2 *>(smem);                 // ET entries
-    uint32_t *s_off = smem + 2 * ET;                                  // T + 1 offsets
-    uint32_t *s_lab = s_off + T + 1;                                  // T * K labels
-    for (uint32_t i = threadIdx.x; i < ET; i += blockDim.x) s_arc[i] = A.down_arc[i];
-    for (uint32_t i = threadIdx.x; i <= T; i += blockDim.x) s_off[i] = A.down_off[i];
-    for (uint32_t i = threadIdx.x; i < (T << lk); i += blockDim.x) {
-        uint32_t v = i >> lk, j = i & (K - 1);
-        uint32_t s = A.uslot[v];
-        s_lab[i] = s != NO_SLOT ? A.uval[(s << lk) + j] : INF;
-    }
-    __syncthreads();
-    auto arc = [&](uint32_t e) { return s_arc[e]; };
-    for (uint32_t l = 0; l < nl; ++l) {
-        uint32_t a = top_lvl[l], b = top_lvl[l + 1];
-        // sub-lanes per vertex: enough to cover the level's mean in-degree, within one wavefront
-        uint32_t deg = (s_off[b] - s_off[a] + (b - a) - 1) / (b - a);
-        uint32_t ls = 0;
-        while ((1u << ls) < deg && (K << (ls + 1)) <= 64u) ++ls;
-        const uint32_t S = 1u << ls, lgs = lk + ls;
-        const uint32_t per_pass = blockDim.x >> lgs;
-        for (uint32_t vb = a; vb < b; vb += per_pass) {
-            uint32_t v = vb + (threadIdx.x >> lgs);
-            uint32_t j = threadIdx.x & (K - 1), sub = (threadIdx.x >> lk) & (S - 1);
-            bool act = v < b;
-            uint32_t tau = A.taus[j];
-            uint32_t beg = act ? s_off[v] : 0, end = act ? s_off[v + 1] : 0;
-            auto lab = [&](uint32_t t) { return s_lab[(t << lk) + j]; };
-            bool any_in = false, any_out = false;
-            uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, act ? s_lab[(v << lk) + j] : INF, tau,
-                                      any_in, any_out);
-            if (act && sub == 0) {
-                s_lab[(v << lk) + j] = dv;
-                set_cell_flags(A.core_cell[v], A.core_ecc[v], dv, tau, j, A.flag_words, A.fl_in, A.fl_out);
-            }
-            extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
+// Top of the core as a table: X = positions [0, TX) (the top levels, where the
+// hierarchy narrows to a near-clique chain of one-vertex levels).  D[y][x] is the
+// length of a shortest path y -> x that uses only vertices of X (upward arcs and
+// downward entries among them; 0 on the diagonal, INF if none), precomputed per
+// graph.  The host's upward search stops at the first vertices of X it reaches
+// (every upward path entering X stays in X), and a query's labels on X are
+//   d(x) = min over reached y in X of up(y) + D[y][x]
+// - a shortest up-down path to x (Section 2, CH) through its first vertex in X,
+// written as one (min,+) product instead of a level-by-level sweep of X.
+// One wavefront per (64-column tile, lane, split of the lane's upward list); the
+// splits are combined with atomicMin into dcore (pre-filled with INF).
+__global__ void __launch_bounds__(64)
+k_top_table(const uint32_t *__restrict__ D, uint32_t TX, const uint32_t *__restrict__ xptr,
+            const uint32_t *__restrict__ xpos, const uint32_t *__restrict__ xval, uint32_t *__restrict__ dcore,
+            uint32_t lk, uint32_t tiles, uint32_t splits) {
+    const uint32_t K = 1u << lk;
+    uint32_t b = blockIdx.x;
+    uint32_t tile = b % tiles;
+    uint32_t j = (b / tiles) & (K - 1);
+    uint32_t q = b / (tiles * K);
+    uint32_t x = tile * 64 + threadIdx.x;
+    uint32_t lo = xptr[j], hi = xptr[j + 1];
+    uint32_t len = hi - lo, per = (len + splits - 1) / splits;
+    uint32_t e0 = lo + q * per, e1 = min(hi, e0 + per);
+    uint32_t acc = INF;
+    if (x < TX) {
+        uint32_t e = e0;
+        for (; e + 4 <= e1; e += 4) {
+            uint32_t y0 = xpos[e], y1 = xpos[e + 1], y2 = xpos[e + 2], y3 = xpos[e + 3];
+            uint32_t d0 = D[size_t(y0) * TX + x], d1 = D[size_t(y1) * TX + x];
+            uint32_t d2 = D[size_t(y2) * TX + x], d3 = D[size_t(y3) * TX + x];
+            acc = min(min(acc, min(sat_add(xval[e], d0), sat_add(xval[e + 1], d1))),
+                      min(sat_add(xval[e + 2], d2), sat_add(xval[e + 3], d3)));
         }
-        __syncthreads();
+        for (; e < e1; ++e) acc = min(acc, sat_add(xval[e], D[size_t(xpos[e]) * TX + x]));
+        if (acc != INF) atomicMin(&dcore[(x << lk) + j], acc);
     }
-    for (uint32_t i = threadIdx.x; i < (T << lk); i += blockDim.x) A.dcore[i] = s_lab[i];
 }
 
-// One core level: positions [vbeg, vend); S = 1 << ls sub-lanes per (vertex, lane).
-__global__ void __launch_bounds__(256)
-k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
+// Flags and isochrone edges of the table vertices (all their labels are final).
+// Flags and isochrone edges of the table vertices (all their labels are final).  S = 1 << ls
+// sub-lanes per (vertex, lane) split the entry list: the first pass over the entries finds
+// which sub-lanes can hold a straddling arc, the second emits them.
+__global__ void __launch_bounds__(256) k_top_finish(CoreArgs A, uint32_t TX, uint32_t ls) {
     const uint32_t lk = A.lk, K = 1u << lk, S = 1u << ls, lgs = lk + ls;
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t v = t >> lgs, j = t & (K - 1), sub = (t >> lk) & (S - 1);
+    bool act = v < TX;
+    uint32_t tau = A.taus[j];
+    uint32_t dv = act ? A.dcore[(v << lk) + j] : INF;
+    uint32_t beg = act ? A.down_off[v] : 0, end = act ? A.down_off[v + 1] : 0;
+    if (act && sub == 0) set_cell_flags(A.core_cell[v], A.core_ecc[v], dv, tau, j, K, A.fl_in, A.fl_out);
+    const uint2 *__restrict__ darc = A.down_arc;
+    const uint32_t *__restrict__ dc = A.dcore;
+    auto arc = [&](uint32_t e) { return darc[e]; };
+    auto lab = [&](uint32_t tl) { return dc[(tl << lk) + j]; };
+    bool any_in = false, any_out = false;
+    for (uint32_t e = beg + sub; e < end; e += S) {
+        uint2 a = arc(e);
+        if (a.x & FLAGS) { if (lab(a.x & TAIL_MASK) <= tau) any_in = true; else any_out = true; }
+    }
+    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
+}
+
+// One item of a core level: thread t of the level serves vertex vbeg + (t >> (lk + ls)),
+// lane t & (K - 1), sub-lane (t >> lk) & (S - 1).  All lanes of a wavefront must call it.
+__device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_t ls, uint32_t vbeg,
+                                          uint32_t vend) {
+    const uint32_t lk = A.lk, K = 1u << lk, S = 1u << ls, lgs = lk + ls;
     uint32_t v = vbeg + (t >> lgs);
     uint32_t j = t & (K - 1), sub = (t >> lk) & (S - 1);
     bool act = v < vend;
@@ -237,39 +261,96 @@ k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
     uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, any_in, any_out);
     if (act && sub == 0) {
         A.dcore[(v << lk) + j] = dv;
-        set_cell_flags(A.core_cell[v], A.core_ecc[v], dv, tau, j, A.flag_words, A.fl_in, A.fl_out);
+        set_cell_flags(A.core_cell[v], A.core_ecc[v], dv, tau, j, K, A.fl_in, A.fl_out);
     }
     extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
 }
 
-// Active cells of every lane; plain mode passes all_cells = 1.
+// Sub-lanes per vertex for a level: enough to cover its mean in-degree, at most 8, and the
+// group (K lanes x S sub-lanes) within one wavefront.
+__host__ __device__ __forceinline__ uint32_t level_ls(uint32_t vertices, uint32_t entries, uint32_t K) {
+    uint32_t deg = (entries + vertices - 1) / vertices;
+    uint32_t ls = 0;
+    while ((1u << ls) < deg && (K << (ls + 1)) <= 64u && ls < 3) ++ls;
+    return ls;
+}
+
+// One core level: positions [vbeg, vend).
+__global__ void __launch_bounds__(1024)
+k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
+    core_item(A, blockIdx.x * blockDim.x + threadIdx.x, ls, vbeg, vend);
+}
+
+// Active cells of a batch and, per cell, the lanes for which it is active (a 64-bit mask;
+// the flag rule of the cell-restricted sweep, or every real lane in plain mode, which passes
+// all_cells = 1; padding lanes have no source cell and are never active).  The lanes of a
+// cell are cut into work items of at most G = 1 << lg lanes: item c << 6 | q covers the
+// lanes of rank [qG, qG + G) in the mask.  A cell's items are consecutive in the list.
 __global__ void k_active_cells(const uint32_t *__restrict__ fl_in, const uint32_t *__restrict__ fl_out,
-                               uint32_t flag_words, const uint8_t *__restrict__ uncovered,
+                               uint32_t kpow2, const uint8_t *__restrict__ uncovered,
                                const uint32_t *__restrict__ cell_off, const uint32_t *__restrict__ src_cell,
-                               uint32_t k, uint32_t num_cells, uint32_t all_cells,
-                               uint32_t *__restrict__ list, uint32_t *__restrict__ list_len) {
+                               uint32_t k, uint32_t num_cells, uint32_t all_cells, uint32_t lg,
+                               uint64_t *__restrict__ cmask, uint32_t *__restrict__ list,
+                               uint32_t *__restrict__ items, uint32_t *__restrict__ counters) {
     uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = false;
+    uint64_t m = 0;
     if (c < num_cells && cell_off[c + 1] > cell_off[c]) {
-        if (all_cells) {
-            act = true;
-        } else {
-            uint32_t bit = 1u << (c & 31u);
-            for (uint32_t j = 0; j < k && !act; ++j) {
-                uint32_t w = j * flag_words + (c >> 5);
-                bool i_ = fl_in[w] & bit, o_ = fl_out[w] & bit;
-                act = (i_ && (o_ || uncovered[c])) || src_cell[j] == c;
+        const uint32_t bit = 1u << (c & 31u);
+        for (uint32_t j = 0; j < k; ++j) {
+            const uint32_t sc = src_cell[j];
+            bool act = false;
+            if (sc != NO_CELL) {
+                if (all_cells) {
+                    act = true;
+                } else {
+                    uint32_t w = (c >> 5) * kpow2 + j;
+                    bool i_ = fl_in[w] & bit, o_ = fl_out[w] & bit;
+                    act = (i_ && (o_ || uncovered[c])) || sc == c;
+                }
             }
+            if (act) m |= 1ull << j;
         }
     }
-    uint64_t mask = __ballot(act);
-    if (mask == 0) return;
-    uint32_t lane = __lane_id();
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if ((int)lane == leader) base = atomicAdd(list_len, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (act) list[base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = c;
+    const bool act = m != 0;
+    const uint32_t nch = act ? (uint32_t(__popcll(m)) + (1u << lg) - 1u) >> lg : 0u;
+    const uint64_t amask = __ballot(act);
+    if (amask == 0) return;
+    const uint32_t lane = __lane_id();
+    // inclusive scan of the item counts over the wavefront
+    uint32_t incl = nch;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    uint32_t lbase = 0, ibase = 0;
+    if (lane == 0) {
+        lbase = atomicAdd(counters + 1, (uint32_t)__popcll(amask));
+        ibase = atomicAdd(counters + 2, total);
+    }
+    lbase = __shfl(lbase, 0);
+    ibase = __shfl(ibase, 0);
+    if (act) {
+        cmask[c] = m;
+        list[lbase + (uint32_t)__popcll(amask & ((1ull << lane) - 1ull))] = c;
+        const uint32_t first = ibase + incl - nch;
+        for (uint32_t q = 0; q < nch; ++q) items[first + q] = (c << 6) | q;
+    }
+}
+
+// Position of the set bit of rank r (0-based) in m; r must be below popcount(m).
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t w = 32; w > 0; w >>= 1) {
+        const uint32_t lo = uint32_t(__popcll(m & ((1ull << w) - 1ull)));
+        if (r >= lo) {
+            r -= lo;
+            m >>= w;
+            pos += w;
+        }
+    }
+    return pos;
 }
 
 // Words of a cell blob: offsets (cnt + 1), level bounds (nl + 1), core refs, pad to even,
@@ -282,100 +363,182 @@ __host__ __device__ __forceinline__ uint32_t blob_words(uint32_t cnt, uint32_t n
 }
 
 struct CellArgs {
-    const uint32_t *list, *list_len, *cblob, *blob, *cell_off, *dcore, *uslot, *uval, *perm, *taus,
+    const uint32_t *items, *n_items, *cblob, *blob, *cell_off, *dcore, *uslot, *uval, *perm, *taus,
         *src_cell;
+    const uint64_t *cmask;
     const uint4 *cmeta;
     uint32_t *dist_out;
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk, lg;
+    uint32_t out_cap, lane_base, lk, lg, num_cells;
 };
 
-// One workgroup per (active cell, group of G = 1 << lg lanes).  STAGED: the blob is copied
-// to LDS; otherwise it is read from global memory (cells larger than the LDS budget).
-template <bool STAGED>
-__global__ void __launch_bounds__(256) k_cell_sweep(CellArgs A, uint32_t lab_offset_words) {
+constexpr uint32_t CELL_THREADS = 256;
+constexpr uint32_t CELL_BUF = 512;         // entries per LDS level buffer (two buffers)
+constexpr uint32_t CELL_REGS = CELL_BUF / CELL_THREADS;
+
+// LDS words of a cell workgroup: offsets and level bounds (padded to even), two level
+// buffers of CELL_BUF entries, labels (cnt + refs rows of G lanes).
+__host__ __device__ __forceinline__ uint32_t cell_lds_words(uint32_t cnt, uint32_t nl, uint32_t labels,
+                                                            uint32_t lg) {
+    return ((cnt + 1 + nl + 1 + 1u) & ~1u) + 4 * CELL_BUF + (labels << lg);
+}
+
+// One workgroup per work item (an active cell and up to G = 1 << lg of the lanes for which
+// it is active).  Items are dealt to block indices so that XCD x (block index = x mod 8)
+// takes the x-th eighth of the item list: the items of one cell, which are consecutive,
+// run on the same XCD and share its L2.  Offsets, level bounds and labels live in LDS; the
+// entries of level l+1 (contiguous in the blob) are loaded into registers while level l is
+// relaxed, then written to the other LDS buffer.  Isochrone edges are extracted right after
+// a vertex's label is final.  Slots of an item beyond its lane count repeat its first lane
+// and neither write distances nor emit edges.
+__global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
     extern __shared__ uint32_t smem[];
-    const uint32_t lk = A.lk, lg = A.lg, K = 1u << lk, G = 1u << lg, groups = K >> lg;
-    uint32_t item = blockIdx.x / groups;
-    uint32_t grp = blockIdx.x - item * groups;
-    if (item >= *A.list_len) return;
-    const uint32_t c = A.list[item];
+    const uint32_t lk = A.lk, lg = A.lg;
+    const uint32_t b = blockIdx.x;
+    const uint32_t total = *A.n_items;
+    const uint32_t rows = (total + 7u) >> 3;
+    if ((b >> 3) >= rows) return;
+    const uint32_t it = (b & 7u) * rows + (b >> 3);
+    if (it >= total) return;
+    const uint32_t code = A.items[it];
+    const uint32_t c = code >> 6, q = code & 63u;
+    const uint64_t lanes = A.cmask[c];
     const uint4 meta = A.cmeta[c];
-    const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z, ne = meta.w;
+    const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z;
     const uint32_t cb = A.cell_off[c];
-    const uint32_t words = blob_words(cnt, nl, nrefs, ne), head = blob_head_words(cnt, nl, nrefs);
     const uint32_t *gblob = A.blob + A.cblob[c];
-    const uint32_t *blob;
-    if (STAGED) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(gblob);
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        for (uint32_t i = threadIdx.x; i < (words >> 2); i += blockDim.x) dst[i] = src[i];
-        blob = smem;
-    } else {
-        blob = gblob;
-    }
-    uint32_t *lab = smem + lab_offset_words;      // (cnt + nrefs) rows of G labels
-    const uint32_t *off = blob, *lvl = blob + cnt + 1, *refs = lvl + nl + 1;
-    const uint2 *ent = reinterpret_cast<const uint2 *>(blob + head);
-    const uint32_t j = threadIdx.x & (G - 1);     // lane within the group
-    const uint32_t jj = (grp << lg) + j;          // lane within the batch
+    const uint32_t *grefs = gblob + cnt + 1 + nl + 1;
+    const uint2 *gent = reinterpret_cast<const uint2 *>(gblob + blob_head_words(cnt, nl, nrefs));
+    uint32_t *s_off = smem;                                   // cnt + 1
+    uint32_t *s_lvl = smem + cnt + 1;                         // nl + 1
+    uint2 *s_buf = reinterpret_cast<uint2 *>(smem + ((cnt + 1 + nl + 1 + 1u) & ~1u));   // 2 * CELL_BUF
+    uint32_t *s_lab = reinterpret_cast<uint32_t *>(s_buf + 2 * CELL_BUF);               // (cnt + nrefs) * G
+    const uint32_t tid = threadIdx.x;
+    const uint32_t G = 1u << lg;
+    const uint32_t j = tid & (G - 1);             // slot within the item
+    const uint32_t rank = (q << lg) + j;
+    const bool live = rank < uint32_t(__popcll(lanes));
+    const uint32_t jj = nth_set_bit(lanes, live ? rank : (q << lg));   // lane within the batch
     const uint32_t tau = A.taus[jj];
-    bool has_up = false;
-    for (uint32_t q = 0; q < G; ++q) has_up |= A.src_cell[(grp << lg) + q] == c;
-    const uint32_t per_iter = blockDim.x >> lg;
-    if (STAGED) __syncthreads();
-    // labels: internal vertices start at INF (upward labels only in a source's cell),
-    // referenced core vertices take their final core labels
-    for (uint32_t i = threadIdx.x >> lg; i < cnt + nrefs; i += per_iter) {
-        uint32_t val = INF;
-        if (i < cnt) {
-            if (has_up) {
-                uint32_t s = A.uslot[cb + i];
-                if (s != NO_SLOT) val = A.uval[(s << lk) + jj];
-            }
-        } else {
-            val = A.dcore[(refs[i - cnt] << lk) + jj];
+    const bool has_up = A.src_cell[jj] == c;
+    const uint32_t per_iter = CELL_THREADS >> lg;
+    // touch the whole blob once (16-byte loads, all independent) so that the per-level
+    // loads below hit the L2 instead of HBM; the xor keeps the loads alive
+    uint32_t warm = 0;
+    {
+        const uint32_t words = blob_words(cnt, nl, nrefs, meta.w);
+        const uint4 *g4 = reinterpret_cast<const uint4 *>(gblob);
+        for (uint32_t i = tid; i < (words >> 2); i += CELL_THREADS) {
+            uint4 v = g4[i];
+            warm ^= v.x ^ v.w;
         }
-        lab[(i << lg) + j] = val;
+    }
+    for (uint32_t i = tid; i < cnt + 1 + nl + 1; i += CELL_THREADS) s_off[i] = gblob[i];
+    // labels: internal vertices start at INF (upward labels only in a source's cell) ...
+    for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
+        uint32_t val = INF;
+        if (has_up) {
+            uint32_t s = A.uslot[cb + i];
+            if (s != NO_SLOT) val = A.uval[(s << lk) + jj];
+        }
+        s_lab[(i << lg) + j] = val;
+    }
+    // ... referenced core vertices take their final core labels (loads issued four at a time)
+    for (uint32_t r0 = tid >> lg; r0 < nrefs; r0 += 4 * per_iter) {
+        uint32_t rr[4], vv[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            uint32_t r = r0 + u * per_iter;
+            rr[u] = r < nrefs ? grefs[r] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            uint32_t r = r0 + u * per_iter;
+            vv[u] = r < nrefs ? A.dcore[(rr[u] << lk) + jj] : INF;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            uint32_t r = r0 + u * per_iter;
+            if (r < nrefs) s_lab[((cnt + r) << lg) + j] = vv[u];
+        }
+    }
+    asm volatile("" ::"v"(warm));   // consumes `warm` (no instruction is emitted)
+    __syncthreads();
+    // entries of level 0 into buffer 0
+    uint2 r[CELL_REGS];
+    {
+        uint32_t eb = s_off[s_lvl[0]], n = min(s_off[s_lvl[1]] - eb, CELL_BUF);
+#pragma unroll
+        for (uint32_t k = 0; k < CELL_REGS; ++k) {
+            uint32_t idx = tid + k * CELL_THREADS;
+            if (idx < n) s_buf[idx] = gent[eb + idx];
+        }
     }
     __syncthreads();
     for (uint32_t l = 0; l < nl; ++l) {
-        uint32_t a = lvl[l], b = lvl[l + 1];
-        for (uint32_t i = a + (threadIdx.x >> lg); i < b; i += per_iter) {
-            uint32_t dv = lab[(i << lg) + j];
-            for (uint32_t e = off[i]; e < off[i + 1]; ++e) {
-                uint2 x = ent[e];
-                dv = min(dv, sat_add(lab[((x.x & LOCAL_MASK) << lg) + j], x.y));
+        const uint2 *cur = s_buf + (l & 1) * CELL_BUF;
+        uint2 *nxt = s_buf + ((l + 1) & 1) * CELL_BUF;
+        const uint32_t a = s_lvl[l], bnd = s_lvl[l + 1];
+        const uint32_t ebase = s_off[a];
+        // prefetch the next level's entries into registers
+        uint32_t n1 = 0, eb1 = 0;
+        if (l + 1 < nl) {
+            eb1 = s_off[bnd];
+            n1 = min(s_off[s_lvl[l + 2]] - eb1, CELL_BUF);
+#pragma unroll
+            for (uint32_t k = 0; k < CELL_REGS; ++k) {
+                uint32_t idx = tid + k * CELL_THREADS;
+                if (idx < n1) r[k] = gent[eb1 + idx];
             }
-            lab[(i << lg) + j] = dv;
+        }
+        for (uint32_t base = a; base < bnd; base += per_iter) {
+            uint32_t i = base + (tid >> lg);
+            bool act = i < bnd;
+            uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
+            uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
+            bool any_in = false, any_out = false;
+            for (uint32_t e = e0; e < e1; ++e) {
+                uint32_t le = e - ebase;
+                uint2 x = le < CELL_BUF ? cur[le] : gent[e];
+                uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
+                dv = min(dv, sat_add(lt, x.y));
+                if (x.x & FLAGS) { if (lt <= tau) any_in = true; else any_out = true; }
+            }
+            if (act) {
+                s_lab[(i << lg) + j] = dv;
+                if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
+            }
+            // isochrone edges at vertex i: its tails are on earlier levels or in the core
+            bool vin = dv <= tau;
+            bool need = act && live && (vin ? any_out : any_in);
+            uint32_t e = need ? e0 : 0, ee = need ? e1 : 0;
+            uint32_t ov = need ? A.perm[cb + i] : 0u;
+            while (__any(e < ee)) {
+                bool have = e < ee;
+                uint2 x = make_uint2(0u, 0u);
+                if (have) {
+                    uint32_t le = e - ebase;
+                    x = le < CELL_BUF ? cur[le] : gent[e];
+                }
+                uint32_t lt = x.x & LOCAL_MASK;
+                bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
+                uint32_t ot = st ? A.perm[lt < cnt ? cb + lt : grefs[lt - cnt]] : 0u;
+                emit_wave(st && (x.x & FLAG_FWD), edge_key(A.lane_base + jj, ot, ov), A.out_keys, A.out_count,
+                          A.out_cap);
+                emit_wave(st && (x.x & FLAG_REV), edge_key(A.lane_base + jj, ov, ot), A.out_keys, A.out_count,
+                          A.out_cap);
+                ++e;
+            }
+        }
+        if (l + 1 < nl) {
+#pragma unroll
+            for (uint32_t k = 0; k < CELL_REGS; ++k) {
+                uint32_t idx = tid + k * CELL_THREADS;
+                if (idx < n1) nxt[idx] = r[k];
+            }
         }
         __syncthreads();
-    }
-    // isochrone edges inside the cell; the loop bound is uniform per workgroup
-    for (uint32_t base = 0; base < cnt; base += per_iter) {
-        uint32_t i = base + (threadIdx.x >> lg);
-        bool act = i < cnt;
-        uint32_t dv = act ? lab[(i << lg) + j] : INF;
-        if (act && A.dist_out) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
-        bool vin = dv <= tau;
-        uint32_t e = act ? off[i] : 0, ee = act ? off[i + 1] : 0;
-        uint32_t ov = 0;
-        bool ov_loaded = false;
-        while (__any(e < ee)) {
-            bool have = e < ee;
-            uint2 x = have ? ent[e] : make_uint2(0u, 0u);
-            uint32_t lt = x.x & LOCAL_MASK;
-            bool st = have && (x.x & FLAGS) && ((lab[(lt << lg) + j] <= tau) != vin);
-            uint32_t ot = 0;
-            if (st) {
-                if (!ov_loaded) { ov = A.perm[cb + i]; ov_loaded = true; }
-                ot = A.perm[lt < cnt ? cb + lt : refs[lt - cnt]];
-            }
-            emit_wave(st && (x.x & FLAG_FWD), edge_key(A.lane_base + jj, ot, ov), A.out_keys, A.out_count, A.out_cap);
-            emit_wave(st && (x.x & FLAG_REV), edge_key(A.lane_base + jj, ov, ot), A.out_keys, A.out_count, A.out_cap);
-            ++e;
-        }
     }
 }
 
@@ -412,7 +575,6 @@ static int dev_alloc_copy(T **dst, const std::vector<T> &src, uint64_t &bytes) {
 int DevGraph::upload(const iso::Prep &P, int device_) {
     device = device_;
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     n = P.n;
     n_core = P.n_core;
     num_cells = P.num_cells;
@@ -429,13 +591,72 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_perm, P.perm, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_cell, P.core_cell, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_ecc, P.core_ecc, bytes))) return r;
-    if ((r = dev_alloc_copy(&d_top_lvl, P.core_lvl, bytes))) return r;
+    // table of downward distances inside the top levels X = [0, TX), TX <= TABLE_MAX
+    TX = 0;
+    nlev_table = 0;
+    for (size_t l = 0; l + 1 < P.core_lvl.size() && P.core_lvl[l + 1] <= TABLE_MAX; ++l) {
+        TX = P.core_lvl[l + 1];
+        nlev_table = uint32_t(l + 1);
+    }
+    if (TX > 0) {
+        // F[y][x] = shortest path y -> x using only vertices of X and the hierarchy's arcs
+        // among them (upward arcs and downward entries).  Every upward path that enters X stays
+        // in X, and so does every downward path into a vertex of X, so with these distances
+        // the host's upward search can stop at the first vertices of X it reaches.
+        std::vector<uint32_t> xoff(TX + 1, 0), xhead, xw;
+        {
+            std::vector<std::vector<std::pair<uint32_t, uint32_t>>> adj(TX);
+            for (uint32_t x = 0; x < TX; ++x) {
+                for (uint32_t e = P.down_off[x]; e < P.down_off[x + 1]; ++e) {
+                    uint32_t t2 = P.down_arc[2 * uint64_t(e)] & TAIL_MASK, w = P.down_arc[2 * uint64_t(e) + 1];
+                    if (w != INF) adj[t2].push_back({x, w});
+                }
+                for (uint32_t e = P.up_off[x]; e < P.up_off[x + 1]; ++e) adj[x].push_back({P.up_head[e], P.up_w[e]});
+            }
+            for (uint32_t x = 0; x < TX; ++x) {
+                xoff[x + 1] = xoff[x] + uint32_t(adj[x].size());
+                for (auto &a : adj[x]) { xhead.push_back(a.first); xw.push_back(a.second); }
+            }
+        }
+        std::vector<uint32_t> D(size_t(TX) * TX, INF);
+        int T = iso::resolve_threads(0);
+        std::vector<std::thread> pool;
+        std::atomic<uint32_t> next{0};
+        for (int t = 0; t < T; ++t)
+            pool.emplace_back([&]() {
+                std::vector<std::pair<uint32_t, uint32_t>> heap;
+                auto cmp = [](const std::pair<uint32_t, uint32_t> &a, const std::pair<uint32_t, uint32_t> &b) {
+                    return a.first > b.first;
+                };
+                for (;;) {
+                    uint32_t y = next.fetch_add(1);
+                    if (y >= TX) break;
+                    uint32_t *row = D.data() + size_t(y) * TX;
+                    row[y] = 0;
+                    heap.assign(1, {0u, y});
+                    while (!heap.empty()) {
+                        std::pop_heap(heap.begin(), heap.end(), cmp);
+                        auto [k, u] = heap.back();
+                        heap.pop_back();
+                        if (k != row[u]) continue;
+                        for (uint32_t e = xoff[u]; e < xoff[u + 1]; ++e) {
+                            uint32_t nd = iso::sat_add(k, xw[e]);
+                            if (nd < row[xhead[e]]) {
+                                row[xhead[e]] = nd;
+                                heap.push_back({nd, xhead[e]});
+                                std::push_heap(heap.begin(), heap.end(), cmp);
+                            }
+                        }
+                    }
+                }
+            });
+        for (auto &th : pool) th.join();
+        if ((r = dev_alloc_copy(&d_table, D, bytes))) return r;
+    }
     std::vector<uint32_t> co = P.cell_off;
     if (co.empty()) co.assign(1, n);
     if ((r = dev_alloc_copy(&d_cell_off, co, bytes))) return r;
     if ((r = dev_alloc_copy(&d_uncovered, P.uncovered, bytes))) return r;
-    std::vector<uint32_t> slots(n, NO_SLOT);
-    if ((r = dev_alloc_copy(&d_uslot, slots, bytes))) return r;
     core_entries = P.down_off[n_core];
 
     // cell blobs: local entry offsets, local level bounds, sorted distinct core tails, and
@@ -479,6 +700,7 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
         }
         max_blob_words = std::max(max_blob_words, cell_words[c]);
         max_cell_labels = std::max(max_cell_labels, cnt + nr);
+        max_cell_cnt = std::max(max_cell_cnt, cnt);
     }
     std::vector<uint32_t> blob(std::max<uint64_t>(4, total_words), 0);
     for (uint32_t c = 0; c < num_cells; ++c) {
@@ -506,32 +728,51 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_blob, blob, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cblob, cblob, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cmeta, cmeta, bytes))) return r;
+    max_cell_levels = 0;
+    for (uint32_t c = 0; c < num_cells; ++c) max_cell_levels = std::max(max_cell_levels, uint32_t(cmeta[c].y));
+    HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(LDS_MAX)));
+    return main.create(device);
+}
+
+int SweepCtx::create(int device_) {
+    device = device_;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
     for (auto &e : prof.ev) HIPCHK(hipEventCreate(&e));
-    HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(LDS_MAX)));
-    HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(LDS_MAX)));
-    HIPCHK(hipFuncSetAttribute((const void *)k_core_top, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               int(LDS_MAX)));
     return 0;
+}
+
+void SweepCtx::release() {
+    if (device < 0) return;
+    hipSetDevice(device);
+    if (stream) hipStreamSynchronize(stream);
+    bufs.release();
+    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    xcap = 0;
+    for (auto &e : prof.ev) if (e) hipEventDestroy(e);
+    if (done) hipEventDestroy(done);
+    if (stream) hipStreamDestroy(stream);
+    stream = nullptr;
+    done = nullptr;
+    device = -1;
 }
 
 void DevGraph::release() {
     if (device < 0) return;
+    main.release();
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
-                    d_uslot, d_top_lvl, d_blob, d_cblob, d_cmeta};
+                    d_table, d_blob, d_cblob, d_cmeta};
     for (void *p : ptrs) if (p) hipFree(p);
-    bufs.release();
-    for (auto &e : prof.ev) if (e) hipEventDestroy(e);
-    if (stream) hipStreamDestroy(stream);
-    stream = nullptr;
     device = -1;
 }
 
 void QueryBufs::release() {
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
-                    d_keys_sorted, d_sort_tmp, d_dist};
+                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot};
     for (void *p : ptrs) if (p) hipFree(p);
     if (h_pinned) hipHostFree(h_pinned);
     *this = QueryBufs();
@@ -552,28 +793,74 @@ static int ensure(void **p, size_t &have, size_t need) {
     return 0;
 }
 
-int DevGraph::run(const RunArgs &A, RunResult &R) {
+size_t DevGraph::ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const {
+    uint32_t K = 1;
+    while (K < k) K <<= 1;
+    size_t flag_words = std::max<uint32_t>(1, (num_cells + 31) / 32);
+    return size_t(n_core) * K * 4 + size_t(n) * 4 + upward_entries * (K + 3) * 4 + 2 * flag_words * K * 4 +
+           size_t(num_cells) * 4 + 2 * cap * 8 + (1 << 20);
+}
+
+int DevGraph::run(SweepCtx &C, const RunArgs &A, RunResult &R) {
+    int r = launch(C, A);
+    if (r) return r;
+    return finish(C, R);
+}
+
+int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     HIPCHK(hipSetDevice(device));
     const uint32_t K = A.k_pow2, lk = ilog2(K);
-    const uint32_t nu = uint32_t(A.upos.size());
+    // upward entries inside the table go to per-lane lists (entries arrive grouped by lane,
+    // ascending position within a lane); the others go to the slot table
+    std::vector<uint32_t> xptr(K + 1, 0), xpos, xval, spos, slane, sval;
+    xpos.reserve(A.upos.size());
+    xval.reserve(A.upos.size());
+    for (size_t i = 0; i < A.upos.size(); ++i) {
+        if (A.upos[i] < TX) {
+            xptr[A.ulane[i] + 1]++;
+            xpos.push_back(A.upos[i]);
+            xval.push_back(A.uval[i]);
+        } else {
+            spos.push_back(A.upos[i]);
+            slane.push_back(A.ulane[i]);
+            sval.push_back(A.uval[i]);
+        }
+    }
+    for (uint32_t j = 0; j < K; ++j) xptr[j + 1] += xptr[j];
+    const uint32_t nu = uint32_t(spos.size()), nx = uint32_t(xpos.size());
     const uint32_t flag_words = std::max<uint32_t>(1, (num_cells + 31) / 32);
-    QueryBufs &B = bufs;
+    QueryBufs &B = C.bufs;
+    hipStream_t s = C.stream;
     int r;
+    if (!B.d_uslot) {
+        if ((r = ensure((void **)&B.d_uslot, B.sz_uslot, size_t(n) * 4))) return r;
+        k_fill<<<dim3(2048), dim3(256), 0, s>>>(B.d_uslot, NO_SLOT, uint64_t(n));
+    }
     size_t core_words = std::max<size_t>(1, size_t(n_core) * K);
     if ((r = ensure((void **)&B.d_dcore, B.sz_dcore, core_words * 4))) return r;
-    if ((r = ensure((void **)&B.d_uval, B.sz_uval, size_t(std::max(1u, nu)) * K * 4))) return r;
+    if ((r = ensure((void **)&B.d_uval, B.sz_uval, size_t(std::max(8192u, nu)) * K * 4))) return r;
     if ((r = ensure((void **)&B.d_uin, B.sz_uin, size_t(std::max(1u, nu)) * 3 * 4))) return r;
+    // table lists: ptr (K + 1) | positions (xcap) | labels (xcap), capacity kept across calls so
+    // that the pointers in a captured graph stay valid
+    if (C.xcap < nx || B.sz_xin < (size_t(K) + 1 + 2 * size_t(C.xcap)) * 4) {
+        C.xcap = std::max<uint32_t>(std::max<uint32_t>(nx + nx / 2, 1024u * K), C.xcap);
+        if ((r = ensure((void **)&B.d_xin, B.sz_xin, (size_t(K) + 1 + 2 * size_t(C.xcap)) * 4))) return r;
+    }
+    const uint32_t xcap = C.xcap;
     if ((r = ensure((void **)&B.d_taus, B.sz_taus, 2 * K * 4))) return r;
     if ((r = ensure((void **)&B.d_flags, B.sz_flags, size_t(2) * flag_words * K * 4))) return r;
-    if ((r = ensure((void **)&B.d_list, B.sz_list, size_t(std::max(1u, num_cells)) * 4))) return r;
+    if ((r = ensure((void **)&B.d_list, B.sz_list, size_t(std::max(1u, num_cells)) * (3 + MAX_LANES) * 4)))
+        return r;
     if ((r = ensure((void **)&B.d_counters, B.sz_counters, 64))) return r;
     size_t cap = A.out_cap;
     if ((r = ensure((void **)&B.d_keys, B.sz_keys, cap * 8))) return r;
     if ((r = ensure((void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8))) return r;
     if (A.want_dist && (r = ensure((void **)&B.d_dist, B.sz_dist, size_t(n) * K * 4))) return r;
-    // per-call host inputs staged in one pinned buffer: taus, source cells, upward entries
-    size_t stage = (2 * size_t(K) + 3 * size_t(nu)) * 4;
+    // per-call host inputs staged in one pinned buffer: counters back, taus, source cells,
+    // upward entries
+    size_t stage = (16 + 2 * size_t(K) + 3 * size_t(nu) + (K + 1) + 2 * size_t(nx)) * 4;
     if (stage > B.sz_pinned) {
+        HIPCHK(hipStreamSynchronize(s));
         if (B.h_pinned) hipHostFree(B.h_pinned);
         B.h_pinned = nullptr;
         size_t b = std::max<size_t>(stage * 2, 1 << 16);
@@ -581,16 +868,25 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
         B.sz_pinned = b;
     }
     uint32_t *hp = (uint32_t *)B.h_pinned;
-    std::copy(A.taus.begin(), A.taus.end(), hp);
-    std::copy(A.src_cell.begin(), A.src_cell.end(), hp + K);
-    uint32_t *hu = hp + 2 * K;
-    std::copy(A.upos.begin(), A.upos.end(), hu);
-    std::copy(A.ulane.begin(), A.ulane.end(), hu + nu);
-    std::copy(A.uval.begin(), A.uval.end(), hu + 2 * size_t(nu));
-    hipStream_t s = stream;
+    C.h_counters = hp;
+    hp[0] = hp[1] = hp[2] = hp[3] = 0;
+    uint32_t *hin = hp + 16;
+    std::copy(A.taus.begin(), A.taus.end(), hin);
+    std::copy(A.src_cell.begin(), A.src_cell.end(), hin + K);
+    uint32_t *hu = hin + 2 * K;
+    std::copy(spos.begin(), spos.end(), hu);
+    std::copy(slane.begin(), slane.end(), hu + nu);
+    std::copy(sval.begin(), sval.end(), hu + 2 * size_t(nu));
+    uint32_t *hx = hu + 3 * size_t(nu);
+    std::copy(xptr.begin(), xptr.end(), hx);
+    std::copy(xpos.begin(), xpos.end(), hx + K + 1);
+    std::copy(xval.begin(), xval.end(), hx + K + 1 + nx);
     uint32_t *d_taus = B.d_taus, *d_src = B.d_taus + K;
-    HIPCHK(hipMemcpyAsync(d_taus, hp, 2 * K * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_taus, hin, 2 * K * 4, hipMemcpyHostToDevice, s));
     if (nu) HIPCHK(hipMemcpyAsync(B.d_uin, hu, size_t(nu) * 3 * 4, hipMemcpyHostToDevice, s));
+    const uint32_t *d_xptr = B.d_xin, *d_xpos = B.d_xin + K + 1, *d_xval = B.d_xin + K + 1 + xcap;
+    HIPCHK(hipMemcpyAsync(B.d_xin, hx, (size_t(K) + 1 + size_t(nx)) * 4, hipMemcpyHostToDevice, s));
+    if (nx) HIPCHK(hipMemcpyAsync((void *)d_xval, hx + K + 1 + nx, size_t(nx) * 4, hipMemcpyHostToDevice, s));
     const uint32_t *d_upos = B.d_uin, *d_ulane = B.d_uin + nu, *d_ulab = B.d_uin + 2 * size_t(nu);
     // clear flags and counters with fill kernels (no memset nodes, so the sequence can be captured)
     k_fill<<<dim3(64), dim3(256), 0, s>>>(B.d_flags, 0u, uint64_t(2) * flag_words * K);
@@ -600,94 +896,163 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
         uint32_t g = (nu + 255) / 256;
         k_fill<<<dim3(std::min<uint32_t>(1024, (nu * K + 255) / 256)), dim3(256), 0, s>>>(B.d_uval, INF,
                                                                                           uint64_t(nu) * K);
-        k_uset_claim<<<dim3(g), dim3(256), 0, s>>>(d_uslot, d_upos, nu);
-        k_uset_write<<<dim3(g), dim3(256), 0, s>>>(d_uslot, d_upos, d_ulane, d_ulab, B.d_uval, nu, lk);
+        k_uset_claim<<<dim3(g), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
+        k_uset_write<<<dim3(g), dim3(256), 0, s>>>(B.d_uslot, d_upos, d_ulane, d_ulab, B.d_uval, nu, lk);
     }
     uint32_t *fl_in = B.d_flags, *fl_out = B.d_flags + size_t(flag_words) * K;
-    uint32_t *out_count = B.d_counters, *list_len = B.d_counters + 1;
-    CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, d_uslot, B.d_uval, d_perm, d_core_cell, d_core_ecc,
+    // counters: edges emitted, active cells, work items; the list buffer holds the cells' lane
+    // masks, the active cells and the work items
+    uint32_t *out_count = B.d_counters, *n_items = B.d_counters + 2;
+    uint64_t *d_cmask = reinterpret_cast<uint64_t *>(B.d_list);
+    uint32_t *d_clist = B.d_list + 2 * size_t(num_cells), *d_items = d_clist + num_cells;
+    CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_perm, d_core_cell, d_core_ecc,
                 d_taus, fl_in, fl_out, flag_words, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk};
-    const bool prof_on = prof.on;
-    if (prof_on) HIPCHK(hipEventRecord(prof.ev[0], s));
-    // core sweep: the top levels in one LDS-resident workgroup, then one launch per level
+    const bool prof_on = C.prof.on;
+    // the device sweep (table, core levels, active cells, cell sweep) has only per-context
+    // kernel arguments; with use_graph it is captured once per signature and replayed
+    const bool use_graph = A.use_graph && !prof_on;
+    GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
+                 uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
+                                 uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
+                                 uint64_t(uintptr_t(B.d_keys)), uint64_t(uintptr_t(B.d_flags)),
+                                 uint64_t(uintptr_t(B.d_counters)), uint64_t(uintptr_t(B.d_list)),
+                                 uint64_t(uintptr_t(A.want_dist ? B.d_dist : nullptr)),
+                                 uint64_t(uintptr_t(B.d_taus))}};
+    bool replay = use_graph && C.graph_exec && std::memcmp(&sig, &C.sig, sizeof sig) == 0;
+    if (use_graph && !replay) {
+        if (C.graph_exec) hipGraphExecDestroy(C.graph_exec);
+        C.graph_exec = nullptr;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    }
+    if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[0], s));
+    // core sweep: the table levels as one (min,+) product, then one launch per level
     size_t nlev = core_lvl.size() - 1;
-    size_t top = 0;
-    while (top < nlev) {
-        size_t T = core_lvl[top + 1], ET = core_lvl_entries[top + 1];
-        size_t need = (2 * ET + (T + 1) + (T << lk)) * 4;
-        if (need > TOP_LDS_BUDGET) break;
-        // stop where levels become wide enough for a grid of workgroups
-        if (core_lvl[top + 1] - core_lvl[top] > 4096) break;
-        ++top;
-    }
-    if (top > 0) {
-        uint32_t T = core_lvl[top], ET = core_lvl_entries[top];
-        size_t lds = (2 * size_t(ET) + (T + 1) + (size_t(T) << lk)) * 4;
-        k_core_top<<<dim3(1), dim3(1024), lds, s>>>(CA, d_top_lvl, uint32_t(top), T, ET);
-    }
-    const uint32_t blk = 256;
-    for (size_t l = top; l < nlev; ++l) {
-        uint32_t vb = core_lvl[l], ve = core_lvl[l + 1];
-        uint32_t deg = (core_lvl_entries[l + 1] - core_lvl_entries[l] + (ve - vb) - 1) / (ve - vb);
-        uint32_t ls = 0;
-        while ((1u << ls) < deg && (K << (ls + 1)) <= 64u && (ls + 1) <= 3) ++ls;
-        uint64_t threads = uint64_t(ve - vb) << (lk + ls);
-        uint32_t grid = uint32_t((threads + blk - 1) / blk);
-        k_core_level<<<dim3(grid), dim3(blk), 0, s>>>(CA, ls, vb, ve);
-    }
-    if (prof_on) HIPCHK(hipEventRecord(prof.ev[1], s));
+    size_t top = nlev_table;
     uint32_t lg = 0;
-    if (num_cells > 0) {
-        k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(
-            fl_in, fl_out, flag_words, d_uncovered, d_cell_off, d_src, A.lanes, num_cells,
-            A.mode_plain ? 1u : 0u, B.d_list, list_len);
-        // lanes per workgroup: as many as fit the LDS budget next to the staged blob
-        size_t blob_bytes = size_t(max_blob_words) * 4;
-        bool staged = blob_bytes + size_t(max_cell_labels) * 4 <= LDS_MAX;
-        size_t fixed = staged ? blob_bytes : 0;
-        lg = lk;
-        while (lg > 0 && fixed + (size_t(max_cell_labels) << lg) * 4 > CELL_LDS_BUDGET) --lg;
-        size_t lds = fixed + (size_t(max_cell_labels) << lg) * 4;
-        if (lds > LDS_MAX) {
-            set_error("a cell does not fit the LDS of one workgroup");
-            return -2;
+    if (replay) {
+        lg = C.lg;
+        HIPCHK(hipGraphLaunch(C.graph_exec, s));
+    } else {
+        if (TX > 0) {
+            k_fill<<<dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (TX * K + 255) / 256))), dim3(256), 0, s>>>(
+                B.d_dcore, INF, uint64_t(TX) * K);
+            uint32_t tiles = (TX + 63) / 64;
+            // splits of each lane's upward list: enough wavefronts to cover the chip
+            uint32_t splits = std::max<uint32_t>(1, std::min<uint32_t>(64, 4096 / std::max<uint32_t>(1, tiles * K)));
+            k_top_table<<<dim3(tiles * K * splits), dim3(64), 0, s>>>(d_table, TX, d_xptr, d_xpos, d_xval, B.d_dcore,
+                                                                       lk, tiles, splits);
+            {
+                // sub-lanes per vertex from the mean entry count of the table vertices
+                uint32_t deg = (core_lvl_entries[nlev_table] + TX - 1) / TX;
+                uint32_t ls = 0;
+                while ((1u << ls) < deg && (K << (ls + 1)) <= 64u) ++ls;
+                k_top_finish<<<dim3(uint32_t(((uint64_t(TX) << (lk + ls)) + 255) / 256)), dim3(256), 0, s>>>(CA, TX, ls);
+            }
         }
-        uint32_t groups = K >> lg;
-        CellArgs LA{B.d_list, list_len, d_cblob, d_blob, d_cell_off, B.d_dcore, d_uslot, B.d_uval, d_perm,
-                    d_taus, d_src, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
-                    uint32_t(cap), A.lane_base, lk, lg};
-        if (prof_on) HIPCHK(hipEventRecord(prof.ev[2], s));
-        if (staged)
-            k_cell_sweep<true><<<dim3(num_cells * groups), dim3(256), lds, s>>>(LA, max_blob_words);
-        else
-            k_cell_sweep<false><<<dim3(num_cells * groups), dim3(256), lds, s>>>(LA, 0);
-    } else if (prof_on) {
-        HIPCHK(hipEventRecord(prof.ev[2], s));
+        const uint32_t blk = A.block;
+        for (size_t l = top; l < nlev; ++l) {
+            uint32_t vb = core_lvl[l], ve = core_lvl[l + 1];
+            uint32_t ls = level_ls(ve - vb, core_lvl_entries[l + 1] - core_lvl_entries[l], K);
+            uint64_t threads = uint64_t(ve - vb) << (lk + ls);
+            uint32_t grid = uint32_t((threads + blk - 1) / blk);
+            k_core_level<<<dim3(grid), dim3(blk), 0, s>>>(CA, ls, vb, ve);
+        }
+        if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
+        if (num_cells > 0) {
+            // lanes per work item: as many as fit the LDS budget
+            lg = lk;
+            while (lg > 0 && size_t(cell_lds_words(max_cell_cnt, max_cell_levels, max_cell_labels, lg)) * 4 >
+                                 A.cell_lds_bytes)
+                --lg;
+            size_t lds = size_t(cell_lds_words(max_cell_cnt, max_cell_levels, max_cell_labels, lg)) * 4;
+            if (lds > LDS_MAX) {
+                if (use_graph) {
+                    hipGraph_t gdrop = nullptr;
+                    hipStreamEndCapture(s, &gdrop);
+                    if (gdrop) hipGraphDestroy(gdrop);
+                }
+                set_error("a cell does not fit the LDS of one workgroup");
+                return -2;
+            }
+            k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(
+                fl_in, fl_out, K, d_uncovered, d_cell_off, d_src, K, num_cells, A.mode_plain ? 1u : 0u, lg,
+                d_cmask, d_clist, d_items, B.d_counters);
+            const uint32_t groups = K >> lg;
+            CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
+                        d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
+                        uint32_t(cap), A.lane_base, lk, lg, num_cells};
+            if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
+            // enough blocks for every lane of every cell in items of G lanes (the others exit)
+            uint32_t grid = ((num_cells * groups + 7) / 8) * 8;
+            k_cell_sweep<<<dim3(grid), dim3(CELL_THREADS), lds, s>>>(LA);
+        } else if (prof_on) {
+            HIPCHK(hipEventRecord(C.prof.ev[2], s));
+        }
     }
-    if (prof_on) HIPCHK(hipEventRecord(prof.ev[3], s));
+    if (use_graph && !replay) {
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamEndCapture(s, &graph));
+        hipError_t ie = hipGraphInstantiate(&C.graph_exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            C.graph_exec = nullptr;
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            return -3;
+        }
+        C.sig = sig;
+        HIPCHK(hipGraphLaunch(C.graph_exec, s));
+    }
+    if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[3], s));
     HIPCHK(hipGetLastError());
-    if (nu) k_uset_clear<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(d_uslot, d_upos, nu);
-    uint32_t counters[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(counters, B.d_counters, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    R.count = counters[0];
-    R.active_cells = A.mode_plain ? 0 : counters[1];
-    R.overflow = counters[0] > cap;
-    if (A.want_dist) {
+    if (nu) k_uset_clear<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
+    HIPCHK(hipMemcpyAsync(C.h_counters, B.d_counters, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(C.done, s));
+    C.pending = true;
+    C.K = K;
+    C.lk = lk;
+    C.lg = lg;
+    C.lanes = A.lanes;
+    C.lane_base = A.lane_base;
+    C.cap = cap;
+    C.mode_plain = A.mode_plain;
+    C.want_dist = A.want_dist;
+    C.nlev = uint32_t(nlev);
+    C.top = uint32_t(top);
+    return 0;
+}
+
+int DevGraph::finish(SweepCtx &C, RunResult &R) {
+    if (!C.pending) {
+        set_error("finish without a launched sweep");
+        return -7;
+    }
+    C.pending = false;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipEventSynchronize(C.done));
+    QueryBufs &B = C.bufs;
+    hipStream_t s = C.stream;
+    const uint32_t K = C.K;
+    const uint32_t cnt_all = C.h_counters[0], n_active = C.h_counters[1];
+    R.count = cnt_all;
+    R.active_cells = C.mode_plain ? 0 : n_active;
+    R.overflow = cnt_all > C.cap;
+    if (C.want_dist) {
         R.dcore.resize(size_t(n_core) * K);
         R.dist.resize(size_t(n) * K);
         HIPCHK(hipMemcpy(R.dcore.data(), B.d_dcore, R.dcore.size() * 4, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(R.dist.data(), B.d_dist, R.dist.size() * 4, hipMemcpyDeviceToHost));
-        R.active_list.resize(A.mode_plain ? 0 : counters[1]);
+        R.active_list.resize(C.mode_plain ? 0 : n_active);
         if (!R.active_list.empty())
-            HIPCHK(hipMemcpy(R.active_list.data(), B.d_list, R.active_list.size() * 4, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(R.active_list.data(), B.d_list + 2 * size_t(num_cells), R.active_list.size() * 4,
+                             hipMemcpyDeviceToHost));
     }
-    if (prof_on) {
+    Profile &prof = C.prof;
+    if (prof.on) {
         float ms = 0;
         prof.calls++;
         HIPCHK(hipEventElapsedTime(&ms, prof.ev[0], prof.ev[1]));
         prof.core_ms += ms;
-        prof.core_launches += (top > 0 ? 1 : 0) + (nlev - top);
+        prof.core_launches += (TX > 0 ? 3 : 0) + (C.nlev - C.top);
         prof.core_entries += core_entries;
         // offsets + entries + cell ids and eccentricities + k labels written and read back once
         prof.core_bytes += 4ull * (n_core + 1) + 8ull * core_entries + 8ull * n_core + uint64_t(K) * 8ull * n_core;
@@ -697,42 +1062,43 @@ int DevGraph::run(const RunArgs &A, RunResult &R) {
             HIPCHK(hipEventElapsedTime(&ms, prof.ev[2], prof.ev[3]));
             prof.cell_ms += ms;
             prof.cell_launches++;
-            std::vector<uint32_t> lst;
-            if (A.mode_plain) {
-                for (uint32_t c = 0; c < num_cells; ++c) if (cell_cnt[c]) lst.push_back(c);
-            } else {
-                lst.resize(counters[1]);
-                if (!lst.empty())
-                    HIPCHK(hipMemcpy(lst.data(), B.d_list, lst.size() * 4, hipMemcpyDeviceToHost));
+            std::vector<uint32_t> lst(n_active);
+            std::vector<uint64_t> masks(num_cells);
+            if (n_active) {
+                HIPCHK(hipMemcpy(lst.data(), B.d_list + 2 * size_t(num_cells), size_t(n_active) * 4,
+                                 hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(masks.data(), B.d_list, size_t(num_cells) * 8, hipMemcpyDeviceToHost));
             }
-            const uint64_t groups = K >> lg;
+            prof.cell_items += C.h_counters[2];
             for (uint32_t c : lst) {
+                const uint64_t lanes = uint64_t(__builtin_popcountll(masks[c]));
                 prof.cells_swept++;
+                prof.cell_lanes += lanes;
                 prof.cell_vertices += cell_cnt[c];
                 prof.cell_entries += cell_entries[c];
-                // each lane group streams the cell's blob once; each lane reads its core refs once
-                prof.cell_bytes += groups * 4ull * cell_words[c] + uint64_t(K) * 4ull * cell_core_refs[c];
+                // the cell's arcs streamed once; each lane reads each referenced core label once
+                prof.cell_bytes += 4ull * cell_words[c] + lanes * 4ull * cell_core_refs[c];
             }
         }
     }
-    if (R.overflow) return 0;   // caller grows the buffer and repeats
+    if (R.overflow) return 0;   // caller grows the buffer and launches again
     // sort keys: lane bits above 58, then tail, then head
-    uint32_t cnt = counters[0];
-    R.keys.resize(cnt);
-    if (cnt) {
-        int end_bit = 58 + int(ilog2(std::max<uint32_t>(1, A.lane_base + K)));
+    R.keys.resize(cnt_all);
+    if (cnt_all) {
+        int end_bit = 58 + int(ilog2(std::max<uint32_t>(1, C.lane_base + K)));
         if (end_bit > 64) end_bit = 64;
         size_t tmp = 0;
+        int r;
         HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
-                                                 int(cnt), 0, end_bit, s));
+                                                 int(cnt_all), 0, end_bit, s));
         if ((r = ensure((void **)&B.d_sort_tmp, B.sz_sort_tmp, tmp))) return r;
-        if (prof_on) HIPCHK(hipEventRecord(prof.ev[4], s));
+        if (prof.on) HIPCHK(hipEventRecord(prof.ev[4], s));
         HIPCHK(hipcub::DeviceRadixSort::SortKeys(B.d_sort_tmp, tmp, (const uint64_t *)B.d_keys,
-                                                 B.d_keys_sorted, int(cnt), 0, end_bit, s));
-        if (prof_on) HIPCHK(hipEventRecord(prof.ev[5], s));
-        HIPCHK(hipMemcpyAsync(R.keys.data(), B.d_keys_sorted, size_t(cnt) * 8, hipMemcpyDeviceToHost, s));
+                                                 B.d_keys_sorted, int(cnt_all), 0, end_bit, s));
+        if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
+        HIPCHK(hipMemcpyAsync(R.keys.data(), B.d_keys_sorted, size_t(cnt_all) * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (prof_on) {
+        if (prof.on) {
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, prof.ev[4], prof.ev[5]));
             prof.sort_ms += ms;

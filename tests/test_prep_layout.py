@@ -286,6 +286,10 @@ def test_abi_error_paths():
     with pytest.raises(iso.IsoError) as e:
         G.set_tuning(lanes_per_launch=65)
     assert e.value.code == iso.ISO_EINVAL
+    for bad in (dict(block=96), dict(cell_lds_kb=8), dict(use_graph=2), dict(core_mode=1)):
+        with pytest.raises(iso.IsoError) as e:
+            G.set_tuning(**bad)
+        assert e.value.code == iso.ISO_EINVAL, bad
 
 
 def test_parallel_arcs_and_self_loops_are_merged():
