@@ -184,6 +184,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="choose lanes per launch, block size and cell LDS budget on a query sample first")
     ap.add_argument("--tuning", default="", help="JSON file written by the autotuner to apply")
+    ap.add_argument("--save-tuning", default="", help="write the autotuner's result to this JSON file")
     ap.add_argument("--serve-rates", default="250,1000,2000,3000",
                     help="offered Poisson rates (queries/s) for the serving section; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -219,6 +220,8 @@ def main():
             ts, tt = autotune.sample(256, src, tau, seed=1)
             res = autotune.tune(G, ts, tt, log=log)
             best = res["best"]
+            if args.save_tuning:
+                autotune.save(res, args.save_tuning)
             tuning_note = "autotuned on 256 queries"
         lanes = best["lanes_per_launch"]
         log(f"tuning: {best} ({tuning_note})")
@@ -235,7 +238,9 @@ def main():
     prof = G.profile_read()
     G.profile_enable(False)
     qps = args.steps * lanes / total
+    batch_stats = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in G.last_stats().items()}
     log(f"cells batched: {qps:.1f} queries/s, {1000 * total / args.steps:.2f} ms/step; profile {prof}")
+    log(f"last batch: {batch_stats}")
 
     # plain sweep, same batches
     run_batches(G, src, tau, lanes, 1, iso.MODE_PLAIN)
@@ -305,6 +310,7 @@ def main():
         "latency_ms": lat,
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
+        "last_batch": batch_stats,
         "step_ms_p50": round(1000 * percentile(times, 50), 3),
         "step_ms_p99": round(1000 * percentile(times, 99), 3),
         "serving": serve,

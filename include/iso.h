@@ -167,6 +167,11 @@ typedef struct {
                                    into a hipGraph and replay it */
     uint32_t core_mode;         /* must be 0 (one launch per core level); other values are reserved and
                                    rejected with ISO_EINVAL */
+    uint32_t cell_stage;        /* 0 = a cell workgroup holds two levels' entries in LDS and loads the next
+                                   level while relaxing the current one; 1 = it copies the cell's whole
+                                   data into LDS first (needs the largest cell's data plus one lane's labels
+                                   to fit 160 KiB, else 0 is used); cell_lds_kb bounds the LDS either way,
+                                   raised to the minimum the variant needs */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);

@@ -1,5 +1,6 @@
 """Autotuner for the device sweep: queries per launch, core-kernel block size, LDS budget per
-cell workgroup (which sets the queries per cell work item), and hipGraph replay.
+cell workgroup (which sets the queries per cell work item), the cell-kernel variant (level
+pipeline or whole cell in LDS) and hipGraph replay.
 
 Coordinate search: starting from the defaults, each knob in turn is set to every candidate
 value while the others stay fixed; the best throughput (queries/s of iso_query_batch on a
@@ -17,12 +18,13 @@ import numpy as np
 from .binding import MODE_CELLS, Graph
 
 SPACE = {
+    "cell_stage": [0, 1],
     "lanes_per_launch": [8, 16, 32, 64],
     "block": [128, 256, 512],
     "cell_lds_kb": [24, 40, 64, 96],
     "use_graph": [0, 1],
 }
-DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 40, "use_graph": 0}
+DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 40, "use_graph": 0, "cell_stage": 0}
 
 
 def measure(G: Graph, sources, taus, mode=MODE_CELLS, repeats: int = 2) -> float:

@@ -48,6 +48,7 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     A.block = g->tuning.block;
     A.cell_lds_bytes = size_t(g->tuning.cell_lds_kb) * 1024;
     A.use_graph = g->tuning.use_graph;
+    A.cell_stage = g->tuning.cell_stage;
     A.lanes = lanes;
     A.k_pow2 = pow2_at_least(lanes);
     A.mode_plain = plain;
@@ -430,6 +431,7 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (t->block < 64 || t->block > 1024 || t->block % 64) return fail(ISO_EINVAL, "block must be a multiple of 64 in [64, 1024]");
     if (t->cell_lds_kb < 16 || t->cell_lds_kb > 160) return fail(ISO_EINVAL, "cell_lds_kb must be in [16, 160]");
     if (t->use_graph > 1) return fail(ISO_EINVAL, "use_graph must be 0 or 1");
+    if (t->cell_stage > 1) return fail(ISO_EINVAL, "cell_stage must be 0 or 1");
     if (t->core_mode != 0)
         return fail(ISO_EINVAL, "core_mode must be 0: the single-launch core sweep with a grid barrier "
                                 "is disabled");

@@ -132,20 +132,20 @@ __device__ __forceinline__ uint32_t relax_group(ARC arc, LAB lab, uint32_t beg, 
                                                 uint32_t S, uint32_t K, uint32_t init, uint32_t tau,
                                                 bool &any_in, bool &any_out) {
     uint32_t m = INF;
-    uint32_t e = beg + sub;
-    auto see = [&](uint2 a, uint32_t l) {
-        m = min(m, sat_add(l, a.y));
-        if (a.x & FLAGS) { if (l <= tau) any_in = true; else any_out = true; }
-    };
-    for (; e + 3 * S < end; e += 4 * S) {
-        uint2 a0 = arc(e), a1 = arc(e + S), a2 = arc(e + 2 * S), a3 = arc(e + 3 * S);
-        uint32_t l0 = lab(a0.x & TAIL_MASK), l1 = lab(a1.x & TAIL_MASK);
-        uint32_t l2 = lab(a2.x & TAIL_MASK), l3 = lab(a3.x & TAIL_MASK);
-        see(a0, l0); see(a1, l1); see(a2, l2); see(a3, l3);
-    }
-    for (; e < end; e += S) {
-        uint2 a0 = arc(e);
-        see(a0, lab(a0.x & TAIL_MASK));
+    // chunks of up to 8 entries: every entry load of a chunk is issued, then every label load,
+    // so a vertex of ordinary degree costs two memory latencies instead of two per entry
+    for (uint32_t e = beg + sub; e < end; e += 8 * S) {
+        uint2 a[8];
+        uint32_t l[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) a[u] = e + u * S < end ? arc(e + u * S) : make_uint2(0u, INF);
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) l[u] = e + u * S < end ? lab(a[u].x & TAIL_MASK) : INF;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+            m = min(m, sat_add(l[u], a[u].y));
+            if (a[u].x & FLAGS) { if (l[u] <= tau) any_in = true; else any_out = true; }
+        }
     }
     for (uint32_t o = K; o < K * S; o <<= 1) m = min(m, (uint32_t)__shfl_xor((int)m, (int)o));
     return min(init, m);
@@ -246,12 +246,16 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     uint32_t j = t & (K - 1), sub = (t >> lk) & (S - 1);
     bool act = v < vend;
     uint32_t tau = A.taus[j];
-    uint32_t init = INF, beg = 0, end = 0;
+    uint32_t init = INF, beg = 0, end = 0, cell = NO_CELL, ecc = 0;
     if (act) {
-        uint32_t s = A.uslot[v];
-        if (s != NO_SLOT) init = A.uval[(s << lk) + j];
         beg = A.down_off[v];
         end = A.down_off[v + 1];
+        uint32_t s = A.uslot[v];
+        if (sub == 0) {
+            cell = A.core_cell[v];
+            ecc = A.core_ecc[v];
+        }
+        if (s != NO_SLOT) init = A.uval[(s << lk) + j];
     }
     const uint2 *__restrict__ darc = A.down_arc;
     const uint32_t *__restrict__ dc = A.dcore;
@@ -261,7 +265,7 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, any_in, any_out);
     if (act && sub == 0) {
         A.dcore[(v << lk) + j] = dv;
-        set_cell_flags(A.core_cell[v], A.core_ecc[v], dv, tau, j, K, A.fl_in, A.fl_out);
+        set_cell_flags(cell, ecc, dv, tau, j, K, A.fl_in, A.fl_out);
     }
     extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
 }
@@ -374,6 +378,10 @@ struct CellArgs {
 };
 
 constexpr uint32_t CELL_THREADS = 256;
+// Isochrone edges found in a cell are first collected in LDS as candidate words (entry
+// index e < 2^25 within the cell, lane slot j, direction) and written out in bulk.
+constexpr uint32_t CAND_CAP = 512;
+constexpr uint32_t CAND_E_BITS = 25;
 constexpr uint32_t CELL_BUF = 512;         // entries per LDS level buffer (two buffers)
 constexpr uint32_t CELL_REGS = CELL_BUF / CELL_THREADS;
 
@@ -381,26 +389,79 @@ constexpr uint32_t CELL_REGS = CELL_BUF / CELL_THREADS;
 // buffers of CELL_BUF entries, labels (cnt + refs rows of G lanes).
 __host__ __device__ __forceinline__ uint32_t cell_lds_words(uint32_t cnt, uint32_t nl, uint32_t labels,
                                                             uint32_t lg) {
-    return ((cnt + 1 + nl + 1 + 1u) & ~1u) + 4 * CELL_BUF + (labels << lg);
+    return ((cnt + 1 + nl + 1 + 1u) & ~1u) + 4 * CELL_BUF + (labels << lg) + CAND_CAP + 4;
 }
 
-// One workgroup per work item (an active cell and up to G = 1 << lg of the lanes for which
-// it is active).  Items are dealt to block indices so that XCD x (block index = x mod 8)
-// takes the x-th eighth of the item list: the items of one cell, which are consecutive,
-// run on the same XCD and share its L2.  Offsets, level bounds and labels live in LDS; the
+// Output key of a candidate: the entry's head is the internal vertex whose entry range holds e
+// (binary search of the LDS offsets), its tail a local index (internal or core reference).
+template <class ENT, class REF>
+__device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, const uint32_t *s_off, uint32_t cnt,
+                                             ENT ent, REF ref, uint32_t cb, uint64_t lanes, uint32_t q) {
+    const uint32_t e = word & ((1u << CAND_E_BITS) - 1u), j = (word >> CAND_E_BITS) & 63u;
+    uint32_t lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint32_t lt = ent(e).x & LOCAL_MASK;
+    const uint32_t ov = A.perm[cb + lo];
+    const uint32_t ot = A.perm[lt < cnt ? cb + lt : ref(lt - cnt)];
+    const uint32_t lane = A.lane_base + nth_set_bit(lanes, (q << A.lg) + j);
+    return (word >> 31) ? edge_key(lane, ov, ot) : edge_key(lane, ot, ov);
+}
+
+// Wavefront-aggregated append of a candidate to the LDS list (count in ctl[0]); every lane of
+// the wavefront must call it.  A candidate beyond the list's capacity is written out at once.
+template <class ENT, class REF>
+__device__ __forceinline__ void push_cand(bool pred, uint32_t word, uint32_t *s_cand, uint32_t *s_ctl,
+                                          const CellArgs &A, const uint32_t *s_off, uint32_t cnt, ENT ent, REF ref,
+                                          uint32_t cb, uint64_t lanes, uint32_t q) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const uint32_t lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(&s_ctl[0], (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (k < CAND_CAP) {
+            s_cand[k] = word;
+        } else {
+            const uint64_t key = cand_key(A, word, s_off, cnt, ent, ref, cb, lanes, q);
+            const uint32_t idx = atomicAdd(A.out_count, 1u);
+            if (idx < A.out_cap) A.out_keys[idx] = key;
+        }
+    }
+}
+
+// Writes the first n listed candidates with one output reservation and empties the list.
+// Called by every thread with the same n, read from ctl[0] between two barriers.
+template <class ENT, class REF>
+__device__ __forceinline__ void flush_cands(uint32_t n, uint32_t *s_cand, uint32_t *s_ctl, const CellArgs &A,
+                                            const uint32_t *s_off, uint32_t cnt, ENT ent, REF ref, uint32_t cb,
+                                            uint64_t lanes, uint32_t q) {
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_ctl[1] = atomicAdd(A.out_count, n);
+    __syncthreads();
+    const uint32_t base = s_ctl[1];
+    for (uint32_t k = tid; k < n; k += CELL_THREADS) {
+        const uint64_t key = cand_key(A, s_cand[k], s_off, cnt, ent, ref, cb, lanes, q);
+        if (base + k < A.out_cap) A.out_keys[base + k] = key;
+    }
+    __syncthreads();
+    if (tid == 0) s_ctl[0] = 0;
+    __syncthreads();
+}
+
+// One work item (an active cell and up to G = 1 << lg of the lanes for which it is active)
+// on one workgroup, level pipeline variant.  Offsets, level bounds and labels live in LDS; the
 // entries of level l+1 (contiguous in the blob) are loaded into registers while level l is
 // relaxed, then written to the other LDS buffer.  Isochrone edges are extracted right after
 // a vertex's label is final.  Slots of an item beyond its lane count repeat its first lane
 // and neither write distances nor emit edges.
-__global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
-    extern __shared__ uint32_t smem[];
+__device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t *smem, uint32_t it) {
     const uint32_t lk = A.lk, lg = A.lg;
-    const uint32_t b = blockIdx.x;
-    const uint32_t total = *A.n_items;
-    const uint32_t rows = (total + 7u) >> 3;
-    if ((b >> 3) >= rows) return;
-    const uint32_t it = (b & 7u) * rows + (b >> 3);
-    if (it >= total) return;
     const uint32_t code = A.items[it];
     const uint32_t c = code >> 6, q = code & 63u;
     const uint64_t lanes = A.cmask[c];
@@ -414,6 +475,10 @@ __global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
     uint32_t *s_lvl = smem + cnt + 1;                         // nl + 1
     uint2 *s_buf = reinterpret_cast<uint2 *>(smem + ((cnt + 1 + nl + 1 + 1u) & ~1u));   // 2 * CELL_BUF
     uint32_t *s_lab = reinterpret_cast<uint32_t *>(s_buf + 2 * CELL_BUF);               // (cnt + nrefs) * G
+    uint32_t *s_cand = s_lab + ((cnt + nrefs) << lg);                                   // CAND_CAP
+    uint32_t *s_ctl = s_cand + CAND_CAP;                                                // count, base
+    auto ent = [&](uint32_t e) { return gent[e]; };
+    auto ref = [&](uint32_t r) { return grefs[r]; };
     const uint32_t tid = threadIdx.x;
     const uint32_t G = 1u << lg;
     const uint32_t j = tid & (G - 1);             // slot within the item
@@ -435,6 +500,7 @@ __global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
         }
     }
     for (uint32_t i = tid; i < cnt + 1 + nl + 1; i += CELL_THREADS) s_off[i] = gblob[i];
+    if (tid == 0) s_ctl[0] = 0;
     // labels: internal vertices start at INF (upward labels only in a source's cell) ...
     for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
         uint32_t val = INF;
@@ -509,11 +575,11 @@ __global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
                 s_lab[(i << lg) + j] = dv;
                 if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
             }
-            // isochrone edges at vertex i: its tails are on earlier levels or in the core
+            // isochrone edges at vertex i (its tails are on earlier levels or in the core) go to
+            // the candidate list
             bool vin = dv <= tau;
             bool need = act && live && (vin ? any_out : any_in);
             uint32_t e = need ? e0 : 0, ee = need ? e1 : 0;
-            uint32_t ov = need ? A.perm[cb + i] : 0u;
             while (__any(e < ee)) {
                 bool have = e < ee;
                 uint2 x = make_uint2(0u, 0u);
@@ -523,11 +589,10 @@ __global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
                 }
                 uint32_t lt = x.x & LOCAL_MASK;
                 bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
-                uint32_t ot = st ? A.perm[lt < cnt ? cb + lt : grefs[lt - cnt]] : 0u;
-                emit_wave(st && (x.x & FLAG_FWD), edge_key(A.lane_base + jj, ot, ov), A.out_keys, A.out_count,
-                          A.out_cap);
-                emit_wave(st && (x.x & FLAG_REV), edge_key(A.lane_base + jj, ov, ot), A.out_keys, A.out_count,
-                          A.out_cap);
+                const uint32_t word = e | (j << CAND_E_BITS);
+                push_cand(st && (x.x & FLAG_FWD), word, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+                push_cand(st && (x.x & FLAG_REV), word | (1u << 31), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb,
+                          lanes, q);
                 ++e;
             }
         }
@@ -539,6 +604,153 @@ __global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
             }
         }
         __syncthreads();
+        // write the candidates out when the list is half full, and after the last level
+        const uint32_t pend = s_ctl[0];
+        __syncthreads();
+        if (pend > (l + 1 < nl ? CAND_CAP / 2 : 0u))
+            flush_cands(min(pend, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+    }
+}
+
+// LDS words of the whole-cell variant: the blob itself, then the labels.
+__host__ __device__ __forceinline__ uint32_t staged_lds_words(uint32_t words, uint32_t labels, uint32_t lg) {
+    return words + (labels << lg) + CAND_CAP + 4;
+}
+
+// Same work item, results and extraction as cell_item_pipelined, but the whole blob (offsets, level
+// bounds, core refs, entries) is copied into LDS once, with every load of a chunk issued
+// before its stores, so that the level loop touches no global memory except where an
+// isochrone edge is written: each level costs LDS accesses and one barrier.  The copy keeps up
+// to eight 16-byte loads per thread in flight.
+__device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *smem, uint32_t it) {
+    const uint32_t lk = A.lk, lg = A.lg;
+    const uint32_t code = A.items[it];
+    const uint32_t c = code >> 6, q = code & 63u;
+    const uint64_t lanes = A.cmask[c];
+    const uint4 meta = A.cmeta[c];
+    const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z;
+    const uint32_t cb = A.cell_off[c];
+    const uint32_t *gblob = A.blob + A.cblob[c];
+    const uint32_t words = blob_words(cnt, nl, nrefs, meta.w);
+    const uint32_t *grefs = gblob + cnt + 1 + nl + 1;
+    uint32_t *s_lab = smem + words;                           // (cnt + nrefs) * G
+    uint32_t *s_cand = s_lab + ((cnt + nrefs) << lg);         // CAND_CAP
+    uint32_t *s_ctl = s_cand + CAND_CAP;                      // count, base
+    const uint32_t tid = threadIdx.x;
+    const uint32_t G = 1u << lg;
+    const uint32_t j = tid & (G - 1);
+    const uint32_t rank = (q << lg) + j;
+    const bool live = rank < uint32_t(__popcll(lanes));
+    const uint32_t jj = nth_set_bit(lanes, live ? rank : (q << lg));
+    const uint32_t tau = A.taus[jj];
+    const bool has_up = A.src_cell[jj] == c;
+    const uint32_t per_iter = CELL_THREADS >> lg;
+    // referenced core labels: loads issued before the blob copy is stored
+    const uint32_t r0 = tid >> lg;
+    uint32_t rv0 = INF, rv1 = INF;
+    if (r0 < nrefs) rv0 = A.dcore[(grefs[r0] << lk) + jj];
+    if (r0 + per_iter < nrefs) rv1 = A.dcore[(grefs[r0 + per_iter] << lk) + jj];
+    {
+        const uint4 *g4 = reinterpret_cast<const uint4 *>(gblob);
+        uint4 *s4 = reinterpret_cast<uint4 *>(smem);
+        const uint32_t n4 = words >> 2;
+        constexpr uint32_t T = CELL_THREADS;
+        const uint32_t last = n4 - 1;   // a blob holds at least its offsets, so n4 >= 1
+        for (uint32_t i = tid; i < n4; i += 8 * T) {
+            // indices past the end read the last vector again (never stored): no branches
+            const uint4 v0 = g4[i], v1 = g4[min(i + T, last)], v2 = g4[min(i + 2 * T, last)];
+            const uint4 v3 = g4[min(i + 3 * T, last)], v4 = g4[min(i + 4 * T, last)];
+            const uint4 v5 = g4[min(i + 5 * T, last)], v6 = g4[min(i + 6 * T, last)];
+            const uint4 v7 = g4[min(i + 7 * T, last)];
+            s4[i] = v0;
+            if (i + T < n4) s4[i + T] = v1;
+            if (i + 2 * T < n4) s4[i + 2 * T] = v2;
+            if (i + 3 * T < n4) s4[i + 3 * T] = v3;
+            if (i + 4 * T < n4) s4[i + 4 * T] = v4;
+            if (i + 5 * T < n4) s4[i + 5 * T] = v5;
+            if (i + 6 * T < n4) s4[i + 6 * T] = v6;
+            if (i + 7 * T < n4) s4[i + 7 * T] = v7;
+        }
+    }
+    if (r0 < nrefs) s_lab[((cnt + r0) << lg) + j] = rv0;
+    if (r0 + per_iter < nrefs) s_lab[((cnt + r0 + per_iter) << lg) + j] = rv1;
+    for (uint32_t r = r0 + 2 * per_iter; r < nrefs; r += per_iter)
+        s_lab[((cnt + r) << lg) + j] = A.dcore[(grefs[r] << lk) + jj];
+    if (tid == 0) s_ctl[0] = 0;
+    // internal vertices start at INF; upward labels only in a source's cell
+    for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
+        uint32_t val = INF;
+        if (has_up) {
+            uint32_t s = A.uslot[cb + i];
+            if (s != NO_SLOT) val = A.uval[(s << lk) + jj];
+        }
+        s_lab[(i << lg) + j] = val;
+    }
+    __syncthreads();
+    const uint32_t *s_off = smem;
+    const uint32_t *s_lvl = smem + cnt + 1;
+    const uint32_t *s_refs = smem + cnt + 1 + nl + 1;
+    const uint2 *s_ent = reinterpret_cast<const uint2 *>(smem + blob_head_words(cnt, nl, nrefs));
+    auto ent = [&](uint32_t e) { return s_ent[e]; };
+    auto ref = [&](uint32_t r) { return s_refs[r]; };
+    for (uint32_t l = 0; l < nl; ++l) {
+        const uint32_t a = s_lvl[l], bnd = s_lvl[l + 1];
+        for (uint32_t base = a; base < bnd; base += per_iter) {
+            uint32_t i = base + (tid >> lg);
+            bool act = i < bnd;
+            uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
+            uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
+            bool any_in = false, any_out = false;
+            for (uint32_t e = e0; e < e1; ++e) {
+                uint2 x = s_ent[e];
+                uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
+                dv = min(dv, sat_add(lt, x.y));
+                if (x.x & FLAGS) { if (lt <= tau) any_in = true; else any_out = true; }
+            }
+            if (act) {
+                s_lab[(i << lg) + j] = dv;
+                if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
+            }
+            bool vin = dv <= tau;
+            bool need = act && live && (vin ? any_out : any_in);
+            uint32_t e = need ? e0 : 0, ee = need ? e1 : 0;
+            while (__any(e < ee)) {
+                bool have = e < ee;
+                uint2 x = have ? s_ent[e] : make_uint2(0u, 0u);
+                uint32_t lt = x.x & LOCAL_MASK;
+                bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
+                const uint32_t word = e | (j << CAND_E_BITS);
+                push_cand(st && (x.x & FLAG_FWD), word, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+                push_cand(st && (x.x & FLAG_REV), word | (1u << 31), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb,
+                          lanes, q);
+                ++e;
+            }
+        }
+        __syncthreads();
+        const uint32_t pend = s_ctl[0];
+        __syncthreads();
+        if (pend > (l + 1 < nl ? CAND_CAP / 2 : 0u))
+            flush_cands(min(pend, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+    }
+}
+
+// The cell sweep: a grid of resident workgroups walks the work items.  XCD x (block index
+// = x mod 8) takes the x-th eighth of the item list, so the items of one cell, which are
+// consecutive, run on the same XCD and share its L2; its workgroups stride through that
+// range.  No workgroup waits for another.
+template <bool STAGED>
+__global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t total = *A.n_items;
+    const uint32_t rows = (total + 7u) >> 3;
+    const uint32_t x = blockIdx.x & 7u, stride = gridDim.x >> 3;
+    const uint32_t end = min(total, (x + 1u) * rows);
+    for (uint32_t it = x * rows + (blockIdx.x >> 3); it < end; it += stride) {
+        if (STAGED)
+            cell_item_staged(A, smem, it);
+        else
+            cell_item_pipelined(A, smem, it);
+        __syncthreads();   // the next item overwrites the LDS
     }
 }
 
@@ -570,6 +782,23 @@ static int dev_alloc_copy(T **dst, const T *src, size_t count, uint64_t &bytes) 
 template <class T>
 static int dev_alloc_copy(T **dst, const std::vector<T> &src, uint64_t &bytes) {
     return dev_alloc_copy(dst, src.data(), src.size(), bytes);
+}
+
+// Workgroups of a cell-sweep variant that fit one compute unit with `lds` bytes of LDS each
+// (cached per variant and size).
+int DevGraph::cell_occupancy(bool staged, size_t lds, uint32_t &per_cu) {
+    const uint64_t key = (uint64_t(staged) << 40) | lds;
+    auto f = occ_cache.find(key);
+    if (f != occ_cache.end()) {
+        per_cu = f->second;
+        return 0;
+    }
+    int nb = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, staged ? (const void *)k_cell_sweep<true> : (const void *)k_cell_sweep<false>, CELL_THREADS, lds));
+    per_cu = uint32_t(std::max(1, nb));
+    occ_cache[key] = per_cu;
+    return 0;
 }
 
 int DevGraph::upload(const iso::Prep &P, int device_) {
@@ -687,6 +916,10 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
             set_error("a cell references too many vertices for 16-bit local indices");
             return -1;
         }
+        if (ne >= (1u << CAND_E_BITS)) {
+            set_error("a cell has 2^25 or more downward entries");
+            return -1;
+        }
         cell_cnt[c] = cnt;
         cell_core_refs[c] = nr;
         cell_entries[c] = ne;
@@ -730,8 +963,11 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_cmeta, cmeta, bytes))) return r;
     max_cell_levels = 0;
     for (uint32_t c = 0; c < num_cells; ++c) max_cell_levels = std::max(max_cell_levels, uint32_t(cmeta[c].y));
-    HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                int(LDS_MAX)));
+    HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(LDS_MAX)));
+    HIPCHK(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, device));
     return main.create(device);
 }
 
@@ -912,12 +1148,35 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     // kernel arguments; with use_graph it is captured once per signature and replayed
     const bool use_graph = A.use_graph && !prof_on;
     GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
-                 uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
+                 A.cell_stage, 0u, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
                                  uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
                                  uint64_t(uintptr_t(B.d_keys)), uint64_t(uintptr_t(B.d_flags)),
                                  uint64_t(uintptr_t(B.d_counters)), uint64_t(uintptr_t(B.d_list)),
                                  uint64_t(uintptr_t(A.want_dist ? B.d_dist : nullptr)),
                                  uint64_t(uintptr_t(B.d_taus))}};
+    // cell sweep plan: variant, lanes per work item (as many as fit the LDS budget), LDS per
+    // workgroup and a grid of resident workgroups (no more than there can be items), a multiple of 8
+    bool staged = A.cell_stage == 1 && size_t(staged_lds_words(max_blob_words, max_cell_labels, 0)) * 4 <= LDS_MAX;
+    uint32_t cell_lg = 0, cell_grid = 8;
+    size_t lds = 0;
+    if (num_cells > 0) {
+        auto lds_of = [&](uint32_t g) {
+            return size_t(staged ? staged_lds_words(max_blob_words, max_cell_labels, g)
+                                 : cell_lds_words(max_cell_cnt, max_cell_levels, max_cell_labels, g)) * 4;
+        };
+        cell_lg = lk;
+        while (cell_lg > 0 && lds_of(cell_lg) > A.cell_lds_bytes) --cell_lg;
+        lds = lds_of(cell_lg);
+        if (lds > LDS_MAX) {
+            set_error("a cell does not fit the LDS of one workgroup");
+            return -2;
+        }
+        uint32_t per_cu = 0;
+        if ((r = cell_occupancy(staged, lds, per_cu))) return r;
+        uint64_t most = uint64_t(num_cells) << (lk - cell_lg);
+        uint64_t want = std::min<uint64_t>(uint64_t(per_cu) * uint64_t(std::max(1, num_cus)), most);
+        cell_grid = uint32_t(std::max<uint64_t>(8, (want + 7) / 8 * 8));
+    }
     bool replay = use_graph && C.graph_exec && std::memcmp(&sig, &C.sig, sizeof sig) == 0;
     if (use_graph && !replay) {
         if (C.graph_exec) hipGraphExecDestroy(C.graph_exec);
@@ -959,32 +1218,18 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         }
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
         if (num_cells > 0) {
-            // lanes per work item: as many as fit the LDS budget
-            lg = lk;
-            while (lg > 0 && size_t(cell_lds_words(max_cell_cnt, max_cell_levels, max_cell_labels, lg)) * 4 >
-                                 A.cell_lds_bytes)
-                --lg;
-            size_t lds = size_t(cell_lds_words(max_cell_cnt, max_cell_levels, max_cell_labels, lg)) * 4;
-            if (lds > LDS_MAX) {
-                if (use_graph) {
-                    hipGraph_t gdrop = nullptr;
-                    hipStreamEndCapture(s, &gdrop);
-                    if (gdrop) hipGraphDestroy(gdrop);
-                }
-                set_error("a cell does not fit the LDS of one workgroup");
-                return -2;
-            }
             k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(
-                fl_in, fl_out, K, d_uncovered, d_cell_off, d_src, K, num_cells, A.mode_plain ? 1u : 0u, lg,
+                fl_in, fl_out, K, d_uncovered, d_cell_off, d_src, K, num_cells, A.mode_plain ? 1u : 0u, cell_lg,
                 d_cmask, d_clist, d_items, B.d_counters);
-            const uint32_t groups = K >> lg;
+            lg = cell_lg;
             CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
                         d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
                         uint32_t(cap), A.lane_base, lk, lg, num_cells};
             if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
-            // enough blocks for every lane of every cell in items of G lanes (the others exit)
-            uint32_t grid = ((num_cells * groups + 7) / 8) * 8;
-            k_cell_sweep<<<dim3(grid), dim3(CELL_THREADS), lds, s>>>(LA);
+            if (staged)
+                k_cell_sweep<true><<<dim3(cell_grid), dim3(CELL_THREADS), lds, s>>>(LA);
+            else
+                k_cell_sweep<false><<<dim3(cell_grid), dim3(CELL_THREADS), lds, s>>>(LA);
         } else if (prof_on) {
             HIPCHK(hipEventRecord(C.prof.ev[2], s));
         }

@@ -185,9 +185,9 @@ def _identical_across_tuning(road50k, combos):
     g, orc, G = road50k
     src, tau = synth.batch_queries(g.n, 24, seed=77, lo_min=1, hi_min=120)
     ref = G.query_batch(src, tau, iso.MODE_CELLS)
-    for block, lds_kb, lanes, cm in combos:
-        say(f"tuning block={block} cell_lds_kb={lds_kb} lanes={lanes} core_mode={cm}")
-        G.set_tuning(lanes_per_launch=lanes, block=block, cell_lds_kb=lds_kb, core_mode=cm)
+    for block, lds_kb, lanes, cm, stage in combos:
+        say(f"tuning block={block} cell_lds_kb={lds_kb} lanes={lanes} core_mode={cm} cell_stage={stage}")
+        G.set_tuning(lanes_per_launch=lanes, block=block, cell_lds_kb=lds_kb, core_mode=cm, cell_stage=stage)
         out = G.query_batch(src, tau, iso.MODE_CELLS)
         for j in range(len(src)):
             np.testing.assert_array_equal(out[j], ref[j])
@@ -201,8 +201,9 @@ def _identical_across_tuning(road50k, combos):
 
 def test_results_identical_across_tuning(road50k):
     """Block size, LDS budget per cell workgroup and lanes per launch change only the schedule."""
-    _identical_across_tuning(road50k, ((64, 16, 8, 0), (1024, 160, 24, 0), (256, 64, 3, 0), (512, 24, 16, 0),
-                                       (256, 40, 64, 0)))
+    _identical_across_tuning(road50k, ((64, 16, 8, 0, 0), (1024, 160, 24, 0, 0), (256, 64, 3, 0, 1),
+                                       (512, 24, 16, 0, 0), (256, 40, 64, 0, 1), (128, 160, 64, 0, 1),
+                                       (256, 16, 5, 0, 1)))
 
 
 @pytest.mark.skip(reason="core_mode=1 (all core levels in one cooperative launch with a grid barrier "
@@ -210,7 +211,7 @@ def test_results_identical_across_tuning(road50k):
                          "8 blocks x 256 CUs); no cause in the kernel was found, so the mode is switched "
                          "off and iso_set_tuning rejects it")
 def test_results_identical_cooperative_core(road50k):
-    _identical_across_tuning(road50k, ((1024, 160, 24, 1), (256, 64, 3, 1), (256, 40, 64, 1)))
+    _identical_across_tuning(road50k, ((1024, 160, 24, 1, 0), (256, 64, 3, 1, 0), (256, 40, 64, 1, 0)))
 
 
 def test_core_mode_rejected(road50k):
@@ -272,3 +273,28 @@ def test_cell_work_items_follow_active_lanes(road50k):
     p = G.profile_read()
     G.profile_enable(False)
     assert p["cells_swept"] == nonempty and p["cell_lanes"] == nonempty * len(src)
+
+
+@pytest.mark.parametrize("k", [1, 64, 70])
+def test_staged_cell_kernel(road50k, k):
+    """The whole-cell LDS variant of the cell sweep gives the same edges and distances."""
+    g, orc, G = road50k
+    src, tau = synth.batch_queries(g.n, k, seed=300 + k, lo_min=1, hi_min=120)
+    ref = {m: G.query_batch(src, tau, m) for m in (iso.MODE_CELLS, iso.MODE_PLAIN)}
+    d_ref = {m: G.distances(int(src[0]), int(tau[0]), m) for m in (iso.MODE_CELLS, iso.MODE_PLAIN)}
+    try:
+        for lds_kb in (40, 96):
+            say(f"staged k={k} cell_lds_kb={lds_kb}")
+            G.set_tuning(cell_stage=1, cell_lds_kb=lds_kb)
+            for m in (iso.MODE_CELLS, iso.MODE_PLAIN):
+                out = G.query_batch(src, tau, m)
+                for j in range(k):
+                    np.testing.assert_array_equal(out[j], ref[m][j], err_msg=f"mode {m} lane {j}")
+                d, sw = G.distances(int(src[0]), int(tau[0]), m)
+                np.testing.assert_array_equal(sw, d_ref[m][1])
+                np.testing.assert_array_equal(d[sw], d_ref[m][0][sw])
+    finally:
+        G.set_tuning()
+    for j in range(0, k, max(1, k // 3)):
+        want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
+        np.testing.assert_array_equal(ref[iso.MODE_CELLS][j], want)
