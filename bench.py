@@ -185,6 +185,8 @@ def main():
                     help="choose lanes per launch, block size and cell LDS budget on a query sample first")
     ap.add_argument("--tuning", default="", help="JSON file written by the autotuner to apply")
     ap.add_argument("--save-tuning", default="", help="write the autotuner's result to this JSON file")
+    ap.add_argument("--knobs", default="",
+                    help="explicit tuning, e.g. lanes_per_launch=32,cell_lds_kb=24,cell_stage=0 (others default)")
     ap.add_argument("--serve-rates", default="250,1000,2000,3000",
                     help="offered Poisson rates (queries/s) for the serving section; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
@@ -210,7 +212,13 @@ def main():
     lanes = args.lanes
     G.set_tuning(lanes_per_launch=lanes)
     tuning_note = "defaults"
-    if args.autotune or args.tuning:
+    if args.knobs:
+        best = {k: int(v) for k, v in (kv.split("=") for kv in args.knobs.split(",") if kv)}
+        G.set_tuning(**best)
+        lanes = G.get_tuning()["lanes_per_launch"]
+        tuning_note = f"--knobs {args.knobs}"
+        log(f"tuning: {G.get_tuning()} ({tuning_note})")
+    elif args.autotune or args.tuning:
         from paper_1512_09090_amd import autotune
 
         if args.tuning:

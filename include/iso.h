@@ -112,7 +112,10 @@ typedef struct {
     uint64_t swept_vertices;    /* vertices whose label was computed, summed over lanes */
     uint64_t edges;             /* isochrone edges returned, summed over lanes */
     uint64_t upward_settled;    /* vertices settled by the upward searches, summed over lanes */
-    double t_upward_ms, t_device_ms, t_sort_ms, t_total_ms;
+    double t_upward_ms;         /* host upward searches and staging of the device inputs */
+    double t_device_ms;         /* device sweep, waited for on the host */
+    double t_sort_ms;           /* device sort and decode of the edges, copy to host memory */
+    double t_total_ms;
 } iso_query_stats;
 
 /* Preprocess (or load) a graph and make it resident on the device. */

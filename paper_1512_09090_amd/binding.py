@@ -149,14 +149,28 @@ def _u32(a):
     return a, a.ctypes.data_as(_U32P)
 
 
+class _LibBuffer:
+    """Owner of an edge array returned by the library: numpy views keep it alive, and it is
+    released with iso_free when the last view goes away (no copy of the result)."""
+
+    def __init__(self, addr: int, count: int):
+        self._addr = addr
+        self.__array_interface__ = {"data": (addr, False), "shape": (count, 2), "typestr": "<u4",
+                                    "version": 3}
+
+    def __del__(self):
+        if self._addr:
+            lib().iso_free(C.c_void_p(self._addr))
+            self._addr = 0
+
+
 def _edges_to_numpy(ptr, count) -> np.ndarray:
+    addr = C.cast(ptr, C.c_void_p).value
     if count == 0:
-        out = np.zeros((0, 2), dtype=np.uint32)
-    else:
-        raw = np.ctypeslib.as_array(C.cast(ptr, _U32P), shape=(count * 2,))
-        out = raw.reshape(count, 2).copy()
-    lib().iso_free(C.cast(ptr, C.c_void_p))
-    return out
+        if addr:
+            lib().iso_free(C.c_void_p(addr))
+        return np.zeros((0, 2), dtype=np.uint32)
+    return np.asarray(_LibBuffer(addr, count))
 
 
 class Graph:

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -152,6 +153,22 @@ struct iso_graph {
 // of one sweep.  settled (optional, lanes entries) receives the upward search sizes.
 void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
                     bool want_dist, isodev::RunArgs &A, uint32_t *settled);
-// Sorted keys of one sweep -> per-lane edge lists (original ids).
-void decode_keys(const std::vector<uint64_t> &keys, uint32_t lanes, std::vector<std::vector<iso_edge>> &out);
+// A malloc'd edge array (released to the caller, who frees it with iso_free).
+struct EdgeBuf {
+    iso_edge *p = nullptr;
+    size_t n = 0;
+    EdgeBuf() = default;
+    EdgeBuf(const EdgeBuf &) = delete;
+    EdgeBuf &operator=(const EdgeBuf &) = delete;
+    EdgeBuf(EdgeBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    EdgeBuf &operator=(EdgeBuf &&o) noexcept {
+        if (this != &o) { std::free(p); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~EdgeBuf() { std::free(p); }
+    iso_edge *release() { iso_edge *r = p; p = nullptr; n = 0; return r; }
+};
+// The edges of one sweep (R.edges, R.lane_off) -> one malloc'd array per lane; throws
+// std::bad_alloc when host memory runs out.
+void split_edges(const isodev::RunResult &R, uint32_t lanes, std::vector<EdgeBuf> &out);
 int api_fail(int code, const std::string &msg);

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -37,10 +38,15 @@ struct RunArgs {
 };
 
 struct RunResult {
-    uint32_t count = 0;          // keys produced (may exceed the capacity)
+    uint32_t count = 0;          // isochrone edges produced (may exceed the capacity)
     uint32_t active_cells = 0;   // length of the active-cell list (cells mode)
     bool overflow = false;
-    std::vector<uint64_t> keys;  // sorted lane << 58 | tail << 29 | head
+    // The edges as (tail, head) pairs of original ids, sorted by lane, then tail, then head;
+    // lane j's edges are [lane_off[j], lane_off[j + 1]).  They are copied to sink(count) if a
+    // sink is given (2 * count words; nullptr = out of host memory), else into `edges`.
+    std::function<uint32_t *(size_t)> sink;
+    std::vector<uint32_t> edges, lane_off;
+    double t_result_ms = 0;      // host time of sorting, decoding and copying back the edges
     std::vector<uint32_t> dcore, dist, active_list;   // only with want_dist
 };
 
@@ -53,9 +59,11 @@ struct QueryBufs {
              *d_src_cell = nullptr, *d_flags = nullptr, *d_list = nullptr, *d_counters = nullptr,
              *d_dist = nullptr;
     uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
+    uint32_t *d_lane_off = nullptr;   // MAX_LANES + 1 lane starts of the decoded edges
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
     size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
-           sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0;
+           sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0,
+           sz_lane_off = 0;
     void release();
 };
 

@@ -94,12 +94,16 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
         }
 }
 
-void decode_keys(const std::vector<uint64_t> &keys, uint32_t lanes, std::vector<std::vector<iso_edge>> &out) {
-    out.assign(lanes, {});
-    for (uint64_t key : keys) {
-        uint32_t j = uint32_t(key >> 58);
-        if (j < lanes)
-            out[j].push_back(iso_edge{uint32_t((key >> 29) & ((1u << 29) - 1)), uint32_t(key & ((1u << 29) - 1))});
+void split_edges(const isodev::RunResult &R, uint32_t lanes, std::vector<EdgeBuf> &out) {
+    out.clear();
+    out.resize(lanes);
+    for (uint32_t j = 0; j < lanes; ++j) {
+        const size_t a = R.lane_off[j], b = R.lane_off[j + 1];
+        EdgeBuf &e = out[j];
+        e.p = (iso_edge *)std::malloc(std::max<size_t>(1, b - a) * sizeof(iso_edge));
+        if (!e.p) throw std::bad_alloc();
+        e.n = b - a;
+        if (b > a) std::memcpy(e.p, R.edges.data() + 2 * a, (b - a) * sizeof(iso_edge));
     }
 }
 
@@ -131,7 +135,8 @@ int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t l
     g->last.active_cells += R.active_cells;
     for (uint32_t j = 0; j < lanes; ++j) g->last.upward_settled += settled[j];
     g->last.t_upward_ms += t1 - t0;
-    g->last.t_device_ms += t2 - t1;
+    g->last.t_device_ms += t2 - t1 - R.t_result_ms;
+    g->last.t_sort_ms += R.t_result_ms;
     return ISO_OK;
 }
 
@@ -283,31 +288,33 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
                       iso_edge **edges, size_t *offsets) {
     double t0 = now_ms();
     g->last = iso_query_stats{};
-    std::vector<iso_edge> all;
     const uint32_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
+    // every launch's edges are copied from the device straight into the growing result buffer
+    EdgeBuf out;
+    size_t cap = 0;
     offsets[0] = 0;
     for (size_t b = 0; b < k; b += per) {
         uint32_t lanes = uint32_t(std::min<size_t>(per, k - b));
         isodev::RunResult R;
+        R.sink = [&](size_t n) -> uint32_t * {
+            if (out.n + n > cap) {
+                size_t want = std::max(out.n + n, cap + cap / 2 + 1024);
+                iso_edge *p = (iso_edge *)std::realloc(out.p, want * sizeof(iso_edge));
+                if (!p) return nullptr;
+                out.p = p;
+                cap = want;
+            }
+            return reinterpret_cast<uint32_t *>(out.p + out.n);
+        };
         int r = run_lanes(g, src + b, tau + b, lanes, mode == ISO_MODE_PLAIN, false, R);
         if (r) return r;
-        double ts = now_ms();
-        size_t base = all.size();
-        all.resize(base + R.keys.size());
-        std::vector<size_t> cnt(lanes + 1, 0);
-        for (size_t i = 0; i < R.keys.size(); ++i) {
-            uint64_t key = R.keys[i];
-            all[base + i] = iso_edge{uint32_t((key >> 29) & ((1u << 29) - 1)), uint32_t(key & ((1u << 29) - 1))};
-            cnt[(key >> 58) + 1]++;
-        }
-        for (uint32_t j = 0; j < lanes; ++j) offsets[b + j + 1] = offsets[b + j] + cnt[j + 1];
-        g->last.t_sort_ms += now_ms() - ts;
+        for (uint32_t j = 0; j < lanes; ++j) offsets[b + j + 1] = out.n + R.lane_off[j + 1];
+        out.n += R.count;
     }
-    g->last.edges = all.size();
-    iso_edge *buf = (iso_edge *)std::malloc(std::max<size_t>(1, all.size()) * sizeof(iso_edge));
-    if (!buf) return fail(ISO_ENOMEM, "out of host memory for the result");
-    if (!all.empty()) std::memcpy(buf, all.data(), all.size() * sizeof(iso_edge));
-    *edges = buf;
+    g->last.edges = out.n;
+    if (!out.p && !(out.p = (iso_edge *)std::malloc(sizeof(iso_edge))))
+        return fail(ISO_ENOMEM, "out of host memory for the result");
+    *edges = out.release();
     g->last.t_total_ms = now_ms() - t0;
     return ISO_OK;
 }

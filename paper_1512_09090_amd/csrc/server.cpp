@@ -26,7 +26,7 @@ struct Request {
     uint32_t batch_lanes = 0;
     bool done = false;
     int status = ISO_OK;
-    std::vector<iso_edge> edges;
+    EdgeBuf edges;
 };
 
 struct InFlight {
@@ -145,8 +145,16 @@ void completer_loop(iso_server *s) {
         if (r) {
             fail_batch(s, f.tickets, r);
         } else {
-            std::vector<std::vector<iso_edge>> per;
-            decode_keys(R.keys, uint32_t(f.tickets.size()), per);
+            std::vector<EdgeBuf> per;
+            try {
+                split_edges(R, uint32_t(f.tickets.size()), per);
+            } catch (const std::bad_alloc &) {
+                fail_batch(s, f.tickets, api_fail(ISO_ENOMEM, "out of host memory for the results"));
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->free_ctx.push_back(f.ctx);
+                s->cv_work.notify_all();
+                continue;
+            }
             std::lock_guard<std::mutex> lk(s->mu);
             double t = now_ms();
             for (size_t j = 0; j < f.tickets.size(); ++j) {
@@ -263,11 +271,8 @@ int iso_server_wait(iso_server *s, uint64_t ticket, int timeout_ms, iso_edge **e
         stats->batch_lanes = q.batch_lanes;
     }
     if (q.status != ISO_OK) return q.status;
-    iso_edge *buf = (iso_edge *)std::malloc(std::max<size_t>(1, q.edges.size()) * sizeof(iso_edge));
-    if (!buf) return api_fail(ISO_ENOMEM, "out of host memory for the result");
-    if (!q.edges.empty()) std::memcpy(buf, q.edges.data(), q.edges.size() * sizeof(iso_edge));
-    *edges = buf;
-    *count = q.edges.size();
+    *count = q.edges.n;
+    *edges = q.edges.release();
     return ISO_OK;
 }
 

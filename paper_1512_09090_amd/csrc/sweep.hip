@@ -28,6 +28,8 @@
 // atomic per wavefront (ballot + popcount) as 64-bit keys
 // lane << 58 | tail << 29 | head, then radix-sorted (query, tail, head).
 #include <hip/hip_runtime.h>
+
+#include <chrono>
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -74,6 +76,19 @@ __device__ __forceinline__ void emit_wave(bool pred, uint64_t key, uint64_t *__r
         uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
         if (idx < cap) out[idx] = key;
     }
+}
+
+// Sorted keys -> (tail, head) pairs, and the first position of every lane: lane_off[l] = the
+// first i whose lane is >= l (lane_off is filled with the key count beforehand).
+__global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *__restrict__ pairs,
+                         uint32_t *__restrict__ lane_off) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    pairs[i] = make_uint2(uint32_t(k >> 29) & ((1u << 29) - 1u), uint32_t(k) & ((1u << 29) - 1u));
+    const uint32_t j = uint32_t(k >> 58);
+    const uint32_t from = i ? uint32_t(keys[i - 1] >> 58) + 1u : 0u;
+    for (uint32_t l = from; l <= j; ++l) lane_off[l] = i;
 }
 
 __global__ void k_fill(uint32_t *__restrict__ p, uint32_t value, uint64_t count) {
@@ -1008,7 +1023,7 @@ void DevGraph::release() {
 
 void QueryBufs::release() {
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
-                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot};
+                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off};
     for (void *p : ptrs) if (p) hipFree(p);
     if (h_pinned) hipHostFree(h_pinned);
     *this = QueryBufs();
@@ -1091,6 +1106,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     size_t cap = A.out_cap;
     if ((r = ensure((void **)&B.d_keys, B.sz_keys, cap * 8))) return r;
     if ((r = ensure((void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8))) return r;
+    if ((r = ensure((void **)&B.d_lane_off, B.sz_lane_off, (MAX_LANES + 1) * 4))) return r;
     if (A.want_dist && (r = ensure((void **)&B.d_dist, B.sz_dist, size_t(n) * K * 4))) return r;
     // per-call host inputs staged in one pinned buffer: counters back, taus, source cells,
     // upward entries
@@ -1327,8 +1343,10 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         }
     }
     if (R.overflow) return 0;   // caller grows the buffer and launches again
-    // sort keys: lane bits above 58, then tail, then head
-    R.keys.resize(cnt_all);
+    // sort the keys (lane bits above 58, then tail, then head), decode them into (tail, head)
+    // pairs and lane starts on the device, copy both back
+    R.lane_off.assign(size_t(K) + 1, 0);
+    const auto tr0 = std::chrono::steady_clock::now();
     if (cnt_all) {
         int end_bit = 58 + int(ilog2(std::max<uint32_t>(1, C.lane_base + K)));
         if (end_bit > 64) end_bit = 64;
@@ -1340,8 +1358,26 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         if (prof.on) HIPCHK(hipEventRecord(prof.ev[4], s));
         HIPCHK(hipcub::DeviceRadixSort::SortKeys(B.d_sort_tmp, tmp, (const uint64_t *)B.d_keys,
                                                  B.d_keys_sorted, int(cnt_all), 0, end_bit, s));
+        k_fill<<<dim3(1), dim3(128), 0, s>>>(B.d_lane_off, cnt_all, uint64_t(K) + 1);
+        // the pairs overwrite the unsorted keys (same size)
+        k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(B.d_keys_sorted, cnt_all,
+                                                                    reinterpret_cast<uint2 *>(B.d_keys),
+                                                                    B.d_lane_off);
         if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
-        HIPCHK(hipMemcpyAsync(R.keys.data(), B.d_keys_sorted, size_t(cnt_all) * 8, hipMemcpyDeviceToHost, s));
+        uint32_t *dst = nullptr;
+        if (R.sink) {
+            dst = R.sink(cnt_all);
+        } else {
+            R.edges.resize(size_t(cnt_all) * 2);
+            dst = R.edges.data();
+        }
+        if (!dst) {
+            HIPCHK(hipStreamSynchronize(s));
+            set_error("out of host memory for the result");
+            return -2;   // ISO_ENOMEM
+        }
+        HIPCHK(hipMemcpyAsync(dst, B.d_keys, size_t(cnt_all) * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(R.lane_off.data(), B.d_lane_off, (size_t(K) + 1) * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (prof.on) {
             float ms = 0;
@@ -1349,6 +1385,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
             prof.sort_ms += ms;
         }
     }
+    R.t_result_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();
     return 0;
 }
 

@@ -302,3 +302,46 @@ def test_parallel_arcs_and_self_loops_are_merged():
     pos = np.empty(3, dtype=np.int64)
     pos[L["perm"]] = np.arange(3)
     np.testing.assert_array_equal(layout_sweep(L, pos, 0), np.array([0, 3, 5], dtype=np.uint32))
+
+
+def test_result_buffer_views_own_library_memory():
+    """Edge arrays wrap the library's result buffer without a copy; slices keep it alive and
+    the last view releases it with iso_free."""
+    import ctypes
+    import gc
+
+    from paper_1512_09090_amd import binding
+
+    libc = ctypes.CDLL(None)
+    libc.malloc.restype = ctypes.c_void_p
+    libc.malloc.argtypes = [ctypes.c_size_t]
+    freed = []
+    real_free = binding.lib().iso_free
+
+    class Spy:
+        def __getattr__(self, name):
+            return getattr(binding.lib(), name)
+
+        def iso_free(self, p):
+            freed.append(p.value)
+            real_free(p)
+
+    addr = libc.malloc(6 * 4)
+    ctypes.memmove(addr, np.arange(6, dtype=np.uint32).ctypes.data, 24)
+    saved = binding._lib
+    binding._lib = Spy()
+    try:
+        arr = binding._edges_to_numpy(ctypes.cast(addr, ctypes.POINTER(binding.Edge)), 3)
+        assert arr.shape == (3, 2) and arr.dtype == np.uint32
+        tail = arr[1:]
+        del arr
+        gc.collect()
+        assert freed == []
+        np.testing.assert_array_equal(tail, [[2, 3], [4, 5]])
+        del tail
+        gc.collect()
+        assert freed == [addr]
+        empty = binding._edges_to_numpy(ctypes.cast(libc.malloc(8), ctypes.POINTER(binding.Edge)), 0)
+        assert empty.shape == (0, 2) and len(freed) == 2
+    finally:
+        binding._lib = saved
