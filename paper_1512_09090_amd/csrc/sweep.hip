@@ -125,6 +125,17 @@ __device__ __forceinline__ void set_cell_flags(uint32_t c, uint32_t ecc, uint32_
     if (sat_add(dv, ecc) > tau && !(fl_out[w] & bit)) atomicOr(&fl_out[w], bit);
 }
 
+// The same with the flag words read beforehand (seen_in / seen_out, possibly stale: a bit
+// set meanwhile only costs a redundant OR); the ORs return nothing, so nothing waits on them.
+__device__ __forceinline__ void set_cell_flags_seen(uint32_t c, uint32_t ecc, uint32_t dv, uint32_t tau,
+                                                    uint32_t w, uint32_t seen_in, uint32_t seen_out,
+                                                    uint32_t *__restrict__ fl_in, uint32_t *__restrict__ fl_out) {
+    if (c == NO_CELL) return;
+    const uint32_t bit = 1u << (c & 31u);
+    if (dv <= tau && !(seen_in & bit)) atomicOr(&fl_in[w], bit);
+    if (sat_add(dv, ecc) > tau && !(seen_out & bit)) atomicOr(&fl_out[w], bit);
+}
+
 struct CoreArgs {
     const uint32_t *down_off;
     const uint2 *down_arc;
@@ -261,7 +272,7 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     uint32_t j = t & (K - 1), sub = (t >> lk) & (S - 1);
     bool act = v < vend;
     uint32_t tau = A.taus[j];
-    uint32_t init = INF, beg = 0, end = 0, cell = NO_CELL, ecc = 0;
+    uint32_t init = INF, beg = 0, end = 0, cell = NO_CELL, ecc = 0, fw = 0, seen_in = 0, seen_out = 0;
     if (act) {
         beg = A.down_off[v];
         end = A.down_off[v + 1];
@@ -269,6 +280,11 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
         if (sub == 0) {
             cell = A.core_cell[v];
             ecc = A.core_ecc[v];
+            if (cell != NO_CELL) {
+                fw = (cell >> 5) * K + j;   // the k lanes' words of one cell group are contiguous
+                seen_in = A.fl_in[fw];
+                seen_out = A.fl_out[fw];
+            }
         }
         if (s != NO_SLOT) init = A.uval[(s << lk) + j];
     }
@@ -280,7 +296,7 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, any_in, any_out);
     if (act && sub == 0) {
         A.dcore[(v << lk) + j] = dv;
-        set_cell_flags(cell, ecc, dv, tau, j, K, A.fl_in, A.fl_out);
+        set_cell_flags_seen(cell, ecc, dv, tau, fw, seen_in, seen_out, A.fl_in, A.fl_out);
     }
     extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
 }
@@ -469,6 +485,32 @@ __device__ __forceinline__ void flush_cands(uint32_t n, uint32_t *s_cand, uint32
     __syncthreads();
 }
 
+// End of level l of a work item: one barrier, after which every label of the level is final.
+// The candidate list is written out after the last level, and earlier when it held more than
+// a quarter of its capacity at the end of the previous level: thread 0 records the count after
+// each level's barrier in one of two LDS words (alternating with the level's parity), and
+// every thread decides on the word written a level before, so all decide alike without a
+// second barrier.
+template <class ENT, class REF>
+__device__ __forceinline__ void level_end(uint32_t l, uint32_t nl, uint32_t *s_cand, uint32_t *s_ctl,
+                                          const CellArgs &A, const uint32_t *s_off, uint32_t cnt, ENT ent, REF ref,
+                                          uint32_t cb, uint64_t lanes, uint32_t q) {
+    __syncthreads();
+    if (l + 1 == nl) {
+        const uint32_t n = s_ctl[0];   // no candidate is added after the last level
+        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        return;
+    }
+    const uint32_t due = l ? s_ctl[2 + ((l - 1) & 1u)] : 0u;
+    if (due > CAND_CAP / 4) {
+        // every thread is between this level's barrier and the flush: the count is stable
+        flush_cands(min(s_ctl[0], CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        if (threadIdx.x == 0) s_ctl[2 + (l & 1u)] = 0;
+    } else if (threadIdx.x == 0) {
+        s_ctl[2 + (l & 1u)] = s_ctl[0];
+    }
+}
+
 // One work item (an active cell and up to G = 1 << lg of the lanes for which it is active)
 // on one workgroup, level pipeline variant.  Offsets, level bounds and labels live in LDS; the
 // entries of level l+1 (contiguous in the blob) are loaded into registers while level l is
@@ -515,7 +557,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
         }
     }
     for (uint32_t i = tid; i < cnt + 1 + nl + 1; i += CELL_THREADS) s_off[i] = gblob[i];
-    if (tid == 0) s_ctl[0] = 0;
+    if (tid == 0) s_ctl[0] = s_ctl[2] = s_ctl[3] = 0;
     // labels: internal vertices start at INF (upward labels only in a source's cell) ...
     for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
         uint32_t val = INF;
@@ -618,12 +660,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
                 if (idx < n1) nxt[idx] = r[k];
             }
         }
-        __syncthreads();
-        // write the candidates out when the list is half full, and after the last level
-        const uint32_t pend = s_ctl[0];
-        __syncthreads();
-        if (pend > (l + 1 < nl ? CAND_CAP / 2 : 0u))
-            flush_cands(min(pend, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
     }
 }
 
@@ -691,7 +728,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
     if (r0 + per_iter < nrefs) s_lab[((cnt + r0 + per_iter) << lg) + j] = rv1;
     for (uint32_t r = r0 + 2 * per_iter; r < nrefs; r += per_iter)
         s_lab[((cnt + r) << lg) + j] = A.dcore[(grefs[r] << lk) + jj];
-    if (tid == 0) s_ctl[0] = 0;
+    if (tid == 0) s_ctl[0] = s_ctl[2] = s_ctl[3] = 0;
     // internal vertices start at INF; upward labels only in a source's cell
     for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
         uint32_t val = INF;
@@ -716,11 +753,20 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
             uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
             uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
             bool any_in = false, any_out = false;
-            for (uint32_t e = e0; e < e1; ++e) {
-                uint2 x = s_ent[e];
-                uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
-                dv = min(dv, sat_add(lt, x.y));
-                if (x.x & FLAGS) { if (lt <= tau) any_in = true; else any_out = true; }
+            // four entries at a time: their reads, then their tails' labels
+            for (uint32_t e = e0; e < e1; e += 4) {
+                uint2 x[4];
+                uint32_t lt[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) x[u] = e + u < e1 ? s_ent[e + u] : make_uint2(0u, INF);
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+                    lt[u] = e + u < e1 ? s_lab[((x[u].x & LOCAL_MASK) << lg) + j] : INF;
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    dv = min(dv, sat_add(lt[u], x[u].y));
+                    if (x[u].x & FLAGS) { if (lt[u] <= tau) any_in = true; else any_out = true; }
+                }
             }
             if (act) {
                 s_lab[(i << lg) + j] = dv;
@@ -741,11 +787,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
                 ++e;
             }
         }
-        __syncthreads();
-        const uint32_t pend = s_ctl[0];
-        __syncthreads();
-        if (pend > (l + 1 < nl ? CAND_CAP / 2 : 0u))
-            flush_cands(min(pend, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
     }
 }
 

@@ -185,9 +185,12 @@ def _identical_across_tuning(road50k, combos):
     g, orc, G = road50k
     src, tau = synth.batch_queries(g.n, 24, seed=77, lo_min=1, hi_min=120)
     ref = G.query_batch(src, tau, iso.MODE_CELLS)
-    for block, lds_kb, lanes, cm, stage in combos:
-        say(f"tuning block={block} cell_lds_kb={lds_kb} lanes={lanes} core_mode={cm} cell_stage={stage}")
-        G.set_tuning(lanes_per_launch=lanes, block=block, cell_lds_kb=lds_kb, core_mode=cm, cell_stage=stage)
+    for i, (block, lds_kb, lanes, cm, stage) in enumerate(combos):
+        graph = i % 2          # every other setting runs eagerly
+        say(f"tuning block={block} cell_lds_kb={lds_kb} lanes={lanes} core_mode={cm} cell_stage={stage} "
+            f"use_graph={graph}")
+        G.set_tuning(lanes_per_launch=lanes, block=block, cell_lds_kb=lds_kb, core_mode=cm, cell_stage=stage,
+                     use_graph=graph)
         out = G.query_batch(src, tau, iso.MODE_CELLS)
         for j in range(len(src)):
             np.testing.assert_array_equal(out[j], ref[j])
@@ -227,7 +230,7 @@ def test_graph_replay_matches_eager(road50k):
     synchronizations in between; every replay must equal the eager result."""
     g, orc, G = road50k
     src, tau = synth.batch_queries(g.n, 48, seed=88, lo_min=1, hi_min=120)
-    G.set_tuning(lanes_per_launch=16)
+    G.set_tuning(lanes_per_launch=16, use_graph=0)
     eager = {m: G.query_batch(src, tau, m) for m in (iso.MODE_CELLS, iso.MODE_PLAIN)}
     eager1 = [G.query(int(s), int(t), iso.MODE_CELLS) for s, t in zip(src[:5], tau[:5])]
     d_eager, _ = G.distances(int(src[0]), int(tau[0]), iso.MODE_PLAIN)
