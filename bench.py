@@ -134,6 +134,28 @@ def copy_probe(mib):
     log(f"copy probe: 3 x {mib} MiB device-to-device")
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "road18m_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1512_09090_amd", "csrc", "sweep.hip")
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of a phase from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes, scaled by a copy of known size), or None when the summary is missing or
+    was taken on another version of the kernel source."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("sweep_hip_sha256:", f"{phase}_")))
+    if vals.get("sweep_hip_sha256", "").strip() != sha:
+        return None
+    v = vals.get(f"{phase}_bytes_per_launch")
+    return int(v) if v else None
+
+
 def cpu_baseline(g, src, tau, seconds, threads):
     """The oracle (tau-bounded Dijkstra + edge rule) on this host, one query per thread."""
     import oracle
@@ -285,7 +307,7 @@ def main():
     ms, byts, launches = phases[dom]
     achieved = (byts / 1e9) / (ms / 1e3) if ms > 0 else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                 "avg_launch_ms": round(ms / max(1, launches), 4),
                 "algorithmic_bytes_per_launch": int(byts / max(1, launches)),
                 "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()}}

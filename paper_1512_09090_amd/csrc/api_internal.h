@@ -153,22 +153,40 @@ struct iso_graph {
 // of one sweep.  settled (optional, lanes entries) receives the upward search sizes.
 void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
                     bool want_dist, isodev::RunArgs &A, uint32_t *settled);
-// A malloc'd edge array (released to the caller, who frees it with iso_free).
+// Process-wide pool of pinned host blocks for results (device copies into pinned memory run
+// at full link speed).  pinned_get returns a block of at least `bytes` (its capacity in cap)
+// or nullptr; pinned_put takes a block back and returns false for pointers it does not own.
+// iso_free hands every pointer to pinned_put first, then to free().
+void *pinned_get(size_t bytes, size_t &cap);
+bool pinned_put(void *p);
+
+// An edge array released to the caller, who frees it with iso_free: malloc'd, or a pinned
+// pool block.
 struct EdgeBuf {
     iso_edge *p = nullptr;
     size_t n = 0;
+    bool pinned = false;
     EdgeBuf() = default;
     EdgeBuf(const EdgeBuf &) = delete;
     EdgeBuf &operator=(const EdgeBuf &) = delete;
-    EdgeBuf(EdgeBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    EdgeBuf(EdgeBuf &&o) noexcept : p(o.p), n(o.n), pinned(o.pinned) { o.p = nullptr; o.n = 0; }
     EdgeBuf &operator=(EdgeBuf &&o) noexcept {
-        if (this != &o) { std::free(p); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            drop();
+            p = o.p; n = o.n; pinned = o.pinned;
+            o.p = nullptr; o.n = 0;
+        }
         return *this;
     }
-    ~EdgeBuf() { std::free(p); }
+    ~EdgeBuf() { drop(); }
+    void drop() {
+        if (p && !(pinned && pinned_put(p))) std::free(p);
+        p = nullptr;
+    }
     iso_edge *release() { iso_edge *r = p; p = nullptr; n = 0; return r; }
 };
-// The edges of one sweep (R.edges, R.lane_off) -> one malloc'd array per lane; throws
-// std::bad_alloc when host memory runs out.
-void split_edges(const isodev::RunResult &R, uint32_t lanes, std::vector<EdgeBuf> &out);
+// The edges of one sweep ((tail, head) pairs, lane starts) -> one malloc'd array per lane;
+// throws std::bad_alloc when host memory runs out.
+void split_edges(const uint32_t *pairs, const std::vector<uint32_t> &lane_off, uint32_t lanes,
+                 std::vector<EdgeBuf> &out);
 int api_fail(int code, const std::string &msg);

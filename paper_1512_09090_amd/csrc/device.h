@@ -117,6 +117,7 @@ struct DevGraph {
     uint32_t TX = 0, nlev_table = 0;
     uint32_t *d_table = nullptr;
     uint8_t *d_uncovered = nullptr;
+    uint32_t *d_cell_core_off = nullptr, *d_cell_core = nullptr;   // core positions of each cell (CSR)
     // per-cell blobs for the cell sweep: [offsets][level bounds][core refs][entries]
     uint32_t *d_blob = nullptr;
     uint32_t *d_cblob = nullptr;   // word offset of each cell's blob

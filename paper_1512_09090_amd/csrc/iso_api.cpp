@@ -5,6 +5,8 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <unordered_map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -94,17 +96,72 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
         }
 }
 
-void split_edges(const isodev::RunResult &R, uint32_t lanes, std::vector<EdgeBuf> &out) {
+void split_edges(const uint32_t *pairs, const std::vector<uint32_t> &lane_off, uint32_t lanes,
+                 std::vector<EdgeBuf> &out) {
     out.clear();
     out.resize(lanes);
     for (uint32_t j = 0; j < lanes; ++j) {
-        const size_t a = R.lane_off[j], b = R.lane_off[j + 1];
+        const size_t a = lane_off[j], b = lane_off[j + 1];
         EdgeBuf &e = out[j];
         e.p = (iso_edge *)std::malloc(std::max<size_t>(1, b - a) * sizeof(iso_edge));
         if (!e.p) throw std::bad_alloc();
         e.n = b - a;
-        if (b > a) std::memcpy(e.p, R.edges.data() + 2 * a, (b - a) * sizeof(iso_edge));
+        if (b > a) std::memcpy(e.p, pairs + 2 * a, (b - a) * sizeof(iso_edge));
     }
+}
+
+namespace {
+struct PinnedPool {
+    std::mutex mu;
+    std::unordered_map<void *, size_t> owned;      // every block of the pool -> capacity
+    std::multimap<size_t, void *> idle;            // blocks not handed out, by capacity
+    size_t idle_bytes = 0;
+    static constexpr size_t KEEP = size_t(512) << 20;   // idle pinned memory kept for reuse
+};
+PinnedPool &pool() {
+    static PinnedPool *P = new PinnedPool();   // never destroyed: blocks may outlive static teardown
+    return *P;
+}
+}  // namespace
+
+void *pinned_get(size_t bytes, size_t &cap) {
+    PinnedPool &P = pool();
+    {
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.idle.lower_bound(bytes);
+        if (it != P.idle.end() && it->first <= 4 * std::max<size_t>(bytes, 1 << 20)) {
+            cap = it->first;
+            void *p = it->second;
+            P.idle_bytes -= it->first;
+            P.idle.erase(it);
+            return p;
+        }
+    }
+    size_t c = size_t(1) << 20;
+    while (c < bytes) c <<= 1;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess || !p) return nullptr;
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.owned[p] = c;
+    cap = c;
+    return p;
+}
+
+bool pinned_put(void *p) {
+    PinnedPool &P = pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.owned.find(p);
+    if (it == P.owned.end()) return false;
+    P.idle.emplace(it->second, p);
+    P.idle_bytes += it->second;
+    while (P.idle_bytes > PinnedPool::KEEP && !P.idle.empty()) {   // drop the largest idle blocks
+        auto last = std::prev(P.idle.end());
+        P.idle_bytes -= last->first;
+        P.owned.erase(last->second);
+        hipHostFree(last->second);
+        P.idle.erase(last);
+    }
+    return true;
 }
 
 int api_fail(int code, const std::string &msg) {
@@ -156,7 +213,9 @@ extern "C" {
 
 const char *iso_last_error(void) { return g_err.c_str(); }
 
-void iso_free(void *p) { std::free(p); }
+void iso_free(void *p) {
+    if (p && !pinned_put(p)) std::free(p);
+}
 
 int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
     if (!d || !out) return fail(ISO_EINVAL, "NULL argument");
@@ -289,8 +348,10 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
     double t0 = now_ms();
     g->last = iso_query_stats{};
     const uint32_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
-    // every launch's edges are copied from the device straight into the growing result buffer
+    // every launch's edges are copied from the device straight into the result buffer, a
+    // pinned pool block (grown by moving to a larger block when a later launch needs room)
     EdgeBuf out;
+    out.pinned = true;
     size_t cap = 0;
     offsets[0] = 0;
     for (size_t b = 0; b < k; b += per) {
@@ -298,11 +359,13 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         isodev::RunResult R;
         R.sink = [&](size_t n) -> uint32_t * {
             if (out.n + n > cap) {
-                size_t want = std::max(out.n + n, cap + cap / 2 + 1024);
-                iso_edge *p = (iso_edge *)std::realloc(out.p, want * sizeof(iso_edge));
+                size_t want = std::max(out.n + n, cap + cap / 2), got = 0;
+                iso_edge *p = (iso_edge *)pinned_get(want * sizeof(iso_edge), got);
                 if (!p) return nullptr;
+                if (out.n) std::memcpy(p, out.p, out.n * sizeof(iso_edge));
+                if (out.p) pinned_put(out.p);
                 out.p = p;
-                cap = want;
+                cap = got / sizeof(iso_edge);
             }
             return reinterpret_cast<uint32_t *>(out.p + out.n);
         };
@@ -312,8 +375,11 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         out.n += R.count;
     }
     g->last.edges = out.n;
-    if (!out.p && !(out.p = (iso_edge *)std::malloc(sizeof(iso_edge))))
-        return fail(ISO_ENOMEM, "out of host memory for the result");
+    if (!out.p) {   // no edges at all: a malloc'd placeholder
+        out.pinned = false;
+        if (!(out.p = (iso_edge *)std::malloc(sizeof(iso_edge))))
+            return fail(ISO_ENOMEM, "out of host memory for the result");
+    }
     *edges = out.release();
     g->last.t_total_ms = now_ms() - t0;
     return ISO_OK;

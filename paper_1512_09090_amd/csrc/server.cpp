@@ -134,6 +134,14 @@ void completer_loop(iso_server *s) {
             s->inflight.pop_front();
         }
         isodev::RunResult R;
+        EdgeBuf batch;   // the sweep's edges, copied from the device into a pinned pool block
+        batch.pinned = true;
+        R.sink = [&](size_t n) -> uint32_t * {
+            size_t cap = 0;
+            batch.drop();
+            batch.p = (iso_edge *)pinned_get(n * sizeof(iso_edge), cap);
+            return reinterpret_cast<uint32_t *>(batch.p);
+        };
         int r = g->D.finish(*f.ctx, R);
         for (int attempt = 0; !r && R.overflow && attempt < 8; ++attempt) {
             s->out_cap = std::max<size_t>(s->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
@@ -147,7 +155,8 @@ void completer_loop(iso_server *s) {
         } else {
             std::vector<EdgeBuf> per;
             try {
-                split_edges(R, uint32_t(f.tickets.size()), per);
+                split_edges(reinterpret_cast<const uint32_t *>(batch.p), R.lane_off, uint32_t(f.tickets.size()),
+                            per);
             } catch (const std::bad_alloc &) {
                 fail_batch(s, f.tickets, api_fail(ISO_ENOMEM, "out of host memory for the results"));
                 std::lock_guard<std::mutex> lk(s->mu);

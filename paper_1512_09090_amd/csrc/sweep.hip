@@ -114,26 +114,24 @@ __global__ void k_uset_clear(uint32_t *__restrict__ uslot, const uint32_t *__res
     if (i < nu) uslot[upos[i]] = NO_SLOT;
 }
 
-// Flags of core vertex v in its cell for lane j (relaxed rule: d <= tau sets i, d + ecc > tau sets o).
-__device__ __forceinline__ void set_cell_flags(uint32_t c, uint32_t ecc, uint32_t dv, uint32_t tau, uint32_t j,
-                                               uint32_t K, uint32_t *__restrict__ fl_in,
-                                               uint32_t *__restrict__ fl_out) {
-    if (c == NO_CELL) return;
-    uint32_t bit = 1u << (c & 31u);
-    uint32_t w = (c >> 5) * K + j;   // the k lanes' words of one cell group are contiguous
-    if (dv <= tau && !(fl_in[w] & bit)) atomicOr(&fl_in[w], bit);
-    if (sat_add(dv, ecc) > tau && !(fl_out[w] & bit)) atomicOr(&fl_out[w], bit);
-}
-
-// The same with the flag words read beforehand (seen_in / seen_out, possibly stale: a bit
-// set meanwhile only costs a redundant OR); the ORs return nothing, so nothing waits on them.
-__device__ __forceinline__ void set_cell_flags_seen(uint32_t c, uint32_t ecc, uint32_t dv, uint32_t tau,
-                                                    uint32_t w, uint32_t seen_in, uint32_t seen_out,
-                                                    uint32_t *__restrict__ fl_in, uint32_t *__restrict__ fl_out) {
-    if (c == NO_CELL) return;
-    const uint32_t bit = 1u << (c & 31u);
-    if (dv <= tau && !(seen_in & bit)) atomicOr(&fl_in[w], bit);
-    if (sat_add(dv, ecc) > tau && !(seen_out & bit)) atomicOr(&fl_out[w], bit);
+// Cell flags of a core vertex v for the K lanes of its group (relaxed rule: d <= tau is "in",
+// d + ecc > tau is "out"): two wavefront ballots; the group's first thread stores the group's
+// K-bit slices as v's lane masks (plain stores, no atomics).  The lanes of a group are
+// consecutive in the wavefront (K lanes x S sub-lanes, K * S <= 64), and only sub-lane 0
+// holds the final label.  Every thread of the wavefront must call it.
+__device__ __forceinline__ void store_vertex_masks(bool act, uint32_t v, uint32_t cell, uint32_t ecc, uint32_t dv,
+                                                   uint32_t tau, uint32_t j, uint32_t sub, uint32_t lk,
+                                                   uint32_t lgs, uint64_t *__restrict__ vin,
+                                                   uint64_t *__restrict__ vout) {
+    const bool mine = act && sub == 0 && cell != NO_CELL;
+    const uint64_t bin = __ballot(mine && dv <= tau);
+    const uint64_t bout = __ballot(mine && sat_add(dv, ecc) > tau);
+    if (mine && j == 0) {
+        const uint32_t sh = (__lane_id() >> lgs) << lgs;
+        const uint64_t m = lk == 6 ? ~0ull : ((1ull << (1u << lk)) - 1ull);
+        vin[v] = (bin >> sh) & m;
+        vout[v] = (bout >> sh) & m;
+    }
 }
 
 struct CoreArgs {
@@ -141,8 +139,7 @@ struct CoreArgs {
     const uint2 *down_arc;
     uint32_t *dcore;
     const uint32_t *uslot, *uval, *perm, *core_cell, *core_ecc, *taus;
-    uint32_t *fl_in, *fl_out;
-    uint32_t flag_words;
+    uint64_t *vin, *vout;   // per core vertex: lanes with d <= tau, lanes with d + ecc > tau
     uint64_t *out_keys;
     uint32_t *out_count;
     uint32_t out_cap, lane_base, lk;
@@ -250,7 +247,9 @@ __global__ void __launch_bounds__(256) k_top_finish(CoreArgs A, uint32_t TX, uin
     uint32_t tau = A.taus[j];
     uint32_t dv = act ? A.dcore[(v << lk) + j] : INF;
     uint32_t beg = act ? A.down_off[v] : 0, end = act ? A.down_off[v + 1] : 0;
-    if (act && sub == 0) set_cell_flags(A.core_cell[v], A.core_ecc[v], dv, tau, j, K, A.fl_in, A.fl_out);
+    const uint32_t cell = act && sub == 0 ? A.core_cell[v] : NO_CELL;
+    const uint32_t ecc = cell != NO_CELL ? A.core_ecc[v] : 0u;
+    store_vertex_masks(act, v, cell, ecc, dv, tau, j, sub, lk, lgs, A.vin, A.vout);
     const uint2 *__restrict__ darc = A.down_arc;
     const uint32_t *__restrict__ dc = A.dcore;
     auto arc = [&](uint32_t e) { return darc[e]; };
@@ -272,7 +271,7 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     uint32_t j = t & (K - 1), sub = (t >> lk) & (S - 1);
     bool act = v < vend;
     uint32_t tau = A.taus[j];
-    uint32_t init = INF, beg = 0, end = 0, cell = NO_CELL, ecc = 0, fw = 0, seen_in = 0, seen_out = 0;
+    uint32_t init = INF, beg = 0, end = 0, cell = NO_CELL, ecc = 0;
     if (act) {
         beg = A.down_off[v];
         end = A.down_off[v + 1];
@@ -280,11 +279,6 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
         if (sub == 0) {
             cell = A.core_cell[v];
             ecc = A.core_ecc[v];
-            if (cell != NO_CELL) {
-                fw = (cell >> 5) * K + j;   // the k lanes' words of one cell group are contiguous
-                seen_in = A.fl_in[fw];
-                seen_out = A.fl_out[fw];
-            }
         }
         if (s != NO_SLOT) init = A.uval[(s << lk) + j];
     }
@@ -294,10 +288,8 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     auto lab = [&](uint32_t tl) { return dc[(tl << lk) + j]; };
     bool any_in = false, any_out = false;
     uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, any_in, any_out);
-    if (act && sub == 0) {
-        A.dcore[(v << lk) + j] = dv;
-        set_cell_flags_seen(cell, ecc, dv, tau, fw, seen_in, seen_out, A.fl_in, A.fl_out);
-    }
+    if (act && sub == 0) A.dcore[(v << lk) + j] = dv;
+    store_vertex_masks(act, v, cell, ecc, dv, tau, j, sub, lk, lgs, A.vin, A.vout);
     extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
 }
 
@@ -316,36 +308,49 @@ k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
     core_item(A, blockIdx.x * blockDim.x + threadIdx.x, ls, vbeg, vend);
 }
 
-// Active cells of a batch and, per cell, the lanes for which it is active (a 64-bit mask;
-// the flag rule of the cell-restricted sweep, or every real lane in plain mode, which passes
-// all_cells = 1; padding lanes have no source cell and are never active).  The lanes of a
-// cell are cut into work items of at most G = 1 << lg lanes: item c << 6 | q covers the
-// lanes of rank [qG, qG + G) in the mask.  A cell's items are consecutive in the list.
-__global__ void k_active_cells(const uint32_t *__restrict__ fl_in, const uint32_t *__restrict__ fl_out,
-                               uint32_t kpow2, const uint8_t *__restrict__ uncovered,
-                               const uint32_t *__restrict__ cell_off, const uint32_t *__restrict__ src_cell,
-                               uint32_t k, uint32_t num_cells, uint32_t all_cells, uint32_t lg,
-                               uint64_t *__restrict__ cmask, uint32_t *__restrict__ list,
-                               uint32_t *__restrict__ items, uint32_t *__restrict__ counters) {
-    uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+// Lanes for which each cell is active, one wavefront per cell: the flag rule of the
+// cell-restricted sweep, i and (o or uncovered), or the cell holds the lane's source, with i
+// and o the ORs of the lane masks of the cell's core vertices (cell_core lists them); in
+// plain mode (all_cells = 1) every real lane.  Padding lanes have no source cell and are
+// never active.
+__global__ void k_cell_masks(const uint32_t *__restrict__ cell_core_off, const uint32_t *__restrict__ cell_core,
+                             const uint64_t *__restrict__ vin, const uint64_t *__restrict__ vout,
+                             const uint8_t *__restrict__ uncovered, const uint32_t *__restrict__ cell_off,
+                             const uint32_t *__restrict__ src_cell, uint32_t k, uint32_t num_cells,
+                             uint32_t all_cells, uint64_t *__restrict__ cmask) {
+    const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = __lane_id();
+    if (c >= num_cells) return;   // uniform over the wavefront
+    const uint32_t sc = lane < k ? src_cell[lane] : NO_CELL;
+    const uint64_t real = __ballot(sc != NO_CELL), src = __ballot(sc == c);
     uint64_t m = 0;
-    if (c < num_cells && cell_off[c + 1] > cell_off[c]) {
-        const uint32_t bit = 1u << (c & 31u);
-        for (uint32_t j = 0; j < k; ++j) {
-            const uint32_t sc = src_cell[j];
-            bool act = false;
-            if (sc != NO_CELL) {
-                if (all_cells) {
-                    act = true;
-                } else {
-                    uint32_t w = (c >> 5) * kpow2 + j;
-                    bool i_ = fl_in[w] & bit, o_ = fl_out[w] & bit;
-                    act = (i_ && (o_ || uncovered[c])) || sc == c;
-                }
+    if (cell_off[c + 1] > cell_off[c]) {
+        if (all_cells) {
+            m = real;
+        } else {
+            uint64_t in = 0, out = 0;
+            for (uint32_t p = cell_core_off[c] + lane; p < cell_core_off[c + 1]; p += 64) {
+                const uint32_t v = cell_core[p];
+                in |= vin[v];
+                out |= vout[v];
             }
-            if (act) m |= 1ull << j;
+            for (uint32_t o = 32; o > 0; o >>= 1) {
+                in |= (uint64_t)__shfl_xor((unsigned long long)in, (int)o);
+                out |= (uint64_t)__shfl_xor((unsigned long long)out, (int)o);
+            }
+            m = ((in & (uncovered[c] ? real : out)) | src) & real;
         }
     }
+    if (lane == 0) cmask[c] = m;
+}
+
+// Active cells (nonzero lane mask) in a list, and work items: the lanes of a cell are cut into
+// items of at most G = 1 << lg lanes; item c << 6 | q covers the lanes of rank [qG, qG + G) in
+// the mask.  A cell's items are consecutive in the item list.
+__global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_cells, uint32_t lg,
+                               uint32_t *__restrict__ list, uint32_t *__restrict__ items,
+                               uint32_t *__restrict__ counters) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t m = c < num_cells ? cmask[c] : 0ull;
     const bool act = m != 0;
     const uint32_t nch = act ? (uint32_t(__popcll(m)) + (1u << lg) - 1u) >> lg : 0u;
     const uint64_t amask = __ballot(act);
@@ -366,7 +371,6 @@ __global__ void k_active_cells(const uint32_t *__restrict__ fl_in, const uint32_
     lbase = __shfl(lbase, 0);
     ibase = __shfl(ibase, 0);
     if (act) {
-        cmask[c] = m;
         list[lbase + (uint32_t)__popcll(amask & ((1ull << lane) - 1ull))] = c;
         const uint32_t first = ibase + incl - nch;
         for (uint32_t q = 0; q < nch; ++q) items[first + q] = (c << 6) | q;
@@ -943,6 +947,19 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if (co.empty()) co.assign(1, n);
     if ((r = dev_alloc_copy(&d_cell_off, co, bytes))) return r;
     if ((r = dev_alloc_copy(&d_uncovered, P.uncovered, bytes))) return r;
+    {
+        // core positions of each cell, grouped by cell (read by the cell-mask kernel)
+        std::vector<uint32_t> off(size_t(num_cells) + 1, 0), lst;
+        for (uint32_t v = 0; v < n_core; ++v)
+            if (P.core_cell[v] < num_cells) off[P.core_cell[v] + 1]++;
+        for (uint32_t c = 0; c < num_cells; ++c) off[c + 1] += off[c];
+        lst.resize(off[num_cells]);
+        std::vector<uint32_t> at(off.begin(), off.end() - 1);
+        for (uint32_t v = 0; v < n_core; ++v)
+            if (P.core_cell[v] < num_cells) lst[at[P.core_cell[v]]++] = v;
+        if ((r = dev_alloc_copy(&d_cell_core_off, off, bytes))) return r;
+        if ((r = dev_alloc_copy(&d_cell_core, lst, bytes))) return r;
+    }
     core_entries = P.down_off[n_core];
 
     // cell blobs: local entry offsets, local level bounds, sorted distinct core tails, and
@@ -1058,6 +1075,7 @@ void DevGraph::release() {
     main.release();
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
+                    d_cell_core_off, d_cell_core,
                     d_table, d_blob, d_cblob, d_cmeta};
     for (void *p : ptrs) if (p) hipFree(p);
     device = -1;
@@ -1089,9 +1107,8 @@ static int ensure(void **p, size_t &have, size_t need) {
 size_t DevGraph::ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const {
     uint32_t K = 1;
     while (K < k) K <<= 1;
-    size_t flag_words = std::max<uint32_t>(1, (num_cells + 31) / 32);
-    return size_t(n_core) * K * 4 + size_t(n) * 4 + upward_entries * (K + 3) * 4 + 2 * flag_words * K * 4 +
-           size_t(num_cells) * 4 + 2 * cap * 8 + (1 << 20);
+    return size_t(n_core) * K * 4 + size_t(n) * 4 + upward_entries * (K + 3) * 4 + size_t(n_core) * 16 +
+           size_t(num_cells) * (3 + MAX_LANES) * 4 + 2 * cap * 8 + (1 << 20);
 }
 
 int DevGraph::run(SweepCtx &C, const RunArgs &A, RunResult &R) {
@@ -1121,7 +1138,6 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     }
     for (uint32_t j = 0; j < K; ++j) xptr[j + 1] += xptr[j];
     const uint32_t nu = uint32_t(spos.size()), nx = uint32_t(xpos.size());
-    const uint32_t flag_words = std::max<uint32_t>(1, (num_cells + 31) / 32);
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
     int r;
@@ -1141,7 +1157,8 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     }
     const uint32_t xcap = C.xcap;
     if ((r = ensure((void **)&B.d_taus, B.sz_taus, 2 * K * 4))) return r;
-    if ((r = ensure((void **)&B.d_flags, B.sz_flags, size_t(2) * flag_words * K * 4))) return r;
+    // per core vertex: lanes in range, lanes whose range may leave the vertex's cell
+    if ((r = ensure((void **)&B.d_flags, B.sz_flags, size_t(std::max(1u, n_core)) * 16))) return r;
     if ((r = ensure((void **)&B.d_list, B.sz_list, size_t(std::max(1u, num_cells)) * (3 + MAX_LANES) * 4)))
         return r;
     if ((r = ensure((void **)&B.d_counters, B.sz_counters, 64))) return r;
@@ -1183,7 +1200,6 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     if (nx) HIPCHK(hipMemcpyAsync((void *)d_xval, hx + K + 1 + nx, size_t(nx) * 4, hipMemcpyHostToDevice, s));
     const uint32_t *d_upos = B.d_uin, *d_ulane = B.d_uin + nu, *d_ulab = B.d_uin + 2 * size_t(nu);
     // clear flags and counters with fill kernels (no memset nodes, so the sequence can be captured)
-    k_fill<<<dim3(64), dim3(256), 0, s>>>(B.d_flags, 0u, uint64_t(2) * flag_words * K);
     k_fill<<<dim3(1), dim3(64), 0, s>>>(B.d_counters, 0u, 16);
     if (A.want_dist) k_fill<<<dim3(2048), dim3(256), 0, s>>>(B.d_dist, INF, uint64_t(n) * K);
     if (nu) {
@@ -1193,14 +1209,14 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         k_uset_claim<<<dim3(g), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
         k_uset_write<<<dim3(g), dim3(256), 0, s>>>(B.d_uslot, d_upos, d_ulane, d_ulab, B.d_uval, nu, lk);
     }
-    uint32_t *fl_in = B.d_flags, *fl_out = B.d_flags + size_t(flag_words) * K;
+    uint64_t *vin = reinterpret_cast<uint64_t *>(B.d_flags), *vout = vin + n_core;
     // counters: edges emitted, active cells, work items; the list buffer holds the cells' lane
     // masks, the active cells and the work items
     uint32_t *out_count = B.d_counters, *n_items = B.d_counters + 2;
     uint64_t *d_cmask = reinterpret_cast<uint64_t *>(B.d_list);
     uint32_t *d_clist = B.d_list + 2 * size_t(num_cells), *d_items = d_clist + num_cells;
     CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_perm, d_core_cell, d_core_ecc,
-                d_taus, fl_in, fl_out, flag_words, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk};
+                d_taus, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk};
     const bool prof_on = C.prof.on;
     // the device sweep (table, core levels, active cells, cell sweep) has only per-context
     // kernel arguments; with use_graph it is captured once per signature and replayed
@@ -1276,9 +1292,11 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         }
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
         if (num_cells > 0) {
-            k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(
-                fl_in, fl_out, K, d_uncovered, d_cell_off, d_src, K, num_cells, A.mode_plain ? 1u : 0u, cell_lg,
-                d_cmask, d_clist, d_items, B.d_counters);
+            k_cell_masks<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(
+                d_cell_core_off, d_cell_core, vin, vout, d_uncovered, d_cell_off, d_src, K, num_cells,
+                A.mode_plain ? 1u : 0u, d_cmask);
+            k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(d_cmask, num_cells, cell_lg, d_clist,
+                                                                              d_items, B.d_counters);
             lg = cell_lg;
             CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
                         d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,

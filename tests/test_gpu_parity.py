@@ -181,6 +181,41 @@ def test_road1m_config():
         check_query(G, orc, s, tau)
 
 
+@pytest.mark.slow
+@pytest.mark.timeout(1500)
+def test_road18m_benchmark_batch_sampled():
+    """The benchmark's workload at full size in the benchmark's launch configuration: one batch
+    of its first 64 queries (cells mode, default tuning); sampled lanes equal the oracle exactly,
+    two lanes equal single queries in both modes, every lane's output is sorted, unique and in
+    range."""
+    import os
+
+    name = "road18m"
+    cfg = synth.CONFIGS[name]
+    g = synth.config_graph(name)
+    say(f"{name}: n={g.n} m={g.m}; preprocessing or loading")
+    cache = os.environ.get("ISO_CACHE", "/tmp/iso_cache")
+    os.makedirs(cache, exist_ok=True)
+    G = iso.Graph.from_synth(g, num_cells=cfg["cells"], device=0,
+                             prep_path=os.path.join(cache, f"{name}-c{cfg['cells']}-v1.prep"), verbose=True)
+    src, tau = synth.config_queries(name, 64)
+    out = G.query_batch(src, tau, iso.MODE_CELLS)
+    say(f"batch done: {sum(len(o) for o in out)} edges")
+    for j, e in enumerate(out):
+        assert e.shape[1] == 2 and (e < g.n).all()
+        if len(e) > 1:
+            key = e[:, 0].astype(np.uint64) << np.uint64(32) | e[:, 1].astype(np.uint64)
+            assert (np.diff(key) > 0).all(), f"lane {j} not sorted and unique"
+    for j in (0, 63):
+        for mode in (iso.MODE_CELLS, iso.MODE_PLAIN):
+            np.testing.assert_array_equal(G.query(int(src[j]), int(tau[j]), mode), out[j], err_msg=f"lane {j}")
+    orc = Oracle.from_graph(g)
+    for j in (0, 21, 42, 63):
+        say(f"oracle lane {j} (tau {int(tau[j])} ms)")
+        want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
+        np.testing.assert_array_equal(out[j], want, err_msg=f"lane {j}")
+
+
 def _identical_across_tuning(road50k, combos):
     g, orc, G = road50k
     src, tau = synth.batch_queries(g.n, 24, seed=77, lo_min=1, hi_min=120)
