@@ -155,7 +155,7 @@ int iso_last_query_stats(const iso_graph *g, iso_query_stats *stats);
 
 /*
  * Tuning knobs of the device sweep (chosen by the autotuner; when never set:
- * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 0).  lanes_per_launch: queries per sweep in
+ * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 1).  lanes_per_launch: queries per sweep in
  * iso_query_batch (1..64); block: threads per workgroup of the core level
  * kernel (64..1024, multiple of 64); cell_lds_kb: LDS budget of one cell
  * workgroup in KiB (16..160), which sets how many queries' labels a cell

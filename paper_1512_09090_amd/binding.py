@@ -278,7 +278,7 @@ class Graph:
         _check(lib().iso_last_query_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in QueryStats._fields_}
 
-    def set_tuning(self, lanes_per_launch=64, block=256, cell_lds_kb=64, use_graph=1, core_mode=0, cell_stage=0):
+    def set_tuning(self, lanes_per_launch=64, block=256, cell_lds_kb=64, use_graph=1, core_mode=0, cell_stage=1):
         t = Tuning(lanes_per_launch, block, cell_lds_kb, use_graph, core_mode, cell_stage)
         _check(lib().iso_set_tuning(self._h, C.byref(t)))
 

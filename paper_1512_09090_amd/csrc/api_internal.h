@@ -142,7 +142,7 @@ struct iso_graph {
     int threads = 1;
     std::atomic<bool> busy{false};
     iso_query_stats last{};
-    iso_tuning tuning{64, 256, 64, 1, 0, 0};   // the autotuner's choice on an 18M-vertex road graph
+    iso_tuning tuning{64, 256, 64, 1, 0, 1};   // the autotuner's choice on an 18M-vertex road graph
     UpwardGraph upg;                // packed upward graph
     std::vector<UpwardSearch> up;   // one workspace per host thread
     size_t out_cap = 1 << 20;

@@ -62,22 +62,6 @@ __device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t tail, uint3
     return (uint64_t(lane) << 58) | (uint64_t(tail) << 29) | uint64_t(head);
 }
 
-// Wavefront-aggregated append; every lane of the wavefront must call it.
-__device__ __forceinline__ void emit_wave(bool pred, uint64_t key, uint64_t *__restrict__ out,
-                                          uint32_t *__restrict__ counter, uint32_t cap) {
-    uint64_t mask = __ballot(pred);
-    if (mask == 0) return;
-    uint32_t lane = __lane_id();
-    int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (pred) {
-        uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-        if (idx < cap) out[idx] = key;
-    }
-}
-
 // Sorted keys -> (tail, head) pairs, and the first position of every lane: lane_off[l] = the
 // first i whose lane is >= l (lane_off is filled with the key count beforehand).
 __global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *__restrict__ pairs,
@@ -145,19 +129,27 @@ struct CoreArgs {
     uint32_t out_cap, lane_base, lk;
 };
 
+// Per (vertex, lane, sub-lane): bit k of `in` / `flag` tells whether the sub-lane's k-th entry
+// (beg + sub + k * S) has its tail in range / is flagged, for k < 32; `over` marks sub-lanes
+// with more than 32 entries.
+struct EntryBits {
+    uint32_t in = 0, flag = 0;
+    bool over = false;
+};
+
 // One core vertex v for lane j, sub-lane `sub` of S (= 1 << ls): partial minimum over
 // entries beg+sub, beg+sub+S, ...; LAB(tail) gives the tail's label for lane j.  The
 // partial minima are combined across the S sub-lanes (lanes K, 2K, ... apart).  Returns
-// the final label; any_in / any_out record whether a flagged entry of this sub-lane has
-// its tail in / out of range (only then can it straddle).
+// min(init, the minimum); eb records which entries can straddle tau once the label is known.
 template <class ARC, class LAB>
 __device__ __forceinline__ uint32_t relax_group(ARC arc, LAB lab, uint32_t beg, uint32_t end, uint32_t sub,
                                                 uint32_t S, uint32_t K, uint32_t init, uint32_t tau,
-                                                bool &any_in, bool &any_out) {
+                                                EntryBits &eb) {
     uint32_t m = INF;
     // chunks of up to 8 entries: every entry load of a chunk is issued, then every label load,
     // so a vertex of ordinary degree costs two memory latencies instead of two per entry
-    for (uint32_t e = beg + sub; e < end; e += 8 * S) {
+    uint32_t k = 0;
+    for (uint32_t e = beg + sub; e < end; e += 8 * S, k += 8) {
         uint2 a[8];
         uint32_t l[8];
 #pragma unroll
@@ -167,33 +159,94 @@ __device__ __forceinline__ uint32_t relax_group(ARC arc, LAB lab, uint32_t beg, 
 #pragma unroll
         for (uint32_t u = 0; u < 8; ++u) {
             m = min(m, sat_add(l[u], a[u].y));
-            if (a[u].x & FLAGS) { if (l[u] <= tau) any_in = true; else any_out = true; }
+            if (k + u < 32) {
+                if (a[u].x & FLAGS) eb.flag |= 1u << (k + u);
+                if (l[u] <= tau) eb.in |= 1u << (k + u);
+            } else if (e + u * S < end) {
+                eb.over = true;
+            }
         }
     }
     for (uint32_t o = K; o < K * S; o <<= 1) m = min(m, (uint32_t)__shfl_xor((int)m, (int)o));
     return min(init, m);
 }
 
-// Isochrone edges at core vertex v (label dv final): only sub-lanes that saw a possible
-// straddle walk their entries again.  Wavefront-uniform loop (emit_wave inside).
+// Block-wide list of output keys in LDS (count in *s_n, capacity CORE_KEYS); written out with
+// one output reservation per workgroup.
+constexpr uint32_t CORE_KEYS = 1024;
+
+// Wavefront-aggregated append of a key to the block's list; a key that finds the list full is
+// written out at once.  Every lane of the wavefront must call it.
+__device__ __forceinline__ void push_key(bool pred, uint64_t key, uint64_t *s_keys, uint32_t *s_n,
+                                         const CoreArgs &A) {
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return;
+    const uint32_t lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(s_n, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const uint32_t k = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (k < CORE_KEYS) {
+            s_keys[k] = key;
+        } else {
+            const uint32_t idx = atomicAdd(A.out_count, 1u);
+            if (idx < A.out_cap) A.out_keys[idx] = key;
+        }
+    }
+}
+
+// Isochrone edges at core vertex v (label dv final) for lane j: the flagged entries of this
+// sub-lane whose tails lie on the other side of tau, from the bits recorded while relaxing
+// (entry loads and perm lookups only for those); sub-lanes with more than 32 entries walk
+// theirs again.  Wavefront-uniform loops.
 template <class ARC, class LAB>
 __device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &A, bool act, uint32_t v,
                                               uint32_t beg, uint32_t end, uint32_t sub, uint32_t S,
-                                              uint32_t j, uint32_t dv, uint32_t tau, bool any_in, bool any_out) {
-    bool vin = dv <= tau;
-    bool need = act && (vin ? any_out : any_in);
-    uint32_t e = need ? beg + sub : 0, stop = need ? end : 0;
-    uint32_t ov = need ? A.perm[v] : 0u;
+                                              uint32_t j, uint32_t dv, uint32_t tau, const EntryBits &eb,
+                                              uint64_t *s_keys, uint32_t *s_n) {
+    const bool vin = dv <= tau;
+    uint32_t st = act && !eb.over ? (eb.flag & (vin ? ~eb.in : eb.in)) : 0u;
+    const bool walk = act && eb.over;
+    const uint32_t lane = A.lane_base + j;
+    const uint32_t ov = (st != 0 || walk) ? A.perm[v] : 0u;
+    while (__any(st != 0)) {
+        const bool have = st != 0;
+        const uint32_t k = have ? uint32_t(__ffs(st) - 1) : 0u;
+        st &= st - 1u;
+        const uint2 a = have ? arc(beg + sub + k * S) : make_uint2(0u, 0u);
+        const uint32_t ot = have ? A.perm[a.x & TAIL_MASK] : 0u;
+        push_key(have && (a.x & FLAG_FWD), edge_key(lane, ot, ov), s_keys, s_n, A);
+        push_key(have && (a.x & FLAG_REV), edge_key(lane, ov, ot), s_keys, s_n, A);
+    }
+    uint32_t e = walk ? beg + sub : 0, stop = walk ? end : 0;
     while (__any(e < stop)) {
-        bool have = e < stop;
-        uint2 a = have ? arc(e) : make_uint2(0u, 0u);
-        uint32_t tl = a.x & TAIL_MASK;
-        bool st = have && (a.x & FLAGS) && ((lab(tl) <= tau) != vin);
-        uint32_t ot = st ? A.perm[tl] : 0u;
-        emit_wave(st && (a.x & FLAG_FWD), edge_key(A.lane_base + j, ot, ov), A.out_keys, A.out_count, A.out_cap);
-        emit_wave(st && (a.x & FLAG_REV), edge_key(A.lane_base + j, ov, ot), A.out_keys, A.out_count, A.out_cap);
+        const bool have = e < stop;
+        const uint2 a = have ? arc(e) : make_uint2(0u, 0u);
+        const uint32_t tl = a.x & TAIL_MASK;
+        const bool str = have && (a.x & FLAGS) && ((lab(tl) <= tau) != vin);
+        const uint32_t ot = str ? A.perm[tl] : 0u;
+        push_key(str && (a.x & FLAG_FWD), edge_key(lane, ot, ov), s_keys, s_n, A);
+        push_key(str && (a.x & FLAG_REV), edge_key(lane, ov, ot), s_keys, s_n, A);
         e += S;
     }
+}
+
+// Start and end of a core kernel's block-wide key list (every thread calls both).
+__device__ __forceinline__ void keys_begin(uint32_t *s_n) {
+    if (threadIdx.x == 0) *s_n = 0;
+    __syncthreads();
+}
+__device__ __forceinline__ void keys_end(uint64_t *s_keys, uint32_t *s_n, uint32_t *s_base, const CoreArgs &A) {
+    __syncthreads();
+    const uint32_t n = min(*s_n, CORE_KEYS);   // no key is added any more
+    if (n == 0) return;
+    if (threadIdx.x == 0) *s_base = atomicAdd(A.out_count, n);
+    __syncthreads();
+    const uint32_t base = *s_base;
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+        if (base + k < A.out_cap) A.out_keys[base + k] = s_keys[k];
 }
 
 // Top of the core as a table: X = positions [0, TX) (the top levels, where the
@@ -240,6 +293,9 @@ k_top_table(const uint32_t *__restrict__ D, uint32_t TX, const uint32_t *__restr
 // sub-lanes per (vertex, lane) split the entry list: the first pass over the entries finds
 // which sub-lanes can hold a straddling arc, the second emits them.
 __global__ void __launch_bounds__(256) k_top_finish(CoreArgs A, uint32_t TX, uint32_t ls) {
+    __shared__ uint64_t s_keys[CORE_KEYS];
+    __shared__ uint32_t s_n, s_base;
+    keys_begin(&s_n);
     const uint32_t lk = A.lk, K = 1u << lk, S = 1u << ls, lgs = lk + ls;
     uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t v = t >> lgs, j = t & (K - 1), sub = (t >> lk) & (S - 1);
@@ -254,18 +310,16 @@ __global__ void __launch_bounds__(256) k_top_finish(CoreArgs A, uint32_t TX, uin
     const uint32_t *__restrict__ dc = A.dcore;
     auto arc = [&](uint32_t e) { return darc[e]; };
     auto lab = [&](uint32_t tl) { return dc[(tl << lk) + j]; };
-    bool any_in = false, any_out = false;
-    for (uint32_t e = beg + sub; e < end; e += S) {
-        uint2 a = arc(e);
-        if (a.x & FLAGS) { if (lab(a.x & TAIL_MASK) <= tau) any_in = true; else any_out = true; }
-    }
-    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
+    EntryBits eb;
+    relax_group(arc, lab, beg, end, sub, S, K, INF, tau, eb);   // the labels are final: only the bits count
+    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, eb, s_keys, &s_n);
+    keys_end(s_keys, &s_n, &s_base, A);
 }
 
 // One item of a core level: thread t of the level serves vertex vbeg + (t >> (lk + ls)),
 // lane t & (K - 1), sub-lane (t >> lk) & (S - 1).  All lanes of a wavefront must call it.
 __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_t ls, uint32_t vbeg,
-                                          uint32_t vend) {
+                                          uint32_t vend, uint64_t *s_keys, uint32_t *s_n) {
     const uint32_t lk = A.lk, K = 1u << lk, S = 1u << ls, lgs = lk + ls;
     uint32_t v = vbeg + (t >> lgs);
     uint32_t j = t & (K - 1), sub = (t >> lk) & (S - 1);
@@ -286,11 +340,11 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     const uint32_t *__restrict__ dc = A.dcore;
     auto arc = [&](uint32_t e) { return darc[e]; };
     auto lab = [&](uint32_t tl) { return dc[(tl << lk) + j]; };
-    bool any_in = false, any_out = false;
-    uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, any_in, any_out);
+    EntryBits eb;
+    uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, eb);
     if (act && sub == 0) A.dcore[(v << lk) + j] = dv;
     store_vertex_masks(act, v, cell, ecc, dv, tau, j, sub, lk, lgs, A.vin, A.vout);
-    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, any_in, any_out);
+    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, eb, s_keys, s_n);
 }
 
 // Sub-lanes per vertex for a level: enough to cover its mean in-degree, at most 8, and the
@@ -305,7 +359,11 @@ __host__ __device__ __forceinline__ uint32_t level_ls(uint32_t vertices, uint32_
 // One core level: positions [vbeg, vend).
 __global__ void __launch_bounds__(1024)
 k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
-    core_item(A, blockIdx.x * blockDim.x + threadIdx.x, ls, vbeg, vend);
+    __shared__ uint64_t s_keys[CORE_KEYS];
+    __shared__ uint32_t s_n, s_base;
+    keys_begin(&s_n);
+    core_item(A, blockIdx.x * blockDim.x + threadIdx.x, ls, vbeg, vend, s_keys, &s_n);
+    keys_end(s_keys, &s_n, &s_base, A);
 }
 
 // Lanes for which each cell is active, one wavefront per cell: the flag rule of the
