@@ -283,6 +283,18 @@ def main():
     qps_plain = max(2, args.steps // 4) * lanes / total_p
     log(f"plain batched: {qps_plain:.1f} queries/s; profile {prof_plain}")
 
+    # one call with 8 sweeps: consecutive sweeps overlap (host upward searches and result copies of
+    # one sweep run during the device work of the next)
+    big = 8 * lanes
+    idx = np.arange(big) % len(src)
+    G.query_batch(src[idx], tau[idx], iso.MODE_CELLS)
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        G.query_batch(src[idx], tau[idx], iso.MODE_CELLS)
+    qps_pipe = reps * big / (time.perf_counter() - t0)
+    log(f"pipelined batched ({big} queries per call): {qps_pipe:.1f} queries/s")
+
     # single-query latency (one query per call)
     lat = {}
     single_qps = {}
@@ -340,6 +352,7 @@ def main():
         "latency_ms": lat,
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
+        "batched_pipelined_qps": {"queries_per_call": big, "value": round(qps_pipe, 2)},
         "last_batch": batch_stats,
         "step_ms_p50": round(1000 * percentile(times, 50), 3),
         "step_ms_p99": round(1000 * percentile(times, 99), 3),

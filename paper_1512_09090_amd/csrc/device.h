@@ -128,6 +128,8 @@ struct DevGraph {
     int cell_occupancy(bool staged, size_t lds, uint32_t &per_cu);
     uint64_t bytes = 0;
     SweepCtx main;   // context of the direct query calls
+    SweepCtx aux;    // second context of a batch call, so that consecutive sweeps overlap (made on first use)
+    bool aux_ready = false;
     // per-cell sizes for the byte accounting
     std::vector<uint32_t> cell_cnt, cell_words, cell_core_refs;
     std::vector<uint64_t> cell_entries;

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <unordered_map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -343,19 +344,36 @@ int iso_graph_get_info(const iso_graph *g, iso_graph_info *info) {
     return ISO_OK;
 }
 
+// k queries in sweeps of up to lanes_per_launch lanes.  With more than one sweep, two sweep
+// contexts alternate: the host upward searches and the launch of sweep i overlap the device
+// work of sweep i - 1, whose edges are then collected (sequential while profiling, so that
+// the phase timings stay per sweep).
 static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_t *tau, int mode,
                       iso_edge **edges, size_t *offsets) {
     double t0 = now_ms();
     g->last = iso_query_stats{};
     const uint32_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
-    // every launch's edges are copied from the device straight into the result buffer, a
-    // pinned pool block (grown by moving to a larger block when a later launch needs room)
+    const size_t nsweeps = (k + per - 1) / per;
+    isodev::DevGraph &D = g->D;
+    const bool overlap = nsweeps > 1 && !D.main.prof.on;
+    if (overlap && !D.aux_ready) {
+        if (D.aux.create(D.device)) return fail(ISO_EDEVICE, "creating the second sweep context failed");
+        D.aux_ready = true;
+    }
+    // every sweep's edges are copied from the device straight into the result buffer, a
+    // pinned pool block (grown by moving to a larger block when a later sweep needs room)
     EdgeBuf out;
     out.pinned = true;
     size_t cap = 0;
     offsets[0] = 0;
-    for (size_t b = 0; b < k; b += per) {
-        uint32_t lanes = uint32_t(std::min<size_t>(per, k - b));
+    struct Sweep {
+        isodev::RunArgs A;
+        isodev::SweepCtx *C = nullptr;
+        size_t b = 0;
+        uint32_t lanes = 0;
+        std::vector<uint32_t> settled;
+    };
+    auto collect = [&](Sweep &W) -> int {
         isodev::RunResult R;
         R.sink = [&](size_t n) -> uint32_t * {
             if (out.n + n > cap) {
@@ -369,10 +387,67 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
             }
             return reinterpret_cast<uint32_t *>(out.p + out.n);
         };
-        int r = run_lanes(g, src + b, tau + b, lanes, mode == ISO_MODE_PLAIN, false, R);
+        const double tw = now_ms();
+        int r = D.finish(*W.C, R);
+        for (int attempt = 0; !r && R.overflow && attempt < 8; ++attempt) {   // grow the edge buffer, sweep again
+            g->out_cap = std::max<size_t>(g->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
+            W.A.out_cap = g->out_cap;
+            r = D.launch(*W.C, W.A);
+            if (!r) r = D.finish(*W.C, R);
+        }
         if (r) return r;
-        for (uint32_t j = 0; j < lanes; ++j) offsets[b + j + 1] = out.n + R.lane_off[j + 1];
+        if (R.overflow) return fail(ISO_ENOMEM, "edge buffer overflow");
+        for (uint32_t j = 0; j < W.lanes; ++j) offsets[W.b + j + 1] = out.n + R.lane_off[j + 1];
         out.n += R.count;
+        g->last.lanes += W.lanes;
+        g->last.active_cells += R.active_cells;
+        for (uint32_t s : W.settled) g->last.upward_settled += s;
+        g->last.t_device_ms += now_ms() - tw - R.t_result_ms;
+        g->last.t_sort_ms += R.t_result_ms;
+        return ISO_OK;
+    };
+    std::unique_ptr<Sweep> prev;
+    auto drain = [&]() {   // leave a launched sweep's context idle after an error
+        if (!prev) return;
+        isodev::RunResult R;
+        D.finish(*prev->C, R);
+        prev.reset();
+    };
+    for (size_t i = 0; i < nsweeps; ++i) {
+        auto W = std::make_unique<Sweep>();
+        W->b = i * per;
+        W->lanes = uint32_t(std::min<size_t>(per, k - W->b));
+        W->C = overlap && (i & 1) ? &D.aux : &D.main;
+        W->settled.assign(W->lanes, 0);
+        const double tu = now_ms();
+        build_run_args(g, src + W->b, tau + W->b, W->lanes, mode == ISO_MODE_PLAIN, false, W->A, W->settled.data());
+        W->A.out_cap = g->out_cap;
+        g->last.t_upward_ms += now_ms() - tu;
+        int r = D.launch(*W->C, W->A);
+        if (r) {
+            drain();
+            return r;
+        }
+        if (prev) {
+            r = collect(*prev);
+            prev.reset();
+            if (r) {
+                prev = std::move(W);
+                drain();
+                return r;
+            }
+        }
+        prev = std::move(W);
+        if (!overlap) {   // one context: collect before the next sweep is launched
+            r = collect(*prev);
+            prev.reset();
+            if (r) return r;
+        }
+    }
+    if (prev) {
+        int r = collect(*prev);
+        prev.reset();
+        if (r) return r;
     }
     g->last.edges = out.n;
     if (!out.p) {   // no edges at all: a malloc'd placeholder

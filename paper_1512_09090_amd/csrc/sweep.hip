@@ -471,10 +471,31 @@ struct CellArgs {
 };
 
 constexpr uint32_t CELL_THREADS = 256;
-// Isochrone edges found in a cell are first collected in LDS as candidate words (entry
-// index e < 2^25 within the cell, lane slot j, direction) and written out in bulk.
+// Isochrone edges found in a cell are first collected in LDS as candidate words and written
+// out in bulk.  A word holds the internal head vertex i (12 bits; a cell has at most 4096
+// vertices), the entry's offset k among i's entries (13 bits), the lane slot j (6 bits) and
+// the direction (bit 31: the reverse arc).
 constexpr uint32_t CAND_CAP = 512;
-constexpr uint32_t CAND_E_BITS = 25;
+constexpr uint32_t CAND_K_MAX = 1u << 13;
+__device__ __forceinline__ uint32_t cand_word(uint32_t i, uint32_t k, uint32_t j, bool rev) {
+    return i | (k << 12) | (j << 25) | (uint32_t(rev) << 31);
+}
+
+// Bits of one vertex's first 32 entries, recorded while relaxing: tail in range, forward
+// original arc, reverse original arc; `over` marks vertices with more entries.
+struct CellBits {
+    uint32_t in = 0, fwd = 0, rev = 0;
+    bool over = false;
+    __device__ __forceinline__ void see(uint32_t k, uint32_t x, bool tail_in) {
+        if (k < 32) {
+            if (tail_in) in |= 1u << k;
+            if (x & FLAG_FWD) fwd |= 1u << k;
+            if (x & FLAG_REV) rev |= 1u << k;
+        } else {
+            over = true;
+        }
+    }
+};
 constexpr uint32_t CELL_BUF = 512;         // entries per LDS level buffer (two buffers)
 constexpr uint32_t CELL_REGS = CELL_BUF / CELL_THREADS;
 
@@ -485,19 +506,14 @@ __host__ __device__ __forceinline__ uint32_t cell_lds_words(uint32_t cnt, uint32
     return ((cnt + 1 + nl + 1 + 1u) & ~1u) + 4 * CELL_BUF + (labels << lg) + CAND_CAP + 4;
 }
 
-// Output key of a candidate: the entry's head is the internal vertex whose entry range holds e
-// (binary search of the LDS offsets), its tail a local index (internal or core reference).
+// Output key of a candidate: head = internal vertex i, tail = the local index in i's k-th entry
+// (internal or core reference), both mapped to original ids.
 template <class ENT, class REF>
 __device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, const uint32_t *s_off, uint32_t cnt,
                                              ENT ent, REF ref, uint32_t cb, uint64_t lanes, uint32_t q) {
-    const uint32_t e = word & ((1u << CAND_E_BITS) - 1u), j = (word >> CAND_E_BITS) & 63u;
-    uint32_t lo = 0, hi = cnt;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= e) lo = mid; else hi = mid;
-    }
-    const uint32_t lt = ent(e).x & LOCAL_MASK;
-    const uint32_t ov = A.perm[cb + lo];
+    const uint32_t i = word & 0xFFFu, k = (word >> 12) & (CAND_K_MAX - 1u), j = (word >> 25) & 63u;
+    const uint32_t lt = ent(s_off[i] + k).x & LOCAL_MASK;
+    const uint32_t ov = A.perm[cb + i];
     const uint32_t ot = A.perm[lt < cnt ? cb + lt : ref(lt - cnt)];
     const uint32_t lane = A.lane_base + nth_set_bit(lanes, (q << A.lg) + j);
     return (word >> 31) ? edge_key(lane, ov, ot) : edge_key(lane, ot, ov);
@@ -545,6 +561,41 @@ __device__ __forceinline__ void flush_cands(uint32_t n, uint32_t *s_cand, uint32
     __syncthreads();
     if (tid == 0) s_ctl[0] = 0;
     __syncthreads();
+}
+
+// Isochrone edges at internal vertex i (label dv final) for the thread's lane slot j: its
+// flagged entries whose tails lie on the other side of tau, from the bits recorded while
+// relaxing; a vertex with more than 32 entries walks them again (ENT gives an entry, and
+// s_lab the labels).  Candidates go to the LDS list.  Wavefront-uniform loops.
+template <class ENT, class REF>
+__device__ __forceinline__ void emit_cell_vertex(bool go, uint32_t i, uint32_t e0, uint32_t e1, uint32_t dv,
+                                                 uint32_t tau, const CellBits &b, uint32_t j, uint32_t lg,
+                                                 const uint32_t *s_lab, uint32_t *s_cand, uint32_t *s_ctl,
+                                                 const CellArgs &A, const uint32_t *s_off, uint32_t cnt, ENT ent,
+                                                 REF ref, uint32_t cb, uint64_t lanes, uint32_t q) {
+    const bool vin = dv <= tau;
+    const uint32_t str = go && !b.over ? (vin ? ~b.in : b.in) : 0u;
+    uint32_t sf = str & b.fwd, sr = str & b.rev;
+    while (__any((sf | sr) != 0)) {
+        const bool hf = sf != 0, hr = sr != 0;
+        const uint32_t kf = hf ? uint32_t(__ffs(sf) - 1) : 0u, kr = hr ? uint32_t(__ffs(sr) - 1) : 0u;
+        sf &= sf - 1u;
+        sr &= sr - 1u;
+        push_cand(hf, cand_word(i, kf, j, false), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        push_cand(hr, cand_word(i, kr, j, true), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+    }
+    uint32_t e = go && b.over ? e0 : 0u, ee = go && b.over ? e1 : 0u;
+    while (__any(e < ee)) {
+        const bool have = e < ee;
+        const uint2 x = have ? ent(e) : make_uint2(0u, 0u);
+        const uint32_t lt = x.x & LOCAL_MASK;
+        const bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
+        push_cand(st && (x.x & FLAG_FWD), cand_word(i, e - e0, j, false), s_cand, s_ctl, A, s_off, cnt, ent, ref,
+                  cb, lanes, q);
+        push_cand(st && (x.x & FLAG_REV), cand_word(i, e - e0, j, true), s_cand, s_ctl, A, s_off, cnt, ent, ref,
+                  cb, lanes, q);
+        ++e;
+    }
 }
 
 // End of level l of a work item: one barrier, after which every label of the level is final.
@@ -682,13 +733,13 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             bool act = i < bnd;
             uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
             uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
-            bool any_in = false, any_out = false;
+            CellBits bits;
             for (uint32_t e = e0; e < e1; ++e) {
                 uint32_t le = e - ebase;
                 uint2 x = le < CELL_BUF ? cur[le] : gent[e];
                 uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
                 dv = min(dv, sat_add(lt, x.y));
-                if (x.x & FLAGS) { if (lt <= tau) any_in = true; else any_out = true; }
+                bits.see(e - e0, x.x, lt <= tau);
             }
             if (act) {
                 s_lab[(i << lg) + j] = dv;
@@ -696,24 +747,8 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             }
             // isochrone edges at vertex i (its tails are on earlier levels or in the core) go to
             // the candidate list
-            bool vin = dv <= tau;
-            bool need = act && live && (vin ? any_out : any_in);
-            uint32_t e = need ? e0 : 0, ee = need ? e1 : 0;
-            while (__any(e < ee)) {
-                bool have = e < ee;
-                uint2 x = make_uint2(0u, 0u);
-                if (have) {
-                    uint32_t le = e - ebase;
-                    x = le < CELL_BUF ? cur[le] : gent[e];
-                }
-                uint32_t lt = x.x & LOCAL_MASK;
-                bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
-                const uint32_t word = e | (j << CAND_E_BITS);
-                push_cand(st && (x.x & FLAG_FWD), word, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
-                push_cand(st && (x.x & FLAG_REV), word | (1u << 31), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb,
-                          lanes, q);
-                ++e;
-            }
+            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
+                             ref, cb, lanes, q);
         }
         if (l + 1 < nl) {
 #pragma unroll
@@ -814,7 +849,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
             bool act = i < bnd;
             uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
             uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
-            bool any_in = false, any_out = false;
+            CellBits bits;
             // four entries at a time: their reads, then their tails' labels
             for (uint32_t e = e0; e < e1; e += 4) {
                 uint2 x[4];
@@ -827,27 +862,15 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
 #pragma unroll
                 for (uint32_t u = 0; u < 4; ++u) {
                     dv = min(dv, sat_add(lt[u], x[u].y));
-                    if (x[u].x & FLAGS) { if (lt[u] <= tau) any_in = true; else any_out = true; }
+                    if (e + u < e1) bits.see(e + u - e0, x[u].x, lt[u] <= tau);
                 }
             }
             if (act) {
                 s_lab[(i << lg) + j] = dv;
                 if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
             }
-            bool vin = dv <= tau;
-            bool need = act && live && (vin ? any_out : any_in);
-            uint32_t e = need ? e0 : 0, ee = need ? e1 : 0;
-            while (__any(e < ee)) {
-                bool have = e < ee;
-                uint2 x = have ? s_ent[e] : make_uint2(0u, 0u);
-                uint32_t lt = x.x & LOCAL_MASK;
-                bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
-                const uint32_t word = e | (j << CAND_E_BITS);
-                push_cand(st && (x.x & FLAG_FWD), word, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
-                push_cand(st && (x.x & FLAG_REV), word | (1u << 31), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb,
-                          lanes, q);
-                ++e;
-            }
+            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
+                             ref, cb, lanes, q);
         }
         level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
     }
@@ -1048,10 +1071,11 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
             set_error("a cell references too many vertices for 16-bit local indices");
             return -1;
         }
-        if (ne >= (1u << CAND_E_BITS)) {
-            set_error("a cell has 2^25 or more downward entries");
-            return -1;
-        }
+        for (uint32_t v = b; v < e; ++v)
+            if (P.down_off[v + 1] - P.down_off[v] >= CAND_K_MAX) {
+                set_error("a cell vertex has 8192 or more downward entries");
+                return -1;
+            }
         cell_cnt[c] = cnt;
         cell_core_refs[c] = nr;
         cell_entries[c] = ne;
@@ -1131,6 +1155,8 @@ void SweepCtx::release() {
 void DevGraph::release() {
     if (device < 0) return;
     main.release();
+    if (aux_ready) aux.release();
+    aux_ready = false;
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
