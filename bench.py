@@ -75,20 +75,23 @@ def serving(G, n, rates, duration, lanes, inflight):
     import synth
 
     out = []
+    warm = 0.5
     for rate in rates:
-        t, src, tau = synth.serving_trace(n, rate, duration, seed=15)
+        t, src, tau = synth.serving_trace(n, rate, duration + warm, seed=15)
         srv = iso.Server(G, max_lanes=lanes, max_inflight=inflight, mode=iso.MODE_CELLS)
         q = queue.Queue()
         lat, batch, done_at = [], [], [0.0]
 
         def collect():
             while True:
-                tk = q.get()
-                if tk is None:
+                item = q.get()
+                if item is None:
                     return
+                tk, counted = item
                 _, st = srv.wait(tk)
-                lat.append(st["t_total_ms"])
-                batch.append(st["batch_lanes"])
+                if counted:
+                    lat.append(st["t_total_ms"])
+                    batch.append(st["batch_lanes"])
                 done_at[0] = time.perf_counter()
 
         th = threading.Thread(target=collect)
@@ -99,14 +102,14 @@ def serving(G, n, rates, duration, lanes, inflight):
                 dt = t0 + t[i] - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
-                q.put(srv.submit(int(src[i]), int(tau[i])))
+                q.put((srv.submit(int(src[i]), int(tau[i])), t[i] >= warm))
         finally:
             q.put(None)
             th.join()
             stats = srv.stats()
             srv.close()
-        span = max(done_at[0] - t0, 1e-9)
-        r = {"offered_hz": rate, "requests": len(t), "completed_qps": round(len(lat) / span, 1),
+        span = max(done_at[0] - (t0 + warm), 1e-9)
+        r = {"offered_hz": rate, "requests": len(lat), "completed_qps": round(len(lat) / span, 1),
              "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
              "mean_batch": round(float(np.mean(batch)), 2), "sweeps": stats["sweeps"]}
         log(f"serving {r}")
@@ -157,39 +160,93 @@ def measured_traffic(phase):
 
 
 def cpu_baseline(g, src, tau, seconds, threads):
-    """The oracle (tau-bounded Dijkstra + edge rule) on this host, one query per thread."""
+    """The oracle on this host: throughput with one query per thread on `threads` threads (the
+    plain tau-bounded Dijkstra with the edge rule, and the paper's isoDijkstra), and the plain
+    oracle's single-thread latency; about `seconds` of wall time in total."""
     import oracle
 
     t0 = time.time()
     orc = oracle.Oracle.from_graph(g)
     workers = [oracle.OracleWorker(orc) for _ in range(threads)]
     log(f"cpu baseline: oracle graph built ({time.time() - t0:.1f}s), {threads} threads, ~{seconds}s budget")
-    nxt = [0]
-    done = []
-    lock = threading.Lock()
-    deadline = time.perf_counter() + seconds
 
-    def work(wk):
-        while True:
-            with lock:
-                if time.perf_counter() > deadline or nxt[0] >= len(src):
-                    return
-                j = nxt[0]
-                nxt[0] += 1
-            wk.isochrone(int(src[j]), int(tau[j]))
-            with lock:
-                done.append(j)
+    def throughput(method, budget, nthreads, start):
+        nxt, done, lock = [start], [], threading.Lock()
+        deadline = time.perf_counter() + budget
 
+        def work(wk):
+            while True:
+                with lock:
+                    if time.perf_counter() > deadline:
+                        return
+                    j = nxt[0] % len(src)
+                    nxt[0] += 1
+                a = time.perf_counter()
+                getattr(wk, method)(int(src[j]), int(tau[j]))
+                with lock:
+                    done.append(1000.0 * (time.perf_counter() - a))
+
+        t1 = time.perf_counter()
+        ths = [threading.Thread(target=work, args=(w,)) for w in workers[:nthreads]]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        return len(done) / (time.perf_counter() - t1), done
+
+    lat_budget, iso_budget = 0.25 * seconds, 0.25 * seconds
+    _, lat = throughput("isochrone", lat_budget, 1, 0)
+    qps, _ = throughput("isochrone", seconds - lat_budget - iso_budget, threads, 0)
+    iso_qps, _ = throughput("iso_dijkstra", iso_budget, threads, 0)
+    return {"value": qps, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"the benchmark's query list (tau uniform 10-240 min) from its start, one query per thread; "
+                      f"{seconds:.0f}s in total",
+            "single_thread_latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "queries": len(lat)},
+            "iso_dijkstra_qps": iso_qps}
+
+
+def lanes_sweep(G, src, tau, ks=(8, 16, 32, 64), count=256):
+    """Cells-mode throughput of iso_query_batch over `count` queries with k queries per sweep,
+    and the same pairs as sequential single plain-mode queries."""
+    import paper_1512_09090_amd as iso
+
+    keep = G.get_tuning()
+    out = {}
+    for k in ks:
+        G.set_tuning(**dict(keep, lanes_per_launch=k))
+        G.query_batch(src[:k], tau[:k], iso.MODE_CELLS)
+        t0 = time.perf_counter()
+        G.query_batch(src[:count], tau[:count], iso.MODE_CELLS)
+        out[str(k)] = round(count / (time.perf_counter() - t0), 1)
+    G.set_tuning(**keep)
     t0 = time.perf_counter()
-    ths = [threading.Thread(target=work, args=(w,)) for w in workers]
-    for t in ths:
-        t.start()
-    for t in ths:
-        t.join()
+    for j in range(count):
+        G.query(int(src[j]), int(tau[j]), iso.MODE_PLAIN)
+    out["sequential_single_plain"] = round(count / (time.perf_counter() - t0), 1)
+    return out
+
+
+def attainable_bandwidth(mib=1024, reps=5):
+    """GB/s of device-to-device copies (read + write bytes), the attainable HBM bandwidth."""
+    import ctypes as C
+
+    hip = C.CDLL("libamdhip64.so")
+    nbytes = int(mib) << 20
+    a, b = C.c_void_p(), C.c_void_p()
+    for p in (a, b):
+        if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
+            return None
+    hip.hipMemset(a, 1, C.c_size_t(nbytes))
+    hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3)
+    hip.hipDeviceSynchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3)
+    hip.hipDeviceSynchronize()
     el = time.perf_counter() - t0
-    return {"value": len(done) / el, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {len(done)} queries of the benchmark list (tau uniform 10-240 min), "
-                      f"one query per thread, {el:.1f}s wall"}
+    hip.hipFree(a)
+    hip.hipFree(b)
+    return 2.0 * reps * nbytes / el / 1e9
 
 
 def main():
@@ -209,9 +266,10 @@ def main():
     ap.add_argument("--save-tuning", default="", help="write the autotuner's result to this JSON file")
     ap.add_argument("--knobs", default="",
                     help="explicit tuning, e.g. lanes_per_launch=32,cell_lds_kb=24,cell_stage=0 (others default)")
-    ap.add_argument("--serve-rates", default="250,1000,2000,3000",
+    ap.add_argument("--serve-rates", default="100,500,1000,2000,5000",
                     help="offered Poisson rates (queries/s) for the serving section; empty to skip")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the queries-per-sweep comparison")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates profiler byte counters)")
     ap.add_argument("--cache-dir", default=os.environ.get("ISO_CACHE", "/tmp/iso_cache"))
@@ -328,9 +386,18 @@ def main():
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serve = {"mode": "cells", "max_lanes": lanes, "max_inflight": 2,
-                 "trace": f"Poisson arrivals, {args.serve_seconds:g}s per rate, uniform sources, "
-                          "tau log-uniform 5-300 min",
+                 "trace": f"Poisson arrivals, {args.serve_seconds:g}s per rate after 0.5s warm-up, uniform "
+                          "sources, tau log-uniform 5-300 min; latency = submit to result ready",
                  "rates": serving(G, info["n"], rates, args.serve_seconds, lanes, 2)}
+
+    sweep = None if args.no_sweep else lanes_sweep(G, src, tau)
+    if sweep:
+        log(f"queries per sweep: {sweep}")
+    bw = attainable_bandwidth()
+    if bw:
+        log(f"attainable bandwidth (device copy): {bw:.0f} GB/s")
+        roofline["attainable_gbs"] = round(bw, 1)
+        roofline["frac_of_attainable"] = round(achieved / bw, 4)
 
     cpu = None
     if not args.no_cpu:
@@ -353,6 +420,7 @@ def main():
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
         "batched_pipelined_qps": {"queries_per_call": big, "value": round(qps_pipe, 2)},
+        "queries_per_sweep_qps": sweep,
         "last_batch": batch_stats,
         "step_ms_p50": round(1000 * percentile(times, 50), 3),
         "step_ms_p99": round(1000 * percentile(times, 99), 3),

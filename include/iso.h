@@ -155,7 +155,8 @@ int iso_last_query_stats(const iso_graph *g, iso_query_stats *stats);
 
 /*
  * Tuning knobs of the device sweep (chosen by the autotuner; when never set:
- * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 1).  lanes_per_launch: queries per sweep in
+ * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 0,
+ * cell_block 0).  lanes_per_launch: queries per sweep in
  * iso_query_batch (1..64); block: threads per workgroup of the core level
  * kernel (64..1024, multiple of 64); cell_lds_kb: LDS budget of one cell
  * workgroup in KiB (16..160), which sets how many queries' labels a cell
@@ -175,6 +176,8 @@ typedef struct {
                                    data into LDS first (needs the largest cell's data plus one lane's labels
                                    to fit 160 KiB, else 0 is used); cell_lds_kb bounds the LDS either way,
                                    raised to the minimum the variant needs */
+    uint32_t cell_block;        /* threads per cell workgroup: 256 or 512; 0 = 512 for sweeps of 32 or more
+                                   queries, else 256 */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);

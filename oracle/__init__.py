@@ -114,6 +114,7 @@ class Oracle:
 
     def isochrone(self, s: int, tau: int, want_dist: bool = False):
         """(edges (k,2) uint32 sorted, dist uint64[n] or None, settled count)."""
+        _check_source(s, self.n)
         ptr, cnt = _U64P(), C.c_uint64()
         dist = np.empty(self.n, dtype=np.uint64) if want_dist else None
         dptr = dist.ctypes.data_as(_U64P) if want_dist else None
@@ -123,6 +124,7 @@ class Oracle:
 
     def distances(self, s: int) -> np.ndarray:
         """d(s, .) for all vertices; INF (2^64-1) where unreachable."""
+        _check_source(s, self.n)
         dist = np.empty(self.n, dtype=np.uint64)
         self._L.orc_distances(self._g, self._ws, int(s), dist.ctypes.data_as(_U64P))
         return dist
@@ -136,6 +138,7 @@ class Oracle:
 
     def iso_dijkstra(self, s: int, tau: int):
         """The paper's isoDijkstra: (edges, settled count).  Requires tau < 2^64-1."""
+        _check_source(s, self.n)
         ptr, cnt = _U64P(), C.c_uint64()
         settled = self._L.orc_iso_dijkstra(self._g, self._ws, int(s), int(tau),
                                            C.byref(ptr), C.byref(cnt))
@@ -154,8 +157,15 @@ class OracleWorker:
             raise MemoryError("oracle workspace allocation failed")
 
     def isochrone(self, s: int, tau: int):
+        _check_source(s, self._parent.n)
         ptr, cnt = _U64P(), C.c_uint64()
         settled = self._L.orc_isochrone(self._g, self._ws, int(s), int(tau), None, C.byref(ptr), C.byref(cnt))
+        return _take_edges(self._L, ptr, cnt), int(settled)
+
+    def iso_dijkstra(self, s: int, tau: int):
+        _check_source(s, self._parent.n)
+        ptr, cnt = _U64P(), C.c_uint64()
+        settled = self._L.orc_iso_dijkstra(self._g, self._ws, int(s), int(tau), C.byref(ptr), C.byref(cnt))
         return _take_edges(self._L, ptr, cnt), int(settled)
 
     def __del__(self):
@@ -163,6 +173,11 @@ class OracleWorker:
             self._L.orc_ws_free(self._ws)
         except Exception:
             pass
+
+
+def _check_source(s: int, n: int):
+    if not 0 <= int(s) < n:
+        raise ValueError(f"source {s} out of range [0, {n})")
 
 
 def clamp_u32(dist: np.ndarray) -> np.ndarray:

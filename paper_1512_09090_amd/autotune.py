@@ -19,12 +19,13 @@ from .binding import MODE_CELLS, Graph
 
 SPACE = {
     "cell_stage": [0, 1],
+    "cell_block": [0, 256, 512],
     "lanes_per_launch": [8, 16, 32, 64],
     "block": [128, 256, 512],
     "cell_lds_kb": [24, 40, 64, 96],
     "use_graph": [0, 1],
 }
-DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 1}
+DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 0, "cell_block": 0}
 
 
 def measure(G: Graph, sources, taus, mode=MODE_CELLS, repeats: int = 2) -> float:

@@ -6,6 +6,11 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <thread>
+#include <mutex>
+#include <memory>
+#include <functional>
+#include <condition_variable>
 #include <cstdlib>
 #include <cstdint>
 #include <string>
@@ -135,6 +140,69 @@ struct UpwardSearch {
     }
 };
 
+// Persistent host worker threads: run(use, f) calls f(w) for w in [0, use) on the pool's
+// threads (the caller is worker 0) and returns when every call has returned.  One run at a
+// time (a graph is used by one call, or by its server, at a time).
+class WorkerPool {
+public:
+    explicit WorkerPool(int n) : n_(std::max(1, n)) {
+        for (int w = 1; w < n_; ++w) th_.emplace_back([this, w] { loop(w); });
+    }
+    ~WorkerPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    int size() const { return n_; }
+    void run(int use, const std::function<void(int)> &f) {
+        use = std::max(1, std::min(use, n_));
+        if (use > 1) {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &f;
+            want_ = use;
+            busy_ = use - 1;
+            ++gen_;
+        }
+        if (use > 1) cv_.notify_all();
+        f(0);
+        if (use > 1) {
+            std::unique_lock<std::mutex> lk(mu_);
+            done_.wait(lk, [&] { return busy_ == 0; });
+            job_ = nullptr;
+        }
+    }
+
+private:
+    void loop(int w) {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)> *job = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                if (w >= want_) continue;
+                job = job_;
+            }
+            (*job)(w);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--busy_ == 0) done_.notify_one();
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *job_ = nullptr;
+    uint64_t gen_ = 0;
+    int want_ = 0, busy_ = 0;
+    bool stop_ = false;
+};
+
 struct iso_graph {
     iso::Prep P;
     isodev::DevGraph D;
@@ -142,9 +210,10 @@ struct iso_graph {
     int threads = 1;
     std::atomic<bool> busy{false};
     iso_query_stats last{};
-    iso_tuning tuning{64, 256, 64, 1, 0, 1};   // the autotuner's choice on an 18M-vertex road graph
+    iso_tuning tuning{64, 256, 64, 1, 0, 0, 0};   // the autotuner's choice on an 18M-vertex road graph
     UpwardGraph upg;                // packed upward graph
     std::vector<UpwardSearch> up;   // one workspace per host thread
+    std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep
     size_t out_cap = 1 << 20;
 };
 

@@ -26,7 +26,8 @@ struct RunArgs {
     uint32_t lane_base = 0;
     uint32_t block = 256;            // threads per workgroup of the core level kernel
     uint32_t use_graph = 0;          // 1: replay the captured device sweep
-    uint32_t cell_stage = 0;         // 1: whole cell staged in LDS (k_cell_sweep_staged)
+    uint32_t cell_stage = 0;         // 1: whole cell staged in LDS
+    uint32_t cell_block = 512;       // threads per cell workgroup
     size_t cell_lds_bytes = 40 * 1024;
     bool mode_plain = true;
     bool want_dist = false;
@@ -78,7 +79,7 @@ struct Profile {
 
 // Everything the captured sweep sequence depends on (kernel arguments and grid shapes).
 struct GraphSig {
-    uint32_t K, plain, dist, block, cell_lds, xcap, cell_stage, reserved;
+    uint32_t K, plain, dist, block, cell_lds, xcap, cell_stage, cell_block;
     uint64_t cap;
     uint64_t ptr[10];
 };
@@ -125,7 +126,7 @@ struct DevGraph {
     uint32_t max_blob_words = 0, max_cell_labels = 0, max_cell_cnt = 0, max_cell_levels = 0;
     int num_cus = 0;                                   // compute units of the device
     std::map<uint64_t, uint32_t> occ_cache;            // cell-sweep workgroups per CU by (variant, LDS)
-    int cell_occupancy(bool staged, size_t lds, uint32_t &per_cu);
+    int cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t &per_cu);
     uint64_t bytes = 0;
     SweepCtx main;   // context of the direct query calls
     SweepCtx aux;    // second context of a batch call, so that consecutive sweeps overlap (made on first use)

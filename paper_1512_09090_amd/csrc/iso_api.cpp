@@ -52,6 +52,7 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     A.cell_lds_bytes = size_t(g->tuning.cell_lds_kb) * 1024;
     A.use_graph = g->tuning.use_graph;
     A.cell_stage = g->tuning.cell_stage;
+    A.cell_block = g->tuning.cell_block ? g->tuning.cell_block : (pow2_at_least(lanes) >= 32 ? 512u : 256u);
     A.lanes = lanes;
     A.k_pow2 = pow2_at_least(lanes);
     A.mode_plain = plain;
@@ -62,20 +63,16 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     // upward searches, one host thread per lane (bounded by g->threads)
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> U(lanes);
     {
-        int T = std::min<int>(g->threads, int(lanes));
         std::atomic<uint32_t> next{0};
-        auto work = [&](int tid) {
+        const std::function<void(int)> work = [&](int w) {
             for (;;) {
                 uint32_t j = next.fetch_add(1);
                 if (j >= lanes) break;
-                uint32_t st = g->up[tid].run(g->upg, P.pos[src[j]], U[j], g->D.TX);
+                uint32_t st = g->up[w].run(g->upg, P.pos[src[j]], U[j], g->D.TX);
                 if (settled) settled[j] = st;
             }
         };
-        std::vector<std::thread> pool;
-        for (int t = 1; t < T; ++t) pool.emplace_back(work, t);
-        work(0);
-        for (auto &th : pool) th.join();
+        g->pool->run(int(lanes), work);
     }
     for (uint32_t j = 0; j < lanes; ++j) {
         A.taus[j] = tau[j];
@@ -300,8 +297,13 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
             delete g;
             return fail(ISO_EFORMAT, "upward arcs must lead to smaller sweep positions");
         }
-        g->up.resize(g->threads);
-        for (auto &u : g->up) u.init(g->P.n);
+        {
+            // one upward-search workspace per worker; a sweep has at most 64 searches
+            const int W = std::min<int>(g->threads, int(isodev::MAX_LANES));
+            g->up.resize(W);
+            for (auto &u : g->up) u.init(g->P.n);
+            g->pool = std::make_unique<WorkerPool>(W);
+        }
         g->out_cap = std::max<size_t>(1 << 16, std::min<size_t>(g->P.m / 4 + 1024, size_t(1) << 24));
         if (d->device >= 0) {
             int r = g->D.upload(g->P, d->device);
@@ -580,6 +582,8 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (t->cell_lds_kb < 16 || t->cell_lds_kb > 160) return fail(ISO_EINVAL, "cell_lds_kb must be in [16, 160]");
     if (t->use_graph > 1) return fail(ISO_EINVAL, "use_graph must be 0 or 1");
     if (t->cell_stage > 1) return fail(ISO_EINVAL, "cell_stage must be 0 or 1");
+    if (t->cell_block != 0 && t->cell_block != 256 && t->cell_block != 512)
+        return fail(ISO_EINVAL, "cell_block must be 0, 256 or 512");
     if (t->core_mode != 0)
         return fail(ISO_EINVAL, "core_mode must be 0: the single-launch core sweep with a grid barrier "
                                 "is disabled");

@@ -10,13 +10,29 @@
 #include <mutex>
 #include <numeric>
 #include <thread>
+#include <cstdlib>
+#include <sched.h>
 
 namespace iso {
 
+// Default thread count: the CPUs this process may run on (affinity mask), capped by a cgroup
+// CPU quota when one is set.
 int resolve_threads(int t) {
     if (t > 0) return t;
     unsigned h = std::thread::hardware_concurrency();
-    return h ? int(h) : 1;
+    int n = h ? int(h) : 1;
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof set, &set) == 0) n = std::max(1, CPU_COUNT(&set));
+    if (FILE *f = std::fopen("/sys/fs/cgroup/cpu.max", "r")) {
+        char quota[32] = {0};
+        long period = 0;
+        if (std::fscanf(f, "%31s %ld", quota, &period) == 2 && std::strcmp(quota, "max") != 0 && period > 0) {
+            long q = std::atol(quota);
+            if (q > 0) n = std::min<long>(n, std::max<long>(1, (q + period - 1) / period));
+        }
+        std::fclose(f);
+    }
+    return n;
 }
 
 // Run f(i, tid) for i in [0, n) on `threads` threads with dynamic chunking.

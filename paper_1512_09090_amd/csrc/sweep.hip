@@ -470,7 +470,8 @@ struct CellArgs {
     uint32_t out_cap, lane_base, lk, lg, num_cells;
 };
 
-constexpr uint32_t CELL_THREADS = 256;
+// Cell workgroups have 256 or 512 threads (the cell_block knob); the item code reads blockDim.x.
+constexpr uint32_t CELL_THREADS_MAX = 512;
 // Isochrone edges found in a cell are first collected in LDS as candidate words and written
 // out in bulk.  A word holds the internal head vertex i (12 bits; a cell has at most 4096
 // vertices), the entry's offset k among i's entries (13 bits), the lane slot j (6 bits) and
@@ -497,7 +498,7 @@ struct CellBits {
     }
 };
 constexpr uint32_t CELL_BUF = 512;         // entries per LDS level buffer (two buffers)
-constexpr uint32_t CELL_REGS = CELL_BUF / CELL_THREADS;
+constexpr uint32_t CELL_REGS = CELL_BUF / 256;   // entries per thread held for the next level (at most)
 
 // LDS words of a cell workgroup: offsets and level bounds (padded to even), two level
 // buffers of CELL_BUF entries, labels (cnt + refs rows of G lanes).
@@ -554,7 +555,7 @@ __device__ __forceinline__ void flush_cands(uint32_t n, uint32_t *s_cand, uint32
     if (tid == 0) s_ctl[1] = atomicAdd(A.out_count, n);
     __syncthreads();
     const uint32_t base = s_ctl[1];
-    for (uint32_t k = tid; k < n; k += CELL_THREADS) {
+    for (uint32_t k = tid; k < n; k += blockDim.x) {
         const uint64_t key = cand_key(A, s_cand[k], s_off, cnt, ent, ref, cb, lanes, q);
         if (base + k < A.out_cap) A.out_keys[base + k] = key;
     }
@@ -657,19 +658,19 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
     const uint32_t jj = nth_set_bit(lanes, live ? rank : (q << lg));   // lane within the batch
     const uint32_t tau = A.taus[jj];
     const bool has_up = A.src_cell[jj] == c;
-    const uint32_t per_iter = CELL_THREADS >> lg;
+    const uint32_t T = blockDim.x, per_iter = T >> lg;
     // touch the whole blob once (16-byte loads, all independent) so that the per-level
     // loads below hit the L2 instead of HBM; the xor keeps the loads alive
     uint32_t warm = 0;
     {
         const uint32_t words = blob_words(cnt, nl, nrefs, meta.w);
         const uint4 *g4 = reinterpret_cast<const uint4 *>(gblob);
-        for (uint32_t i = tid; i < (words >> 2); i += CELL_THREADS) {
+        for (uint32_t i = tid; i < (words >> 2); i += T) {
             uint4 v = g4[i];
             warm ^= v.x ^ v.w;
         }
     }
-    for (uint32_t i = tid; i < cnt + 1 + nl + 1; i += CELL_THREADS) s_off[i] = gblob[i];
+    for (uint32_t i = tid; i < cnt + 1 + nl + 1; i += T) s_off[i] = gblob[i];
     if (tid == 0) s_ctl[0] = s_ctl[2] = s_ctl[3] = 0;
     // labels: internal vertices start at INF (upward labels only in a source's cell) ...
     for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
@@ -707,8 +708,8 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
         uint32_t eb = s_off[s_lvl[0]], n = min(s_off[s_lvl[1]] - eb, CELL_BUF);
 #pragma unroll
         for (uint32_t k = 0; k < CELL_REGS; ++k) {
-            uint32_t idx = tid + k * CELL_THREADS;
-            if (idx < n) s_buf[idx] = gent[eb + idx];
+            uint32_t idx = tid + k * T;
+            if (k * T < CELL_BUF && idx < n) s_buf[idx] = gent[eb + idx];
         }
     }
     __syncthreads();
@@ -724,8 +725,8 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             n1 = min(s_off[s_lvl[l + 2]] - eb1, CELL_BUF);
 #pragma unroll
             for (uint32_t k = 0; k < CELL_REGS; ++k) {
-                uint32_t idx = tid + k * CELL_THREADS;
-                if (idx < n1) r[k] = gent[eb1 + idx];
+                uint32_t idx = tid + k * T;
+                if (k * T < CELL_BUF && idx < n1) r[k] = gent[eb1 + idx];
             }
         }
         for (uint32_t base = a; base < bnd; base += per_iter) {
@@ -753,8 +754,8 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
         if (l + 1 < nl) {
 #pragma unroll
             for (uint32_t k = 0; k < CELL_REGS; ++k) {
-                uint32_t idx = tid + k * CELL_THREADS;
-                if (idx < n1) nxt[idx] = r[k];
+                uint32_t idx = tid + k * T;
+                if (k * T < CELL_BUF && idx < n1) nxt[idx] = r[k];
             }
         }
         level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
@@ -793,7 +794,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
     const uint32_t jj = nth_set_bit(lanes, live ? rank : (q << lg));
     const uint32_t tau = A.taus[jj];
     const bool has_up = A.src_cell[jj] == c;
-    const uint32_t per_iter = CELL_THREADS >> lg;
+    const uint32_t per_iter = blockDim.x >> lg;
     // referenced core labels: loads issued before the blob copy is stored
     const uint32_t r0 = tid >> lg;
     uint32_t rv0 = INF, rv1 = INF;
@@ -803,7 +804,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
         const uint4 *g4 = reinterpret_cast<const uint4 *>(gblob);
         uint4 *s4 = reinterpret_cast<uint4 *>(smem);
         const uint32_t n4 = words >> 2;
-        constexpr uint32_t T = CELL_THREADS;
+        const uint32_t T = blockDim.x;
         const uint32_t last = n4 - 1;   // a blob holds at least its offsets, so n4 >= 1
         for (uint32_t i = tid; i < n4; i += 8 * T) {
             // indices past the end read the last vector again (never stored): no branches
@@ -842,35 +843,59 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
     const uint2 *s_ent = reinterpret_cast<const uint2 *>(smem + blob_head_words(cnt, nl, nrefs));
     auto ent = [&](uint32_t e) { return s_ent[e]; };
     auto ref = [&](uint32_t r) { return s_refs[r]; };
-    for (uint32_t l = 0; l < nl; ++l) {
+    // one vertex (slot i of the current level) for the thread's lane slot
+    auto sweep_vertex = [&](uint32_t i, bool act) {
+        uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
+        uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
+        CellBits bits;
+        // four entries at a time: their reads, then their tails' labels
+        for (uint32_t e = e0; e < e1; e += 4) {
+            uint2 x[4];
+            uint32_t lt[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) x[u] = e + u < e1 ? s_ent[e + u] : make_uint2(0u, INF);
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) lt[u] = e + u < e1 ? s_lab[((x[u].x & LOCAL_MASK) << lg) + j] : INF;
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                dv = min(dv, sat_add(lt[u], x[u].y));
+                if (e + u < e1) bits.see(e + u - e0, x[u].x, lt[u] <= tau);
+            }
+        }
+        if (act) {
+            s_lab[(i << lg) + j] = dv;
+            if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
+        }
+        emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent, ref,
+                         cb, lanes, q);
+    };
+    // The sweep starts with the top of the cell's hierarchy, where levels hold a few vertices:
+    // while a level fits the vertex slots of one wavefront, wavefront 0 sweeps it alone, and its
+    // lanes see each other's label writes through LDS ordering within a wavefront (a
+    // wavefront-scope fence between levels) instead of a workgroup barrier.
+    const uint32_t wslots = 64u >> lg;
+    uint32_t l0 = 0;
+    while (l0 < nl && s_lvl[l0 + 1] - s_lvl[l0] <= wslots) ++l0;
+    if (tid < 64) {
+        for (uint32_t l = 0; l < l0; ++l) {
+            const uint32_t i = s_lvl[l] + (tid >> lg);
+            sweep_vertex(i, i < s_lvl[l + 1]);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (l0 == nl) {   // the whole cell fit one wavefront: write the candidates out
+        __syncthreads();
+        const uint32_t n = s_ctl[0];
+        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        return;
+    }
+    if (l0) __syncthreads();
+    for (uint32_t l = l0; l < nl; ++l) {
         const uint32_t a = s_lvl[l], bnd = s_lvl[l + 1];
         for (uint32_t base = a; base < bnd; base += per_iter) {
-            uint32_t i = base + (tid >> lg);
-            bool act = i < bnd;
-            uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
-            uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
-            CellBits bits;
-            // four entries at a time: their reads, then their tails' labels
-            for (uint32_t e = e0; e < e1; e += 4) {
-                uint2 x[4];
-                uint32_t lt[4];
-#pragma unroll
-                for (uint32_t u = 0; u < 4; ++u) x[u] = e + u < e1 ? s_ent[e + u] : make_uint2(0u, INF);
-#pragma unroll
-                for (uint32_t u = 0; u < 4; ++u)
-                    lt[u] = e + u < e1 ? s_lab[((x[u].x & LOCAL_MASK) << lg) + j] : INF;
-#pragma unroll
-                for (uint32_t u = 0; u < 4; ++u) {
-                    dv = min(dv, sat_add(lt[u], x[u].y));
-                    if (e + u < e1) bits.see(e + u - e0, x[u].x, lt[u] <= tau);
-                }
-            }
-            if (act) {
-                s_lab[(i << lg) + j] = dv;
-                if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
-            }
-            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
-                             ref, cb, lanes, q);
+            const uint32_t i = base + (tid >> lg);
+            sweep_vertex(i, i < bnd);
         }
         level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
     }
@@ -881,7 +906,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
 // consecutive, run on the same XCD and share its L2; its workgroups stride through that
 // range.  No workgroup waits for another.
 template <bool STAGED>
-__global__ void __launch_bounds__(CELL_THREADS) k_cell_sweep(CellArgs A) {
+__global__ void __launch_bounds__(CELL_THREADS_MAX) k_cell_sweep(CellArgs A) {
     extern __shared__ uint32_t smem[];
     const uint32_t total = *A.n_items;
     const uint32_t rows = (total + 7u) >> 3;
@@ -928,8 +953,8 @@ static int dev_alloc_copy(T **dst, const std::vector<T> &src, uint64_t &bytes) {
 
 // Workgroups of a cell-sweep variant that fit one compute unit with `lds` bytes of LDS each
 // (cached per variant and size).
-int DevGraph::cell_occupancy(bool staged, size_t lds, uint32_t &per_cu) {
-    const uint64_t key = (uint64_t(staged) << 40) | lds;
+int DevGraph::cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t &per_cu) {
+    const uint64_t key = (uint64_t(staged) << 40) | (uint64_t(threads) << 24) | lds;
     auto f = occ_cache.find(key);
     if (f != occ_cache.end()) {
         per_cu = f->second;
@@ -937,7 +962,7 @@ int DevGraph::cell_occupancy(bool staged, size_t lds, uint32_t &per_cu) {
     }
     int nb = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, staged ? (const void *)k_cell_sweep<true> : (const void *)k_cell_sweep<false>, CELL_THREADS, lds));
+        &nb, staged ? (const void *)k_cell_sweep<true> : (const void *)k_cell_sweep<false>, int(threads), lds));
     per_cu = uint32_t(std::max(1, nb));
     occ_cache[key] = per_cu;
     return 0;
@@ -1306,7 +1331,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     // kernel arguments; with use_graph it is captured once per signature and replayed
     const bool use_graph = A.use_graph && !prof_on;
     GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
-                 A.cell_stage, 0u, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
+                 A.cell_stage, A.cell_block, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
                                  uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
                                  uint64_t(uintptr_t(B.d_keys)), uint64_t(uintptr_t(B.d_flags)),
                                  uint64_t(uintptr_t(B.d_counters)), uint64_t(uintptr_t(B.d_list)),
@@ -1330,7 +1355,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             return -2;
         }
         uint32_t per_cu = 0;
-        if ((r = cell_occupancy(staged, lds, per_cu))) return r;
+        if ((r = cell_occupancy(staged, A.cell_block, lds, per_cu))) return r;
         uint64_t most = uint64_t(num_cells) << (lk - cell_lg);
         uint64_t want = std::min<uint64_t>(uint64_t(per_cu) * uint64_t(std::max(1, num_cus)), most);
         cell_grid = uint32_t(std::max<uint64_t>(8, (want + 7) / 8 * 8));
@@ -1387,9 +1412,9 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                         uint32_t(cap), A.lane_base, lk, lg, num_cells};
             if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
             if (staged)
-                k_cell_sweep<true><<<dim3(cell_grid), dim3(CELL_THREADS), lds, s>>>(LA);
+                k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
             else
-                k_cell_sweep<false><<<dim3(cell_grid), dim3(CELL_THREADS), lds, s>>>(LA);
+                k_cell_sweep<false><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
         } else if (prof_on) {
             HIPCHK(hipEventRecord(C.prof.ev[2], s));
         }

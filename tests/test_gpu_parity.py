@@ -222,10 +222,11 @@ def _identical_across_tuning(road50k, combos):
     ref = G.query_batch(src, tau, iso.MODE_CELLS)
     for i, (block, lds_kb, lanes, cm, stage) in enumerate(combos):
         graph = i % 2          # every other setting runs eagerly
+        cb = 256 if (i // 2) % 2 == 0 else 512
         say(f"tuning block={block} cell_lds_kb={lds_kb} lanes={lanes} core_mode={cm} cell_stage={stage} "
-            f"use_graph={graph}")
+            f"use_graph={graph} cell_block={cb}")
         G.set_tuning(lanes_per_launch=lanes, block=block, cell_lds_kb=lds_kb, core_mode=cm, cell_stage=stage,
-                     use_graph=graph)
+                     use_graph=graph, cell_block=cb)
         out = G.query_batch(src, tau, iso.MODE_CELLS)
         for j in range(len(src)):
             np.testing.assert_array_equal(out[j], ref[j])
