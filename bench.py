@@ -270,6 +270,8 @@ def main():
                     help="offered Poisson rates (queries/s) for the serving section; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true", help="skip the queries-per-sweep comparison")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the warm-up and the timed cells-mode batches (for profiler runs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates profiler byte counters)")
     ap.add_argument("--cache-dir", default=os.environ.get("ISO_CACHE", "/tmp/iso_cache"))
@@ -329,6 +331,11 @@ def main():
     batch_stats = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in G.last_stats().items()}
     log(f"cells batched: {qps:.1f} queries/s, {1000 * total / args.steps:.2f} ms/step; profile {prof}")
     log(f"last batch: {batch_stats}")
+
+    if args.profile_only:   # the timed cells-mode batches only (for profiler runs)
+        print(json.dumps({"metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "steps": args.steps,
+                          "profile_only": True, "profile": prof}), flush=True)
+        return
 
     # plain sweep, same batches
     run_batches(G, src, tau, lanes, 1, iso.MODE_PLAIN)

@@ -659,18 +659,33 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
     const uint32_t tau = A.taus[jj];
     const bool has_up = A.src_cell[jj] == c;
     const uint32_t T = blockDim.x, per_iter = T >> lg;
-    // touch the whole blob once (16-byte loads, all independent) so that the per-level
-    // loads below hit the L2 instead of HBM; the xor keeps the loads alive
-    uint32_t warm = 0;
+    // touch the whole blob once so that the per-level loads below hit the L2 instead of HBM
+    // (16-byte loads, up to eight per thread in flight; indices past the end repeat the last
+    // vector); the vectors that hold the offsets and level bounds are stored to LDS, the
+    // others are consumed by an empty asm statement.  Stores past the head land in the entry
+    // buffer, which is filled after the barrier below.
     {
-        const uint32_t words = blob_words(cnt, nl, nrefs, meta.w);
         const uint4 *g4 = reinterpret_cast<const uint4 *>(gblob);
-        for (uint32_t i = tid; i < (words >> 2); i += T) {
-            uint4 v = g4[i];
-            warm ^= v.x ^ v.w;
+        uint4 *s4 = reinterpret_cast<uint4 *>(smem);
+        const uint32_t n4 = blob_words(cnt, nl, nrefs, meta.w) >> 2, last = n4 - 1;
+        const uint32_t h4 = (cnt + 1 + nl + 1 + 3u) >> 2;
+        for (uint32_t i = tid; i < n4; i += 8 * T) {
+            const uint4 v0 = g4[i], v1 = g4[min(i + T, last)], v2 = g4[min(i + 2 * T, last)];
+            const uint4 v3 = g4[min(i + 3 * T, last)], v4 = g4[min(i + 4 * T, last)];
+            const uint4 v5 = g4[min(i + 5 * T, last)], v6 = g4[min(i + 6 * T, last)];
+            const uint4 v7 = g4[min(i + 7 * T, last)];
+            if (i < h4) s4[i] = v0;
+            if (i + T < h4) s4[i + T] = v1;
+            if (i + 2 * T < h4) s4[i + 2 * T] = v2;
+            if (i + 3 * T < h4) s4[i + 3 * T] = v3;
+            if (i + 4 * T < h4) s4[i + 4 * T] = v4;
+            if (i + 5 * T < h4) s4[i + 5 * T] = v5;
+            if (i + 6 * T < h4) s4[i + 6 * T] = v6;
+            if (i + 7 * T < h4) s4[i + 7 * T] = v7;
+            asm volatile("" ::"v"(v0.x), "v"(v1.x), "v"(v2.x), "v"(v3.x), "v"(v4.x), "v"(v5.x), "v"(v6.x),
+                         "v"(v7.x));
         }
     }
-    for (uint32_t i = tid; i < cnt + 1 + nl + 1; i += T) s_off[i] = gblob[i];
     if (tid == 0) s_ctl[0] = s_ctl[2] = s_ctl[3] = 0;
     // labels: internal vertices start at INF (upward labels only in a source's cell) ...
     for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
@@ -700,7 +715,6 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             if (r < nrefs) s_lab[((cnt + r) << lg) + j] = vv[u];
         }
     }
-    asm volatile("" ::"v"(warm));   // consumes `warm` (no instruction is emitted)
     __syncthreads();
     // entries of level 0 into buffer 0
     uint2 r[CELL_REGS];
@@ -718,6 +732,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
         uint2 *nxt = s_buf + ((l + 1) & 1) * CELL_BUF;
         const uint32_t a = s_lvl[l], bnd = s_lvl[l + 1];
         const uint32_t ebase = s_off[a];
+        const bool in_buf = s_off[bnd] - ebase <= CELL_BUF;
         // prefetch the next level's entries into registers
         uint32_t n1 = 0, eb1 = 0;
         if (l + 1 < nl) {
@@ -735,12 +750,23 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
             uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
             CellBits bits;
-            for (uint32_t e = e0; e < e1; ++e) {
-                uint32_t le = e - ebase;
-                uint2 x = le < CELL_BUF ? cur[le] : gent[e];
-                uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
-                dv = min(dv, sat_add(lt, x.y));
-                bits.see(e - e0, x.x, lt <= tau);
+            if (in_buf) {
+                // the level's entries are all in the LDS buffer: no global load here, so the
+                // next level's loads stay in flight
+                for (uint32_t e = e0; e < e1; ++e) {
+                    const uint2 x = cur[e - ebase];
+                    const uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
+                    dv = min(dv, sat_add(lt, x.y));
+                    bits.see(e - e0, x.x, lt <= tau);
+                }
+            } else {
+                for (uint32_t e = e0; e < e1; ++e) {
+                    const uint32_t le = e - ebase;
+                    const uint2 x = le < CELL_BUF ? cur[le] : gent[e];
+                    const uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
+                    dv = min(dv, sat_add(lt, x.y));
+                    bits.see(e - e0, x.x, lt <= tau);
+                }
             }
             if (act) {
                 s_lab[(i << lg) + j] = dv;
