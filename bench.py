@@ -141,6 +141,15 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "road18m_hbm_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1512_09090_amd", "csrc", "sweep.hip")
 
 
+def kernel_source_sha():
+    """sha256 of the device code: the kernel source up to its host-side section."""
+    import hashlib
+
+    text = open(KERNEL_SOURCE, "rb").read()
+    cut = text.find(b"// ----------------------------------------------------------------- host side")
+    return hashlib.sha256(text if cut < 0 else text[:cut]).hexdigest()
+
+
 def measured_traffic(phase):
     """HBM bytes per launch of a phase from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE passes, scaled by a copy of known size), or None when the summary is missing or
@@ -149,11 +158,12 @@ def measured_traffic(phase):
 
     try:
         text = open(TRAFFIC_SUMMARY).read()
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = kernel_source_sha()
     except OSError:
         return None
-    vals = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("sweep_hip_sha256:", f"{phase}_")))
-    if vals.get("sweep_hip_sha256", "").strip() != sha:
+    vals = dict(line.split(":", 1) for line in text.splitlines()
+                if line.startswith(("device_code_sha256:", f"{phase}_")))
+    if vals.get("device_code_sha256", "").strip() != sha:
         return None
     v = vals.get(f"{phase}_bytes_per_launch")
     return int(v) if v else None

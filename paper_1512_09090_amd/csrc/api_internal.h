@@ -214,6 +214,7 @@ struct iso_graph {
     UpwardGraph upg;                // packed upward graph
     std::vector<UpwardSearch> up;   // one workspace per host thread
     std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> up_out;   // one search result buffer per worker
     size_t out_cap = 1 << 20;
 };
 

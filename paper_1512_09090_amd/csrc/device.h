@@ -34,8 +34,9 @@ struct RunArgs {
     size_t out_cap = 0;          // capacity of the edge-key buffer
     std::vector<uint32_t> taus;      // k_pow2 (padding lanes: INF)
     std::vector<uint32_t> src_cell;  // k_pow2 (padding lanes: NO_CELL)
-    // upward-search labels of every lane, one entry each: position, lane, label
-    std::vector<uint32_t> upos, ulane, uval;
+    // upward-search labels per lane: positions and labels inside the top table X
+    // (position < TX), and elsewhere
+    std::vector<std::vector<uint32_t>> xpos, xval, spos, sval;
 };
 
 struct RunResult {

@@ -60,16 +60,34 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     const uint32_t K = A.k_pow2;
     A.taus.assign(K, 0u);   // padding lanes: every label INF > 0, so they activate no cell and emit nothing
     A.src_cell.assign(K, iso::NO_CELL);
-    // upward searches, one host thread per lane (bounded by g->threads)
-    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> U(lanes);
+    // upward searches on the graph's worker pool; each worker also splits its lanes' labels into
+    // the top-table part and the rest
+    A.xpos.assign(lanes, {});
+    A.xval.assign(lanes, {});
+    A.spos.assign(lanes, {});
+    A.sval.assign(lanes, {});
     {
         std::atomic<uint32_t> next{0};
+        const uint32_t TX = g->D.TX;
         const std::function<void(int)> work = [&](int w) {
+            std::vector<std::pair<uint32_t, uint32_t>> &U = g->up_out[w];
             for (;;) {
                 uint32_t j = next.fetch_add(1);
                 if (j >= lanes) break;
-                uint32_t st = g->up[w].run(g->upg, P.pos[src[j]], U[j], g->D.TX);
+                uint32_t st = g->up[w].run(g->upg, P.pos[src[j]], U, TX);
                 if (settled) settled[j] = st;
+                auto &xp = A.xpos[j], &xv = A.xval[j], &sp = A.spos[j], &sv = A.sval[j];
+                sp.reserve(U.size());
+                sv.reserve(U.size());
+                for (const auto &pr : U) {
+                    if (pr.first < TX) {
+                        xp.push_back(pr.first);
+                        xv.push_back(pr.second);
+                    } else {
+                        sp.push_back(pr.first);
+                        sv.push_back(pr.second);
+                    }
+                }
             }
         };
         g->pool->run(int(lanes), work);
@@ -78,20 +96,6 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
         A.taus[j] = tau[j];
         A.src_cell[j] = P.num_cells ? P.cell_of[src[j]] : iso::NO_CELL;
     }
-    // upward labels as (position, lane, label) entries; the device builds the slot table
-    size_t total = 0;
-    for (auto &u : U) total += u.size();
-    A.upos.resize(total);
-    A.ulane.resize(total);
-    A.uval.resize(total);
-    size_t o = 0;
-    for (uint32_t j = 0; j < lanes; ++j)
-        for (auto &pr : U[j]) {
-            A.upos[o] = pr.first;
-            A.ulane[o] = j;
-            A.uval[o] = pr.second;
-            ++o;
-        }
 }
 
 void split_edges(const uint32_t *pairs, const std::vector<uint32_t> &lane_off, uint32_t lanes,
@@ -302,6 +306,7 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
             const int W = std::min<int>(g->threads, int(isodev::MAX_LANES));
             g->up.resize(W);
             for (auto &u : g->up) u.init(g->P.n);
+            g->up_out.resize(W);
             g->pool = std::make_unique<WorkerPool>(W);
         }
         g->out_cap = std::max<size_t>(1 << 16, std::min<size_t>(g->P.m / 4 + 1024, size_t(1) << 24));

@@ -356,13 +356,17 @@ __host__ __device__ __forceinline__ uint32_t level_ls(uint32_t vertices, uint32_
     return ls;
 }
 
-// One core level: positions [vbeg, vend).
+// One core level: positions [vbeg, vend).  The grid is a multiple of 8 blocks; block b takes
+// the (b mod 8)-th eighth of the level, so each XCD (blocks are dealt to the 8 XCDs in turn)
+// sweeps a contiguous run of positions.  Within a level the core is ordered by cell, so those
+// vertices are neighbours and share many tails, whose label rows then meet in one XCD's L2.
 __global__ void __launch_bounds__(1024)
 k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
     __shared__ uint64_t s_keys[CORE_KEYS];
     __shared__ uint32_t s_n, s_base;
     keys_begin(&s_n);
-    core_item(A, blockIdx.x * blockDim.x + threadIdx.x, ls, vbeg, vend, s_keys, &s_n);
+    const uint32_t b = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    core_item(A, b * blockDim.x + threadIdx.x, ls, vbeg, vend, s_keys, &s_n);
     keys_end(s_keys, &s_n, &s_base, A);
 }
 
@@ -1255,24 +1259,18 @@ int DevGraph::run(SweepCtx &C, const RunArgs &A, RunResult &R) {
 int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     HIPCHK(hipSetDevice(device));
     const uint32_t K = A.k_pow2, lk = ilog2(K);
-    // upward entries inside the table go to per-lane lists (entries arrive grouped by lane,
-    // ascending position within a lane); the others go to the slot table
-    std::vector<uint32_t> xptr(K + 1, 0), xpos, xval, spos, slane, sval;
-    xpos.reserve(A.upos.size());
-    xval.reserve(A.upos.size());
-    for (size_t i = 0; i < A.upos.size(); ++i) {
-        if (A.upos[i] < TX) {
-            xptr[A.ulane[i] + 1]++;
-            xpos.push_back(A.upos[i]);
-            xval.push_back(A.uval[i]);
-        } else {
-            spos.push_back(A.upos[i]);
-            slane.push_back(A.ulane[i]);
-            sval.push_back(A.uval[i]);
-        }
+    // upward labels: per-lane lists inside the table X (CSR over lanes), the others as
+    // (position, lane, label) entries for the slot table
+    std::vector<uint32_t> xptr(K + 1, 0), soff(K + 1, 0);
+    for (uint32_t j = 0; j < A.xpos.size(); ++j) {
+        xptr[j + 1] = uint32_t(A.xpos[j].size());
+        soff[j + 1] = uint32_t(A.spos[j].size());
     }
-    for (uint32_t j = 0; j < K; ++j) xptr[j + 1] += xptr[j];
-    const uint32_t nu = uint32_t(spos.size()), nx = uint32_t(xpos.size());
+    for (uint32_t j = 0; j < K; ++j) {
+        xptr[j + 1] += xptr[j];
+        soff[j + 1] += soff[j];
+    }
+    const uint32_t nu = soff[K], nx = xptr[K];
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
     int r;
@@ -1320,13 +1318,15 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     std::copy(A.taus.begin(), A.taus.end(), hin);
     std::copy(A.src_cell.begin(), A.src_cell.end(), hin + K);
     uint32_t *hu = hin + 2 * K;
-    std::copy(spos.begin(), spos.end(), hu);
-    std::copy(slane.begin(), slane.end(), hu + nu);
-    std::copy(sval.begin(), sval.end(), hu + 2 * size_t(nu));
     uint32_t *hx = hu + 3 * size_t(nu);
     std::copy(xptr.begin(), xptr.end(), hx);
-    std::copy(xpos.begin(), xpos.end(), hx + K + 1);
-    std::copy(xval.begin(), xval.end(), hx + K + 1 + nx);
+    for (uint32_t j = 0; j < A.xpos.size(); ++j) {
+        std::copy(A.spos[j].begin(), A.spos[j].end(), hu + soff[j]);
+        std::fill(hu + nu + soff[j], hu + nu + soff[j + 1], j);
+        std::copy(A.sval[j].begin(), A.sval[j].end(), hu + 2 * size_t(nu) + soff[j]);
+        std::copy(A.xpos[j].begin(), A.xpos[j].end(), hx + K + 1 + xptr[j]);
+        std::copy(A.xval[j].begin(), A.xval[j].end(), hx + K + 1 + nx + xptr[j]);
+    }
     uint32_t *d_taus = B.d_taus, *d_src = B.d_taus + K;
     HIPCHK(hipMemcpyAsync(d_taus, hin, 2 * K * 4, hipMemcpyHostToDevice, s));
     if (nu) HIPCHK(hipMemcpyAsync(B.d_uin, hu, size_t(nu) * 3 * 4, hipMemcpyHostToDevice, s));
@@ -1423,6 +1423,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             uint32_t ls = level_ls(ve - vb, core_lvl_entries[l + 1] - core_lvl_entries[l], K);
             uint64_t threads = uint64_t(ve - vb) << (lk + ls);
             uint32_t grid = uint32_t((threads + blk - 1) / blk);
+            grid = (grid + 7u) & ~7u;   // a multiple of 8 (the block mapping assumes it)
             k_core_level<<<dim3(grid), dim3(blk), 0, s>>>(CA, ls, vb, ve);
         }
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
