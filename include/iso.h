@@ -90,7 +90,8 @@ typedef struct {
     const char *prep_path;      /* optional: if the file exists and matches the input it is loaded instead
                                    of preprocessing; otherwise the preprocessed data is written there */
     int device;                 /* HIP device ordinal; -1 = host-only preprocessing (queries fail with ISO_EDEVICE) */
-    int threads;                /* host threads for preprocessing and upward searches (0 = all cores) */
+    int threads;                /* host threads for preprocessing and upward searches (0 = the CPUs the
+                                   process may run on, capped by a cgroup CPU quota) */
     int verbose;                /* 1 = progress lines on stderr during preprocessing */
 } iso_graph_desc;
 
@@ -103,6 +104,8 @@ typedef struct {
     uint64_t shortcuts;         /* arcs added by contraction */
     uint64_t device_bytes;      /* resident device memory of the graph */
     double prep_seconds;        /* partition + contraction + layout (0 when loaded from a file) */
+    uint32_t host_threads;      /* host threads for preprocessing; the upward searches use up to 64 */
+    uint32_t top_table;         /* core positions in the top distance table (TX) */
 } iso_graph_info;
 
 /* Per-call counters of the last query on a handle (phase times in ms). */

@@ -39,7 +39,7 @@ class GraphInfo(C.Structure):
                 ("core_levels", C.c_uint32), ("max_cell_levels", C.c_uint32),
                 ("max_cell_internal", C.c_uint32), ("m", C.c_uint64), ("down_arcs", C.c_uint64),
                 ("up_arcs", C.c_uint64), ("shortcuts", C.c_uint64), ("device_bytes", C.c_uint64),
-                ("prep_seconds", C.c_double)]
+                ("prep_seconds", C.c_double), ("host_threads", C.c_uint32), ("top_table", C.c_uint32)]
 
 
 class QueryStats(C.Structure):

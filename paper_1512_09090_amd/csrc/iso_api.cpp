@@ -348,6 +348,8 @@ int iso_graph_get_info(const iso_graph *g, iso_graph_info *info) {
     info->shortcuts = P.shortcuts;
     info->device_bytes = g->D.bytes;
     info->prep_seconds = P.seconds;
+    info->host_threads = uint32_t(g->threads);
+    info->top_table = g->D.TX;
     return ISO_OK;
 }
 
