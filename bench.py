@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of batched isochrone queries on the 18M-vertex synthetic road graph.
 
-One step = one batch of `--lanes` queries (source, tau) answered by
-iso_query_batch in the cell-restricted mode: host upward searches, core sweep
-with cell flags, active-cell selection, per-cell sweeps with isochrone-edge
-extraction, radix sort of the edges, copy back.  Inputs are resident on the
-device before the timed region.  Also reported: single-query latency p50/p99
-(both sweep modes), the plain-sweep batched throughput, latency percentiles of the
-serving loop under Poisson arrivals at several offered rates, the live roofline of
-the dominant kernel phase (HIP events on the library's stream, algorithmic
-bytes from the graph structure), and the CPU oracle timed on this host.
+One step = one sweep over a batch of `--lanes` queries (source, tau) in the
+cell-restricted mode: host upward searches, core sweep with cell flags,
+active-cell selection, per-cell sweeps with isochrone-edge extraction, radix
+sort and decode of the edges.  The timed region is one iso_query_batch_device
+call over `--steps` batches (consecutive sweeps overlap on two streams): the
+graph is resident in HBM and the edges stay there, in torch-allocated device
+buffers.  The same work through iso_query_batch, which copies the edges to host
+memory over PCIe, is reported beside it (host_api_qps).  Also reported:
+single-query latency p50/p99 (both sweep modes), the plain-sweep batched
+throughput, latency percentiles of the serving loop under Poisson arrivals at
+several offered rates, the live roofline of the dominant kernel phase (HIP
+events on the sweep streams over the timed region, algorithmic bytes from the
+graph structure), and the CPU oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload road18m]
 """
@@ -65,6 +69,41 @@ def run_batches(G, src, tau, lanes, steps, mode, start=0):
     return times
 
 
+class DeviceBatches:
+    """Runs iso_query_batch_device over a query list into torch buffers kept between calls
+    (grown when a call reports ISO_ESPACE)."""
+
+    def __init__(self, iso, G, per_query_hint):
+        import torch
+        self.iso, self.G, self.torch = iso, G, torch
+        self.hint = per_query_hint
+        self.pairs = self.offsets = None
+
+    def reserve(self, k):
+        torch = self.torch
+        if self.offsets is None or self.offsets.numel() < k + 1:
+            self.offsets = torch.empty(k + 1, dtype=torch.int32, device="cuda:0")
+        if self.pairs is None or self.pairs.shape[0] < self.hint * k:
+            self.pairs = None
+            self.pairs = torch.empty((int(self.hint * k), 2), dtype=torch.int32, device="cuda:0")
+
+    def run(self, src, tau, mode):
+        torch = self.torch
+        k = len(src)
+        self.reserve(k)
+        try:
+            return self.G.query_batch_device(src, tau, mode, self.pairs, self.offsets[:k + 1])
+        except self.iso.IsoError as e:
+            if e.code != self.iso.ISO_ESPACE:
+                raise
+            log(f"device result buffer: {self.pairs.shape[0]} pairs, need {e.total}; growing")
+            self.hint = max(self.hint, 1.25 * e.total / max(1, k))
+            self.pairs = None
+            torch.cuda.empty_cache()
+            self.pairs = torch.empty((int(self.hint * k), 2), dtype=torch.int32, device="cuda:0")
+            return self.G.query_batch_device(src, tau, mode, self.pairs, self.offsets[:k + 1])
+
+
 def serving(G, n, rates, duration, lanes, inflight):
     """Poisson arrivals at each offered rate through the continuous-batching server
     (iso_server_*): submit at the trace's arrival times, collect every result, report the
@@ -118,22 +157,17 @@ def serving(G, n, rates, duration, lanes, inflight):
 
 
 def copy_probe(mib):
-    """A device-to-device hipMemcpy of `mib` MiB, three times: the runtime's copy kernel reads and
-    writes a known number of bytes, which calibrates the HBM byte counters of a profiler run."""
-    import ctypes as C
+    """A device-to-device copy of `mib` MiB, three times (torch's same-device copy is the HIP
+    runtime's copy kernel): it reads and writes a known number of bytes, which calibrates the
+    HBM byte counters of a profiler run."""
+    import torch
 
-    hip = C.CDLL("libamdhip64.so")
-    nbytes = int(mib) << 20
-    a, b = C.c_void_p(), C.c_void_p()
-    for p in (a, b):
-        if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
-            raise RuntimeError("hipMalloc failed in the copy probe")
-    hip.hipMemset(a, 1, C.c_size_t(nbytes))
+    a = torch.ones((int(mib) << 20) // 4, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
     for _ in range(3):
-        hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3)      # hipMemcpyDeviceToDevice
-    hip.hipDeviceSynchronize()
-    hip.hipFree(a)
-    hip.hipFree(b)
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
     log(f"copy probe: 3 x {mib} MiB device-to-device")
 
 
@@ -238,24 +272,19 @@ def lanes_sweep(G, src, tau, ks=(8, 16, 32, 64), count=256):
 
 def attainable_bandwidth(mib=1024, reps=5):
     """GB/s of device-to-device copies (read + write bytes), the attainable HBM bandwidth."""
-    import ctypes as C
+    import torch
 
-    hip = C.CDLL("libamdhip64.so")
     nbytes = int(mib) << 20
-    a, b = C.c_void_p(), C.c_void_p()
-    for p in (a, b):
-        if hip.hipMalloc(C.byref(p), C.c_size_t(nbytes)) != 0:
-            return None
-    hip.hipMemset(a, 1, C.c_size_t(nbytes))
-    hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3)
-    hip.hipDeviceSynchronize()
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        hip.hipMemcpy(b, a, C.c_size_t(nbytes), 3)
-    hip.hipDeviceSynchronize()
+        b.copy_(a)
+    torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    hip.hipFree(a)
-    hip.hipFree(b)
+    del a, b
     return 2.0 * reps * nbytes / el / 1e9
 
 
@@ -326,49 +355,67 @@ def main():
         lanes = best["lanes_per_launch"]
         log(f"tuning: {best} ({tuning_note})")
 
-    # warmup (also grows the library's device buffers to their steady size)
+    import torch
+
+    def window(start, count):
+        idx = (np.arange(count) + start) % len(src)
+        return src[idx], tau[idx]
+
+    # warmup: W batches (also grows the library's device buffers and sizes the result buffer)
+    dev = DeviceBatches(iso, G, per_query_hint=40_000)
     log(f"warmup {args.warmup} steps of {lanes} queries")
-    run_batches(G, src, tau, lanes, max(1, args.warmup), iso.MODE_CELLS)
-    # timed region: cells mode, batches of `lanes`
+    ws, wt = window(0, max(1, args.warmup) * lanes)
+    dev.run(ws, wt, iso.MODE_CELLS)
+    dev.hint = max(dev.hint, 2.0 * int(dev.offsets[len(ws)].item()) / len(ws))
+    ts_, tt_ = window(args.warmup * lanes, args.steps * lanes)
+    dev.reserve(len(ts_))   # the timed call's result buffers, allocated before the timed region
+    # timed region: one call over `steps` batches of `lanes` queries, cells mode, edges in HBM
     G.profile_enable(True)
     log(f"timed {args.steps} steps")
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    times = run_batches(G, src, tau, lanes, args.steps, iso.MODE_CELLS, start=args.warmup * lanes)
+    edges_total = dev.run(ts_, tt_, iso.MODE_CELLS)
+    torch.cuda.synchronize()
     total = time.perf_counter() - t0
     prof = G.profile_read()
     G.profile_enable(False)
     qps = args.steps * lanes / total
     batch_stats = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in G.last_stats().items()}
-    log(f"cells batched: {qps:.1f} queries/s, {1000 * total / args.steps:.2f} ms/step; profile {prof}")
-    log(f"last batch: {batch_stats}")
+    log(f"cells batched (device output): {qps:.1f} queries/s, {1000 * total / args.steps:.2f} ms/step, "
+        f"{edges_total} edges; profile {prof}")
+    log(f"timed call: {batch_stats}")
 
     if args.profile_only:   # the timed cells-mode batches only (for profiler runs)
         print(json.dumps({"metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "steps": args.steps,
                           "profile_only": True, "profile": prof}), flush=True)
         return
 
-    # plain sweep, same batches
-    run_batches(G, src, tau, lanes, 1, iso.MODE_PLAIN)
+    # the same through the host API (edges copied to host memory over PCIe): one call per batch,
+    # and one call over the same queries (overlapping sweeps)
+    # (one sweep per call: also the phase times of a sweep that shares the GPU with no other)
+    run_batches(G, src, tau, lanes, 1, iso.MODE_CELLS)
     G.profile_enable(True)
     t0 = time.perf_counter()
-    run_batches(G, src, tau, lanes, max(2, args.steps // 4), iso.MODE_PLAIN, start=args.warmup * lanes)
-    total_p = time.perf_counter() - t0
-    prof_plain = G.profile_read()
+    times = run_batches(G, src, tau, lanes, args.steps, iso.MODE_CELLS, start=args.warmup * lanes)
+    qps_host = args.steps * lanes / (time.perf_counter() - t0)
+    prof_iso = G.profile_read()
     G.profile_enable(False)
-    qps_plain = max(2, args.steps // 4) * lanes / total_p
-    log(f"plain batched: {qps_plain:.1f} queries/s; profile {prof_plain}")
-
-    # one call with 8 sweeps: consecutive sweeps overlap (host upward searches and result copies of
-    # one sweep run during the device work of the next)
-    big = 8 * lanes
-    idx = np.arange(big) % len(src)
-    G.query_batch(src[idx], tau[idx], iso.MODE_CELLS)
+    G.query_batch(ts_, tt_, iso.MODE_CELLS)   # warms the pinned result pool for a call of this size
     t0 = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
-        G.query_batch(src[idx], tau[idx], iso.MODE_CELLS)
-    qps_pipe = reps * big / (time.perf_counter() - t0)
-    log(f"pipelined batched ({big} queries per call): {qps_pipe:.1f} queries/s")
+    G.query_batch(ts_, tt_, iso.MODE_CELLS)
+    qps_host_pipe = args.steps * lanes / (time.perf_counter() - t0)
+    log(f"host API: {qps_host:.1f} queries/s one batch per call, {qps_host_pipe:.1f} in one call")
+
+    # plain sweep, device output, a quarter of the batches
+    np_steps = max(2, args.steps // 4)
+    ps_, pt_ = window(args.warmup * lanes, np_steps * lanes)
+    dev.run(ps_[:lanes], pt_[:lanes], iso.MODE_PLAIN)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev.run(ps_, pt_, iso.MODE_PLAIN)
+    torch.cuda.synchronize()
+    qps_plain = np_steps * lanes / (time.perf_counter() - t0)
+    log(f"plain batched (device output): {qps_plain:.1f} queries/s")
 
     # single-query latency (one query per call)
     lat = {}
@@ -397,7 +444,17 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                 "avg_launch_ms": round(ms / max(1, launches), 4),
                 "algorithmic_bytes_per_launch": int(byts / max(1, launches)),
-                "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()}}
+                "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
+                "note": "timed region: consecutive sweeps overlap on two streams, so a launch's duration "
+                        "includes device time shared with the other sweep's kernels"}
+    key = {"core_sweep": "core", "cell_sweep": "cell"}[dom]
+    iso_ms, iso_launches = prof_iso[f"{key}_ms"], prof_iso[f"{key}_launches"]
+    if iso_ms > 0:
+        iso_gbs = (prof_iso[f"{key}_bytes"] / 1e9) / (iso_ms / 1e3)
+        roofline["isolated"] = {"avg_launch_ms": round(iso_ms / max(1, iso_launches), 4),
+                                "achieved": round(iso_gbs, 1), "frac": round(iso_gbs / HBM_PEAK_GBS, 4),
+                                "note": "same kernel, one sweep per call (host API run), no other sweep "
+                                        "on the GPU"}
 
     serve = None
     if args.serve_rates:
@@ -428,7 +485,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {info['n']}-vertex road-like kNN graph, {info['m']} arcs, "
-                               f"{info['num_cells']} cells; batches of {lanes} queries, cell-restricted sweep, "
+                               f"{info['num_cells']} cells; batches of {lanes} queries, cell-restricted sweep, edges kept in HBM, "
                                "tau uniform 10-240 min",
                    "n": info["n"], "m": info["m"], "cells": info["num_cells"], "core": info["n_core"],
                    "core_levels": info["core_levels"], "down_arcs": info["down_arcs"], "lanes": lanes,
@@ -436,11 +493,12 @@ def main():
         "latency_ms": lat,
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
-        "batched_pipelined_qps": {"queries_per_call": big, "value": round(qps_pipe, 2)},
+        "host_api_qps": {"one_batch_per_call": round(qps_host, 2), "one_call": round(qps_host_pipe, 2),
+                         "note": "iso_query_batch, edges copied to host memory (PCIe included)",
+                         "call_ms_p50": round(1000 * percentile(times, 50), 3),
+                         "call_ms_p99": round(1000 * percentile(times, 99), 3)},
         "queries_per_sweep_qps": sweep,
-        "last_batch": batch_stats,
-        "step_ms_p50": round(1000 * percentile(times, 50), 3),
-        "step_ms_p99": round(1000 * percentile(times, 99), 3),
+        "timed_call": dict(batch_stats, edges_in_hbm=int(edges_total)),
         "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -54,7 +54,8 @@ typedef enum {
     ISO_EFORMAT = -4,   /* preprocessed file missing fields, wrong version or checksum mismatch */
     ISO_EBUSY = -6,     /* the handle is in use by another call */
     ISO_ESTATE = -7,    /* call not valid in the current state (e.g. server stopped) */
-    ISO_EAGAIN = -8     /* result not ready within the given timeout */
+    ISO_EAGAIN = -8,    /* result not ready within the given timeout */
+    ISO_ESPACE = -9     /* a caller-supplied output buffer is too small; the size needed is returned */
 } iso_status;
 
 typedef enum {
@@ -144,6 +145,27 @@ int iso_query_batch(iso_graph *g, size_t k, const uint32_t *sources, const uint3
                     int mode, iso_edge **edges, size_t *offsets);
 
 /*
+ * iso_query_batch with the result left in device memory (Section 3's edge set
+ * per query, nothing copied to the host).  sources and taus are host arrays
+ * (the upward searches run on the host).  pairs (capacity cap pairs) and
+ * offsets (k + 1 words) are caller-owned device memory on the graph's device,
+ * e.g. PyTorch allocations; each must lie inside one device allocation, else
+ * ISO_EINVAL before any work.  On ISO_OK, query j's edges are the (tail, head)
+ * pairs pairs[2 * offsets[j] ...] up to offsets[j + 1], sorted by (tail, head),
+ * bit-identical to iso_query_batch, and *total = offsets[k].  If they do not
+ * fit, the call returns ISO_ESPACE with *total set to the exact number needed
+ * and the contents of pairs and offsets unspecified.  stream (a hipStream_t,
+ * NULL = the null stream) is the caller's stream: work queued on it before the
+ * call (e.g. the allocation or a previous use of the buffers) completes before
+ * the library writes them.  The call returns after its device writes are
+ * complete, so the buffers can be used on any stream.  At most 2^32 - 2 edges
+ * per call.
+ */
+int iso_query_batch_device(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus,
+                           int mode, uint32_t *pairs, uint64_t cap, uint32_t *offsets,
+                           uint64_t *total, void *stream);
+
+/*
  * Distance labels of one query (test hook).  dist (n entries, caller host
  * memory) receives min(d(s, v), ISO_INF) for every vertex the sweep labelled
  * (all vertices in ISO_MODE_PLAIN; core vertices and the vertices of active
@@ -218,13 +240,16 @@ int iso_graph_get_layout(const iso_graph *g, iso_layout *layout);
 
 /*
  * Device-side phase profile (for roofline reporting).  While enabled, each
- * query call records HIP events on the library's stream around its device
- * phases and accumulates their durations, launch counts and algorithmic HBM
+ * query call records HIP events on the stream of each sweep around its device
+ * phases (core sweep; cell flags and active cells; cell sweep; sort) and
+ * accumulates their durations, launch counts and algorithmic HBM
  * bytes: the downward-graph entries and offsets the phase reads, the
  * per-lane label writes and reads it must make (core labels written once and
  * read once; cell-internal labels never leave LDS; each cell reads its
  * distinct core tails once), and the per-vertex cell ids and eccentricities
- * of the flag rule.  Enabling resets the accumulators.
+ * of the flag rule.  Enabling resets the accumulators.  Calls with more
+ * than lanes_per_launch queries run consecutive sweeps on two streams, so
+ * there a phase's duration includes device time shared with the other sweep.
  */
 typedef struct {
     double core_ms, active_ms, cell_ms, sort_ms;        /* summed event durations */

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiso.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "iso.h")
 
-ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_EFORMAT, ISO_EBUSY, ISO_ESTATE, ISO_EAGAIN = 0, -1, -2, -3, -4, -6, -7, -8
+ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_EFORMAT, ISO_EBUSY, ISO_ESTATE, ISO_EAGAIN, ISO_ESPACE = \
+    0, -1, -2, -3, -4, -6, -7, -8, -9
 MODE_PLAIN, MODE_CELLS = 0, 1
 INF = 0xFFFFFFFF
 TAU_MAX = 0xFFFFFFFE
@@ -109,6 +110,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    # PyTorch ships its own HIP runtime (same soname as ROCm's).  Loading it first makes the
+    # library bind to that copy, so the process holds one HIP runtime and torch tensors can be
+    # handed to the library; a second runtime loaded after ours cannot open the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     L.iso_load_graph.argtypes = [C.POINTER(GraphDesc), C.POINTER(C.c_void_p)]
     L.iso_free_graph.argtypes = [C.c_void_p]
@@ -119,6 +127,8 @@ def lib():
                             C.POINTER(C.c_size_t)]
     L.iso_query_batch.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.POINTER(C.POINTER(Edge)),
                                   C.POINTER(C.c_size_t)]
+    L.iso_query_batch_device.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.c_void_p, C.c_uint64,
+                                         C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p]
     L.iso_query_distances.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, _U32P, C.POINTER(C.c_uint8)]
     L.iso_last_query_stats.argtypes = [C.c_void_p, C.POINTER(QueryStats)]
     L.iso_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
@@ -265,6 +275,34 @@ class Graph:
         total = offsets[k]
         flat = _edges_to_numpy(ptr, total)
         return [flat[offsets[j]:offsets[j + 1]] for j in range(k)]
+
+    def query_batch_device(self, sources, taus, mode, pairs, offsets, stream=None) -> int:
+        """Edges of k queries written to device memory: `pairs` (cap x 2, 32-bit integers) and
+        `offsets` (k + 1, 32-bit integers) are contiguous torch tensors on the graph's device;
+        `stream` (default: torch's current stream) is waited for before they are written.
+        Returns the edge count; raises IsoError with code ISO_ESPACE and `.total` (the count
+        needed) when `pairs` is too small."""
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(pairs.device).cuda_stream
+        s, sp = _u32(sources)
+        t, tp = _u32(taus)
+        k = s.size
+        for name, x, need in (("pairs", pairs, None), ("offsets", offsets, k + 1)):
+            if x.element_size() != 4 or not x.is_contiguous() or x.device.type != "cuda":
+                raise IsoError(ISO_EINVAL, f"{name} must be a contiguous 32-bit tensor in device memory")
+            if need is not None and x.numel() < need:
+                raise IsoError(ISO_EINVAL, f"{name} needs {need} entries")
+        total = C.c_uint64()
+        st = lib().iso_query_batch_device(self._h, k, sp, tp, int(mode), C.c_void_p(pairs.data_ptr()),
+                                          pairs.numel() // 2, C.c_void_p(offsets.data_ptr()), C.byref(total),
+                                          C.c_void_p(stream))
+        if st == ISO_ESPACE:
+            e = IsoError(st, lib().iso_last_error().decode(errors="replace"))
+            e.total = total.value
+            raise e
+        _check(st)
+        return total.value
 
     def distances(self, source: int, tau: int, mode: int = MODE_PLAIN):
         """(dist uint32[n] with 2^32-1 where not labelled, swept bool[n])."""

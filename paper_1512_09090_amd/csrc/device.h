@@ -48,6 +48,13 @@ struct RunResult {
     // sink is given (2 * count words; nullptr = out of host memory), else into `edges`.
     std::function<uint32_t *(size_t)> sink;
     std::vector<uint32_t> edges, lane_off;
+    // Device destination instead (dev_dst set): the pairs go to dev_pairs + 2 * dev_base and
+    // dev_base + the lane starts to dev_off[0 .. dev_lanes]; dev_overflow if dev_base + count
+    // exceeds dev_cap pairs, or if it was set beforehand (then nothing is written).
+    uint32_t *dev_pairs = nullptr, *dev_off = nullptr;
+    uint64_t dev_cap = 0;
+    uint32_t dev_base = 0, dev_lanes = 0;
+    bool dev_dst = false, dev_overflow = false;
     double t_result_ms = 0;      // host time of sorting, decoding and copying back the edges
     std::vector<uint32_t> dcore, dist, active_list;   // only with want_dist
 };
@@ -143,6 +150,7 @@ struct DevGraph {
     // overflow set must be launched again with a larger capacity.
     int launch(SweepCtx &C, const RunArgs &A);
     int finish(SweepCtx &C, RunResult &R);
+    int sort_keys(SweepCtx &C, uint32_t cnt_all);
     int run(SweepCtx &C, const RunArgs &A, RunResult &R);
     // device bytes a context needs for k lanes and an edge capacity (admission control)
     size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const;

@@ -355,26 +355,53 @@ int iso_graph_get_info(const iso_graph *g, iso_graph_info *info) {
 
 // k queries in sweeps of up to lanes_per_launch lanes.  With more than one sweep, two sweep
 // contexts alternate: the host upward searches and the launch of sweep i overlap the device
-// work of sweep i - 1, whose edges are then collected (sequential while profiling, so that
-// the phase timings stay per sweep).
+// work of sweep i - 1, whose edges are then collected.  (Phase timings of the profile then
+// include the device time that the two sweeps share.)
+// With `dev` set the edges stay on the device instead (iso_query_batch_device): sweep i decodes its
+// lanes into dev->pairs after the edges of the sweeps before it and writes their starts to
+// dev->off; a sweep that would pass dev->cap is counted but not written, and the call then
+// reports ISO_ESPACE with the exact total.
+struct DevOut {
+    uint32_t *pairs, *off;
+    uint64_t cap;
+    hipStream_t caller;   // the sweep streams wait for the work queued on it before the call
+    uint64_t total = 0;
+    bool over = false;
+};
+
+// Makes the sweep contexts' streams wait for the work queued so far on `caller`.
+static int wait_for_caller(isodev::DevGraph &D, hipStream_t caller, bool aux) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail(ISO_EDEVICE, "hipEventCreate failed");
+    bool ok = hipEventRecord(ev, caller) == hipSuccess && hipStreamWaitEvent(D.main.stream, ev, 0) == hipSuccess &&
+              (!aux || hipStreamWaitEvent(D.aux.stream, ev, 0) == hipSuccess);
+    hipEventDestroy(ev);
+    return ok ? ISO_OK : fail(ISO_EDEVICE, "waiting for the caller's stream failed");
+}
+
 static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_t *tau, int mode,
-                      iso_edge **edges, size_t *offsets) {
+                      iso_edge **edges, size_t *offsets, DevOut *dev = nullptr) {
     double t0 = now_ms();
     g->last = iso_query_stats{};
     const uint32_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
     const size_t nsweeps = (k + per - 1) / per;
     isodev::DevGraph &D = g->D;
-    const bool overlap = nsweeps > 1 && !D.main.prof.on;
+    const bool overlap = nsweeps > 1;
     if (overlap && !D.aux_ready) {
         if (D.aux.create(D.device)) return fail(ISO_EDEVICE, "creating the second sweep context failed");
+        D.aux.prof.on = D.main.prof.on;
         D.aux_ready = true;
+    }
+    if (dev) {
+        int r = wait_for_caller(D, dev->caller, overlap);
+        if (r) return r;
     }
     // every sweep's edges are copied from the device straight into the result buffer, a
     // pinned pool block (grown by moving to a larger block when a later sweep needs room)
     EdgeBuf out;
     out.pinned = true;
     size_t cap = 0;
-    offsets[0] = 0;
+    if (offsets) offsets[0] = 0;
     struct Sweep {
         isodev::RunArgs A;
         isodev::SweepCtx *C = nullptr;
@@ -384,6 +411,15 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
     };
     auto collect = [&](Sweep &W) -> int {
         isodev::RunResult R;
+        if (dev) {
+            R.dev_dst = true;
+            R.dev_pairs = dev->pairs;
+            R.dev_overflow = dev->over;   // past the capacity already: count only
+            R.dev_off = dev->off + W.b;
+            R.dev_cap = dev->cap;
+            R.dev_base = uint32_t(dev->total);
+            R.dev_lanes = W.lanes;
+        }
         R.sink = [&](size_t n) -> uint32_t * {
             if (out.n + n > cap) {
                 size_t want = std::max(out.n + n, cap + cap / 2), got = 0;
@@ -406,7 +442,13 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         }
         if (r) return r;
         if (R.overflow) return fail(ISO_ENOMEM, "edge buffer overflow");
-        for (uint32_t j = 0; j < W.lanes; ++j) offsets[W.b + j + 1] = out.n + R.lane_off[j + 1];
+        if (dev) {
+            dev->over = R.dev_overflow;
+            dev->total += R.count;
+            if (dev->total >= iso::INF) return fail(ISO_ESPACE, "more than 2^32 - 2 edges in one call");
+        } else {
+            for (uint32_t j = 0; j < W.lanes; ++j) offsets[W.b + j + 1] = out.n + R.lane_off[j + 1];
+        }
         out.n += R.count;
         g->last.lanes += W.lanes;
         g->last.active_cells += R.active_cells;
@@ -459,6 +501,12 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         if (r) return r;
     }
     g->last.edges = out.n;
+    if (dev) {
+        g->last.t_total_ms = now_ms() - t0;
+        return dev->over ? fail(ISO_ESPACE, "device edge buffer holds " + std::to_string(dev->cap) +
+                                                " pairs, the call found " + std::to_string(dev->total))
+                         : ISO_OK;
+    }
     if (!out.p) {   // no edges at all: a malloc'd placeholder
         out.pinned = false;
         if (!(out.p = (iso_edge *)std::malloc(sizeof(iso_edge))))
@@ -500,6 +548,62 @@ int iso_query_batch(iso_graph *g, size_t k, const uint32_t *sources, const uint3
     BusyGuard guard(g);
     if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
     return query_many(g, k, sources, taus, mode, edges, offsets);
+}
+
+// True if [p, p + bytes) lies inside one device allocation on `device`.
+static bool device_range_ok(const void *p, size_t bytes, int device) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (at.type != hipMemoryTypeDevice || at.device != device) return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = uintptr_t(base), q = uintptr_t(p);
+    return q >= b && bytes <= size && q - b <= size - bytes;
+}
+
+int iso_query_batch_device(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus, int mode,
+                           uint32_t *pairs, uint64_t cap, uint32_t *offsets, uint64_t *total, void *stream) {
+    if (total) *total = 0;
+    if (!offsets || !total || (k && (!sources || !taus)) || (cap && !pairs))
+        return fail(ISO_EINVAL, "NULL argument");
+    if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    for (size_t j = 0; j < k; ++j) {
+        int r = check_query(g, sources[j], taus[j], mode);
+        if (r) return r;
+    }
+    if (k >= iso::INF) return fail(ISO_EINVAL, "too many queries in one call");
+    if (cap > (uint64_t(1) << 60)) return fail(ISO_EINVAL, "capacity out of range");
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    if (!device_range_ok(offsets, (k + 1) * sizeof(uint32_t), g->D.device))
+        return fail(ISO_EINVAL, "offsets is not k + 1 words of device memory on the graph's device");
+    if (cap && !device_range_ok(pairs, cap * 2 * sizeof(uint32_t), g->D.device))
+        return fail(ISO_EINVAL, "pairs is not cap pairs of device memory on the graph's device");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    DevOut dev{pairs, offsets, cap, (hipStream_t)stream};
+    int r;
+    if (k == 0) {
+        isodev::SweepCtx &C = g->D.main;
+        const uint32_t zero = 0;
+        r = wait_for_caller(g->D, dev.caller, false);
+        if (!r)
+            r = hipMemcpyAsync(offsets, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, C.stream) == hipSuccess &&
+                        hipStreamSynchronize(C.stream) == hipSuccess
+                    ? ISO_OK
+                    : fail(ISO_EDEVICE, "writing the offsets failed");
+    } else {
+        r = query_many(g, k, sources, taus, mode, nullptr, nullptr, &dev);
+    }
+    *total = dev.total;
+    return r;
 }
 
 int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode, uint32_t *dist,
@@ -555,24 +659,29 @@ int iso_graph_get_layout(const iso_graph *g, iso_layout *L) {
 int iso_profile_enable(iso_graph *g, int enable) {
     if (!g) return fail(ISO_EINVAL, "NULL argument");
     if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
-    auto &P = g->D.main.prof;
-    hipEvent_t ev[6];
-    std::copy(std::begin(P.ev), std::end(P.ev), ev);
-    P = isodev::Profile();
-    std::copy(ev, ev + 6, P.ev);
-    P.on = enable != 0;
+    for (isodev::SweepCtx *C : {&g->D.main, &g->D.aux}) {   // aux: created with main's setting
+        auto &P = C->prof;
+        hipEvent_t ev[6];
+        std::copy(std::begin(P.ev), std::end(P.ev), ev);
+        P = isodev::Profile();
+        std::copy(ev, ev + 6, P.ev);
+        P.on = enable != 0;
+    }
     return ISO_OK;
 }
 
 int iso_profile_read(const iso_graph *g, iso_profile *o) {
     if (!g || !o) return fail(ISO_EINVAL, "NULL argument");
-    const auto &P = g->D.main.prof;
-    o->core_ms = P.core_ms; o->active_ms = P.active_ms; o->cell_ms = P.cell_ms; o->sort_ms = P.sort_ms;
-    o->core_launches = P.core_launches; o->cell_launches = P.cell_launches; o->calls = P.calls;
-    o->core_bytes = P.core_bytes; o->cell_bytes = P.cell_bytes;
-    o->core_entries = P.core_entries; o->cell_entries = P.cell_entries;
-    o->cell_vertices = P.cell_vertices; o->cells_swept = P.cells_swept;
-    o->cell_lanes = P.cell_lanes; o->cell_items = P.cell_items;
+    *o = iso_profile{};
+    for (const isodev::SweepCtx *C : {&g->D.main, &g->D.aux}) {   // both sweep contexts of query calls
+        const auto &P = C->prof;
+        o->core_ms += P.core_ms; o->active_ms += P.active_ms; o->cell_ms += P.cell_ms; o->sort_ms += P.sort_ms;
+        o->core_launches += P.core_launches; o->cell_launches += P.cell_launches; o->calls += P.calls;
+        o->core_bytes += P.core_bytes; o->cell_bytes += P.cell_bytes;
+        o->core_entries += P.core_entries; o->cell_entries += P.cell_entries;
+        o->cell_vertices += P.cell_vertices; o->cells_swept += P.cells_swept;
+        o->cell_lanes += P.cell_lanes; o->cell_items += P.cell_items;
+    }
     return ISO_OK;
 }
 

@@ -62,17 +62,17 @@ __device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t tail, uint3
     return (uint64_t(lane) << 58) | (uint64_t(tail) << 29) | uint64_t(head);
 }
 
-// Sorted keys -> (tail, head) pairs, and the first position of every lane: lane_off[l] = the
-// first i whose lane is >= l (lane_off is filled with the key count beforehand).
+// Sorted keys -> (tail, head) pairs, and the first position of every lane: lane_off[l] = base +
+// the first i whose lane is >= l (lane_off is filled with base + the key count beforehand).
 __global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *__restrict__ pairs,
-                         uint32_t *__restrict__ lane_off) {
+                         uint32_t *__restrict__ lane_off, uint32_t base) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t k = keys[i];
     pairs[i] = make_uint2(uint32_t(k >> 29) & ((1u << 29) - 1u), uint32_t(k) & ((1u << 29) - 1u));
     const uint32_t j = uint32_t(k >> 58);
     const uint32_t from = i ? uint32_t(keys[i - 1] >> 58) + 1u : 0u;
-    for (uint32_t l = from; l <= j; ++l) lane_off[l] = i;
+    for (uint32_t l = from; l <= j; ++l) lane_off[l] = base + i;
 }
 
 __global__ void k_fill(uint32_t *__restrict__ p, uint32_t value, uint64_t count) {
@@ -1353,9 +1353,11 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_perm, d_core_cell, d_core_ecc,
                 d_taus, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk};
     const bool prof_on = C.prof.on;
-    // the device sweep (table, core levels, active cells, cell sweep) has only per-context
-    // kernel arguments; with use_graph it is captured once per signature and replayed
-    const bool use_graph = A.use_graph && !prof_on;
+    // the core sweep (table and core levels, one launch per level) has only per-context kernel
+    // arguments; with use_graph it is captured once per signature and replayed.  The cell
+    // flags, the active cells and the cell sweep (three launches) follow it eagerly, so the
+    // phase events of the profile sit between whole launches in both cases.
+    const bool use_graph = A.use_graph;
     GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
                  A.cell_stage, A.cell_block, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
                                  uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
@@ -1387,18 +1389,17 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         cell_grid = uint32_t(std::max<uint64_t>(8, (want + 7) / 8 * 8));
     }
     bool replay = use_graph && C.graph_exec && std::memcmp(&sig, &C.sig, sizeof sig) == 0;
+    if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[0], s));
     if (use_graph && !replay) {
         if (C.graph_exec) hipGraphExecDestroy(C.graph_exec);
         C.graph_exec = nullptr;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     }
-    if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[0], s));
     // core sweep: the table levels as one (min,+) product, then one launch per level
     size_t nlev = core_lvl.size() - 1;
     size_t top = nlev_table;
-    uint32_t lg = 0;
+    const uint32_t lg = num_cells > 0 ? cell_lg : 0;
     if (replay) {
-        lg = C.lg;
         HIPCHK(hipGraphLaunch(C.graph_exec, s));
     } else {
         if (TX > 0) {
@@ -1426,25 +1427,6 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             grid = (grid + 7u) & ~7u;   // a multiple of 8 (the block mapping assumes it)
             k_core_level<<<dim3(grid), dim3(blk), 0, s>>>(CA, ls, vb, ve);
         }
-        if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
-        if (num_cells > 0) {
-            k_cell_masks<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(
-                d_cell_core_off, d_cell_core, vin, vout, d_uncovered, d_cell_off, d_src, K, num_cells,
-                A.mode_plain ? 1u : 0u, d_cmask);
-            k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(d_cmask, num_cells, cell_lg, d_clist,
-                                                                              d_items, B.d_counters);
-            lg = cell_lg;
-            CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
-                        d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
-                        uint32_t(cap), A.lane_base, lk, lg, num_cells};
-            if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
-            if (staged)
-                k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
-            else
-                k_cell_sweep<false><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
-        } else if (prof_on) {
-            HIPCHK(hipEventRecord(C.prof.ev[2], s));
-        }
     }
     if (use_graph && !replay) {
         hipGraph_t graph = nullptr;
@@ -1458,6 +1440,24 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         }
         C.sig = sig;
         HIPCHK(hipGraphLaunch(C.graph_exec, s));
+    }
+    if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
+    if (num_cells > 0) {
+        k_cell_masks<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(d_cell_core_off, d_cell_core, vin, vout,
+                                                                      d_uncovered, d_cell_off, d_src, K, num_cells,
+                                                                      A.mode_plain ? 1u : 0u, d_cmask);
+        k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(d_cmask, num_cells, cell_lg, d_clist,
+                                                                          d_items, B.d_counters);
+        CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
+                    d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
+                    uint32_t(cap), A.lane_base, lk, lg, num_cells};
+        if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
+        if (staged)
+            k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
+        else
+            k_cell_sweep<false><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
+    } else if (prof_on) {
+        HIPCHK(hipEventRecord(C.prof.ev[2], s));
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[3], s));
     HIPCHK(hipGetLastError());
@@ -1475,6 +1475,24 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     C.want_dist = A.want_dist;
     C.nlev = uint32_t(nlev);
     C.top = uint32_t(top);
+    return 0;
+}
+
+// Radix sort of a finished sweep's keys into d_keys_sorted (lane bits above 58, then tail,
+// then head); records the profile's sort-start event.
+int DevGraph::sort_keys(SweepCtx &C, uint32_t cnt_all) {
+    QueryBufs &B = C.bufs;
+    hipStream_t s = C.stream;
+    int end_bit = 58 + int(ilog2(std::max<uint32_t>(1, C.lane_base + C.K)));
+    if (end_bit > 64) end_bit = 64;
+    size_t tmp = 0;
+    int r;
+    HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
+                                             int(cnt_all), 0, end_bit, s));
+    if ((r = ensure((void **)&B.d_sort_tmp, B.sz_sort_tmp, tmp))) return r;
+    if (C.prof.on) HIPCHK(hipEventRecord(C.prof.ev[4], s));
+    HIPCHK(hipcub::DeviceRadixSort::SortKeys(B.d_sort_tmp, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
+                                             int(cnt_all), 0, end_bit, s));
     return 0;
 }
 
@@ -1539,26 +1557,44 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         }
     }
     if (R.overflow) return 0;   // caller grows the buffer and launches again
+    const auto tr0 = std::chrono::steady_clock::now();
+    if (R.dev_dst) {
+        // device destination: lanes [0, dev_lanes) of this sweep go to dev_pairs[dev_base ...) and
+        // their starts (plus dev_base) to dev_off[0 .. dev_lanes]; nothing is copied to the host
+        if (R.dev_overflow || uint64_t(R.dev_base) + cnt_all > std::min<uint64_t>(R.dev_cap, INF - 1)) {
+            R.dev_overflow = true;
+            R.t_result_ms = 0;
+            return 0;
+        }
+        k_fill<<<dim3(1), dim3(128), 0, s>>>(R.dev_off, R.dev_base + cnt_all, uint64_t(R.dev_lanes) + 1);
+        if (cnt_all) {
+            int r = sort_keys(C, cnt_all);
+            if (r) return r;
+            k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(
+                B.d_keys_sorted, cnt_all, reinterpret_cast<uint2 *>(R.dev_pairs) + R.dev_base, R.dev_off,
+                R.dev_base);
+            if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (prof.on && cnt_all) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, prof.ev[4], prof.ev[5]));
+            prof.sort_ms += ms;
+        }
+        R.t_result_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();
+        return 0;
+    }
     // sort the keys (lane bits above 58, then tail, then head), decode them into (tail, head)
     // pairs and lane starts on the device, copy both back
     R.lane_off.assign(size_t(K) + 1, 0);
-    const auto tr0 = std::chrono::steady_clock::now();
     if (cnt_all) {
-        int end_bit = 58 + int(ilog2(std::max<uint32_t>(1, C.lane_base + K)));
-        if (end_bit > 64) end_bit = 64;
-        size_t tmp = 0;
-        int r;
-        HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
-                                                 int(cnt_all), 0, end_bit, s));
-        if ((r = ensure((void **)&B.d_sort_tmp, B.sz_sort_tmp, tmp))) return r;
-        if (prof.on) HIPCHK(hipEventRecord(prof.ev[4], s));
-        HIPCHK(hipcub::DeviceRadixSort::SortKeys(B.d_sort_tmp, tmp, (const uint64_t *)B.d_keys,
-                                                 B.d_keys_sorted, int(cnt_all), 0, end_bit, s));
+        int r = sort_keys(C, cnt_all);
+        if (r) return r;
         k_fill<<<dim3(1), dim3(128), 0, s>>>(B.d_lane_off, cnt_all, uint64_t(K) + 1);
         // the pairs overwrite the unsorted keys (same size)
         k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(B.d_keys_sorted, cnt_all,
                                                                     reinterpret_cast<uint2 *>(B.d_keys),
-                                                                    B.d_lane_off);
+                                                                    B.d_lane_off, 0u);
         if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
         uint32_t *dst = nullptr;
         if (R.sink) {
