@@ -77,7 +77,7 @@ typedef struct {
  * their minimum weight (the answer is keyed on (tail, head), Section 3).
  */
 typedef struct {
-    uint32_t n;                 /* |V| (>= 1, < 2^29: edge keys pack two ids in 29 bits each) */
+    uint32_t n;                 /* |V| (>= 1, < 2^29: edge keys pack two ids of ceil(log2 n) bits each) */
     uint64_t m;                 /* |E| (number of entries in tail/head/weight) */
     const uint32_t *tail;       /* m tails, < n */
     const uint32_t *head;       /* m heads, < n */
@@ -181,7 +181,7 @@ int iso_last_query_stats(const iso_graph *g, iso_query_stats *stats);
 /*
  * Tuning knobs of the device sweep (chosen by the autotuner; when never set:
  * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 0,
- * cell_block 0).  lanes_per_launch: queries per sweep in
+ * cell_block 0, table_max 0).  lanes_per_launch: queries per sweep in
  * iso_query_batch (1..64); block: threads per workgroup of the core level
  * kernel (64..1024, multiple of 64); cell_lds_kb: LDS budget of one cell
  * workgroup in KiB (16..160), which sets how many queries' labels a cell
@@ -203,6 +203,12 @@ typedef struct {
                                    raised to the minimum the variant needs */
     uint32_t cell_block;        /* threads per cell workgroup: 256 or 512; 0 = 512 for sweeps of 32 or more
                                    queries, else 256 */
+    uint32_t table_max;         /* level-merge threshold: the top core levels are merged into one (min,+)
+                                   product with the distance table of their vertices while they hold at
+                                   most this many vertices; the levels below get one launch each.  0 =
+                                   4096; 1 = no table (every core level is its own launch and the upward
+                                   search runs to its end); 2..16384, capped at the table built at load
+                                   (iso_graph_info top_table) */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);

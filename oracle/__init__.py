@@ -49,6 +49,8 @@ def _load(path: str):
     lib.orc_edges_by_definition.argtypes = [_P, _U64P, C.c_uint64, C.POINTER(_U64P), _U64P]
     lib.orc_iso_dijkstra.restype = C.c_uint64
     lib.orc_iso_dijkstra.argtypes = [_P, _P, C.c_uint32, C.c_uint64, C.POINTER(_U64P), _U64P]
+    lib.orc_in_range.restype = C.c_uint64
+    lib.orc_in_range.argtypes = [_P, _P, C.c_uint32, C.c_uint64, C.POINTER(_U32P)]
     lib.orc_free.argtypes = [_P]
     return lib
 
@@ -135,6 +137,16 @@ class Oracle:
         self._L.orc_edges_by_definition(self._g, d.ctypes.data_as(_U64P), int(tau),
                                         C.byref(ptr), C.byref(cnt))
         return _take_edges(self._L, ptr, cnt)
+
+    def in_range(self, s: int, tau: int) -> np.ndarray:
+        """The vertices with d(s, v) <= tau (Section 3), sorted, as uint32."""
+        _check_source(s, self.n)
+        ptr = _U32P()
+        cnt = int(self._L.orc_in_range(self._g, self._ws, int(s), int(tau), C.byref(ptr)))
+        try:
+            return np.ctypeslib.as_array(ptr, shape=(cnt,)).copy() if cnt else np.zeros(0, dtype=np.uint32)
+        finally:
+            self._L.orc_free(ptr)
 
     def iso_dijkstra(self, s: int, tau: int):
         """The paper's isoDijkstra: (edges, settled count).  Requires tau < 2^64-1."""

@@ -307,6 +307,27 @@ void orc_edges_by_definition(const orc_graph *g, const uint64_t *dist, uint64_t 
     *edges_out = buf;
 }
 
+/*
+ * The vertices in range (Section 3): v with d(s,v) <= tau, i.e. exactly the
+ * vertices the bounded Dijkstra settles, in increasing id.  *verts_out:
+ * malloc'ed, release with orc_free.  Returns their number.
+ */
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return (x > y) - (x < y);
+}
+
+uint64_t orc_in_range(const orc_graph *g, orc_ws *ws, uint32_t s, uint64_t tau, uint32_t **verts_out)
+{
+    uint64_t settled = bounded_dijkstra(g, ws, s, tau);
+    uint32_t *buf = malloc((settled ? settled : 1) * sizeof(uint32_t));
+    for (uint64_t i = 0; i < settled; ++i) buf[i] = ws->order[i];
+    qsort(buf, settled, sizeof(uint32_t), cmp_u32);
+    *verts_out = buf;
+    return settled;
+}
+
 /* ------------------------------------------------- isoDijkstra (Section 3) */
 
 /*

@@ -1,6 +1,8 @@
 """Autotuner for the device sweep: queries per launch, core-kernel block size, LDS budget per
 cell workgroup (which sets the queries per cell work item), the cell-kernel variant (level
-pipeline or whole cell in LDS) and hipGraph replay.
+pipeline or whole cell in LDS), hipGraph replay and the level-merge threshold (how many
+vertices of the top core levels are merged into one distance-table product instead of one
+launch per level).
 
 Coordinate search: starting from the defaults, each knob in turn is set to every candidate
 value while the others stay fixed; the best throughput (queries/s of iso_query_batch on a
@@ -24,8 +26,10 @@ SPACE = {
     "block": [128, 256, 512],
     "cell_lds_kb": [24, 40, 64, 96],
     "use_graph": [0, 1],
+    "table_max": [0, 1024, 8192, 16384],
 }
-DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 0, "cell_block": 0}
+DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 0, "cell_block": 0,
+           "table_max": 0}
 
 
 def measure(G: Graph, sources, taus, mode=MODE_CELLS, repeats: int = 2) -> float:

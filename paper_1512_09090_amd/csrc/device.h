@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <functional>
@@ -16,7 +17,8 @@ void set_error(const std::string &msg);   // thread-local message behind iso_las
 namespace isodev {
 
 constexpr size_t LDS_MAX = 160 * 1024;          // LDS of one gfx950 compute unit
-constexpr uint32_t TABLE_MAX = 4096;            // vertices of the top-of-hierarchy distance table
+constexpr uint32_t TABLE_MAX = 16384;           // vertices of the top-of-hierarchy distance table built at load
+constexpr uint32_t TABLE_DEFAULT = 4096;        // vertices of the levels merged into it by default
 constexpr uint32_t MAX_LANES = 64;
 constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a 6-bit lane chunk
 
@@ -32,6 +34,8 @@ struct RunArgs {
     bool mode_plain = true;
     bool want_dist = false;
     size_t out_cap = 0;          // capacity of the edge-key buffer
+    uint32_t table_x = 0;        // top table used: core positions [0, table_x), the first table_levels levels
+    uint32_t table_levels = 0;
     std::vector<uint32_t> taus;      // k_pow2 (padding lanes: INF)
     std::vector<uint32_t> src_cell;  // k_pow2 (padding lanes: NO_CELL)
     // upward-search labels per lane: positions and labels inside the top table X
@@ -87,10 +91,11 @@ struct Profile {
 
 // Everything the captured sweep sequence depends on (kernel arguments and grid shapes).
 struct GraphSig {
-    uint32_t K, plain, dist, block, cell_lds, xcap, cell_stage, cell_block;
+    uint32_t K, plain, dist, block, cell_lds, xcap, cell_stage, cell_block, table_x, table_levels;   // no padding
     uint64_t cap;
     uint64_t ptr[10];
 };
+static_assert(sizeof(GraphSig) == 10 * 4 + 8 + 10 * 8, "GraphSig is compared with memcmp: no padding");
 
 // One sweep in flight: its stream, buffers, profile and the state kept between launch and
 // finish.  Several contexts over one DevGraph run concurrently (the serving loop).
@@ -115,6 +120,7 @@ struct SweepCtx {
 struct DevGraph {
     int device = -1;
     uint32_t n = 0, n_core = 0, num_cells = 0;
+    uint32_t id_bits = 29;   // bits per vertex id in an edge key: lane << 2b | tail << b | head
     // core levels (host copy), and prefix sums used to size the LDS top block
     std::vector<uint32_t> core_lvl;
     std::vector<uint32_t> core_lvl_entries;   // down_off at each core level boundary
@@ -124,6 +130,17 @@ struct DevGraph {
     // top-of-hierarchy table: X = core positions [0, TX) covering the first nlev_table levels;
     // d_table[y * TX + x] = shortest downward path y -> x inside X
     uint32_t TX = 0, nlev_table = 0;
+    // the largest prefix of the table's levels with at most `want` vertices (0 = TABLE_DEFAULT;
+    // 1 = no table)
+    void table_cut(uint32_t want, uint32_t &tx, uint32_t &levels) const {
+        const uint32_t cap = want == 1 ? 0u : std::min(want ? want : TABLE_DEFAULT, TX);
+        tx = 0;
+        levels = 0;
+        for (uint32_t l = 0; l < nlev_table && core_lvl[l + 1] <= cap; ++l) {
+            tx = core_lvl[l + 1];
+            levels = l + 1;
+        }
+    }
     uint32_t *d_table = nullptr;
     uint8_t *d_uncovered = nullptr;
     uint32_t *d_cell_core_off = nullptr, *d_cell_core = nullptr;   // core positions of each cell (CSR)

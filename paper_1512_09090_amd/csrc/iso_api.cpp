@@ -68,7 +68,8 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     A.sval.assign(lanes, {});
     {
         std::atomic<uint32_t> next{0};
-        const uint32_t TX = g->D.TX;
+        g->D.table_cut(g->tuning.table_max, A.table_x, A.table_levels);
+        const uint32_t TX = A.table_x;   // the upward searches stop at the table's vertices
         const std::function<void(int)> work = [&](int w) {
             std::vector<std::pair<uint32_t, uint32_t>> &U = g->up_out[w];
             for (;;) {
@@ -700,6 +701,7 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (t->cell_stage > 1) return fail(ISO_EINVAL, "cell_stage must be 0 or 1");
     if (t->cell_block != 0 && t->cell_block != 256 && t->cell_block != 512)
         return fail(ISO_EINVAL, "cell_block must be 0, 256 or 512");
+    if (t->table_max > isodev::TABLE_MAX) return fail(ISO_EINVAL, "table_max must be at most 16384");
     if (t->core_mode != 0)
         return fail(ISO_EINVAL, "core_mode must be 0: the single-launch core sweep with a grid barrier "
                                 "is disabled");

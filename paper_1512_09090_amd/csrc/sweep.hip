@@ -24,9 +24,10 @@
 // k queries share one sweep: labels are stored k-interleaved (row of k uint32
 // per vertex).  In the core kernels a group of S*k lanes serves one vertex:
 // k lanes (one per query) times S sub-lanes that split the vertex's arc list,
-// combined by a shuffle-xor minimum.  Isochrone edges are appended with one
-// atomic per wavefront (ballot + popcount) as 64-bit keys
-// lane << 58 | tail << 29 | head, then radix-sorted (query, tail, head).
+// combined by a shuffle-xor minimum.  Isochrone edges are collected per
+// workgroup in LDS and appended with one output reservation per workgroup as
+// 64-bit keys lane << 2b | tail << b | head (b = bits of a vertex id), then
+// radix-sorted over their 2b + log2 k bits (query, tail, head).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -58,20 +59,21 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
     return s < a ? INF : s;
 }
 
-__device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t tail, uint32_t head) {
-    return (uint64_t(lane) << 58) | (uint64_t(tail) << 29) | uint64_t(head);
+__device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t tail, uint32_t head, uint32_t ib) {
+    return (uint64_t(lane) << (2 * ib)) | (uint64_t(tail) << ib) | uint64_t(head);
 }
 
 // Sorted keys -> (tail, head) pairs, and the first position of every lane: lane_off[l] = base +
 // the first i whose lane is >= l (lane_off is filled with base + the key count beforehand).
 __global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *__restrict__ pairs,
-                         uint32_t *__restrict__ lane_off, uint32_t base) {
+                         uint32_t *__restrict__ lane_off, uint32_t base, uint32_t ib) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t k = keys[i];
-    pairs[i] = make_uint2(uint32_t(k >> 29) & ((1u << 29) - 1u), uint32_t(k) & ((1u << 29) - 1u));
-    const uint32_t j = uint32_t(k >> 58);
-    const uint32_t from = i ? uint32_t(keys[i - 1] >> 58) + 1u : 0u;
+    const uint32_t mask = (1u << ib) - 1u;
+    pairs[i] = make_uint2(uint32_t(k >> ib) & mask, uint32_t(k) & mask);
+    const uint32_t j = uint32_t(k >> (2 * ib));
+    const uint32_t from = i ? uint32_t(keys[i - 1] >> (2 * ib)) + 1u : 0u;
     for (uint32_t l = from; l <= j; ++l) lane_off[l] = base + i;
 }
 
@@ -126,7 +128,7 @@ struct CoreArgs {
     uint64_t *vin, *vout;   // per core vertex: lanes with d <= tau, lanes with d + ecc > tau
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk;
+    uint32_t out_cap, lane_base, lk, ib;
 };
 
 // Per (vertex, lane, sub-lane): bit k of `in` / `flag` tells whether the sub-lane's k-th entry
@@ -217,8 +219,8 @@ __device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &
         st &= st - 1u;
         const uint2 a = have ? arc(beg + sub + k * S) : make_uint2(0u, 0u);
         const uint32_t ot = have ? A.perm[a.x & TAIL_MASK] : 0u;
-        push_key(have && (a.x & FLAG_FWD), edge_key(lane, ot, ov), s_keys, s_n, A);
-        push_key(have && (a.x & FLAG_REV), edge_key(lane, ov, ot), s_keys, s_n, A);
+        push_key(have && (a.x & FLAG_FWD), edge_key(lane, ot, ov, A.ib), s_keys, s_n, A);
+        push_key(have && (a.x & FLAG_REV), edge_key(lane, ov, ot, A.ib), s_keys, s_n, A);
     }
     uint32_t e = walk ? beg + sub : 0, stop = walk ? end : 0;
     while (__any(e < stop)) {
@@ -227,8 +229,8 @@ __device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &
         const uint32_t tl = a.x & TAIL_MASK;
         const bool str = have && (a.x & FLAGS) && ((lab(tl) <= tau) != vin);
         const uint32_t ot = str ? A.perm[tl] : 0u;
-        push_key(str && (a.x & FLAG_FWD), edge_key(lane, ot, ov), s_keys, s_n, A);
-        push_key(str && (a.x & FLAG_REV), edge_key(lane, ov, ot), s_keys, s_n, A);
+        push_key(str && (a.x & FLAG_FWD), edge_key(lane, ot, ov, A.ib), s_keys, s_n, A);
+        push_key(str && (a.x & FLAG_REV), edge_key(lane, ov, ot, A.ib), s_keys, s_n, A);
         e += S;
     }
 }
@@ -258,10 +260,13 @@ __device__ __forceinline__ void keys_end(uint64_t *s_keys, uint32_t *s_n, uint32
 //   d(x) = min over reached y in X of up(y) + D[y][x]
 // - a shortest up-down path to x (Section 2, CH) through its first vertex in X,
 // written as one (min,+) product instead of a level-by-level sweep of X.
-// One wavefront per (64-column tile, lane, split of the lane's upward list); the
-// splits are combined with atomicMin into dcore (pre-filled with INF).
+// The levels of X are a prefix of the table's levels, and a path between two vertices of a
+// prefix stays inside it (it goes up, then down), so the table of a prefix is the top-left
+// corner of the table (rows `stride` apart).  One wavefront per (64-column tile, lane, split
+// of the lane's upward list); the splits are combined with atomicMin into dcore (pre-filled
+// with INF).
 __global__ void __launch_bounds__(64)
-k_top_table(const uint32_t *__restrict__ D, uint32_t TX, const uint32_t *__restrict__ xptr,
+k_top_table(const uint32_t *__restrict__ D, uint32_t TX, uint32_t stride, const uint32_t *__restrict__ xptr,
             const uint32_t *__restrict__ xpos, const uint32_t *__restrict__ xval, uint32_t *__restrict__ dcore,
             uint32_t lk, uint32_t tiles, uint32_t splits) {
     const uint32_t K = 1u << lk;
@@ -278,17 +283,16 @@ k_top_table(const uint32_t *__restrict__ D, uint32_t TX, const uint32_t *__restr
         uint32_t e = e0;
         for (; e + 4 <= e1; e += 4) {
             uint32_t y0 = xpos[e], y1 = xpos[e + 1], y2 = xpos[e + 2], y3 = xpos[e + 3];
-            uint32_t d0 = D[size_t(y0) * TX + x], d1 = D[size_t(y1) * TX + x];
-            uint32_t d2 = D[size_t(y2) * TX + x], d3 = D[size_t(y3) * TX + x];
+            uint32_t d0 = D[size_t(y0) * stride + x], d1 = D[size_t(y1) * stride + x];
+            uint32_t d2 = D[size_t(y2) * stride + x], d3 = D[size_t(y3) * stride + x];
             acc = min(min(acc, min(sat_add(xval[e], d0), sat_add(xval[e + 1], d1))),
                       min(sat_add(xval[e + 2], d2), sat_add(xval[e + 3], d3)));
         }
-        for (; e < e1; ++e) acc = min(acc, sat_add(xval[e], D[size_t(xpos[e]) * TX + x]));
+        for (; e < e1; ++e) acc = min(acc, sat_add(xval[e], D[size_t(xpos[e]) * stride + x]));
         if (acc != INF) atomicMin(&dcore[(x << lk) + j], acc);
     }
 }
 
-// Flags and isochrone edges of the table vertices (all their labels are final).
 // Flags and isochrone edges of the table vertices (all their labels are final).  S = 1 << ls
 // sub-lanes per (vertex, lane) split the entry list: the first pass over the entries finds
 // which sub-lanes can hold a straddling arc, the second emits them.
@@ -471,7 +475,7 @@ struct CellArgs {
     uint32_t *dist_out;
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk, lg, num_cells;
+    uint32_t out_cap, lane_base, lk, lg, num_cells, ib;
 };
 
 // Cell workgroups have 256 or 512 threads (the cell_block knob); the item code reads blockDim.x.
@@ -501,6 +505,31 @@ struct CellBits {
         }
     }
 };
+// Relaxes internal vertex v's entries [e0, e1) for the thread's lane slot j into dv, recording
+// the extraction bits.  Entries are taken four at a time: the four entry reads are issued,
+// then the four label reads, so a vertex of up to four entries waits for two LDS round trips
+// instead of two per entry.  Slots past e1 repeat entry e1 - 1 (harmless for the minimum) and
+// record no bits.  The loop count is the same for the lanes of one vertex group only, so the
+// loop is divergent across the wavefront like the one-entry loop it replaces.
+template <class LOAD>
+__device__ __forceinline__ void relax_cell_vertex(uint32_t e0, uint32_t e1, uint32_t &dv, CellBits &bits,
+                                                  uint32_t tau, const uint32_t *s_lab, uint32_t lg, uint32_t j,
+                                                  LOAD load) {
+    for (uint32_t e = e0; e < e1; e += 4) {
+        uint2 x[4];
+        uint32_t lt[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) x[u] = load(min(e + u, e1 - 1));
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) lt[u] = s_lab[((x[u].x & LOCAL_MASK) << lg) + j];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            dv = min(dv, sat_add(lt[u], x[u].y));
+            if (e + u < e1) bits.see(e + u - e0, x[u].x, lt[u] <= tau);
+        }
+    }
+}
+
 constexpr uint32_t CELL_BUF = 512;         // entries per LDS level buffer (two buffers)
 constexpr uint32_t CELL_REGS = CELL_BUF / 256;   // entries per thread held for the next level (at most)
 
@@ -521,7 +550,7 @@ __device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, c
     const uint32_t ov = A.perm[cb + i];
     const uint32_t ot = A.perm[lt < cnt ? cb + lt : ref(lt - cnt)];
     const uint32_t lane = A.lane_base + nth_set_bit(lanes, (q << A.lg) + j);
-    return (word >> 31) ? edge_key(lane, ov, ot) : edge_key(lane, ot, ov);
+    return (word >> 31) ? edge_key(lane, ov, ot, A.ib) : edge_key(lane, ot, ov, A.ib);
 }
 
 // Wavefront-aggregated append of a candidate to the LDS list (count in ctl[0]); every lane of
@@ -757,20 +786,13 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             if (in_buf) {
                 // the level's entries are all in the LDS buffer: no global load here, so the
                 // next level's loads stay in flight
-                for (uint32_t e = e0; e < e1; ++e) {
-                    const uint2 x = cur[e - ebase];
-                    const uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
-                    dv = min(dv, sat_add(lt, x.y));
-                    bits.see(e - e0, x.x, lt <= tau);
-                }
+                relax_cell_vertex(e0, e1, dv, bits, tau, s_lab, lg, j,
+                                  [&](uint32_t e) { return cur[e - ebase]; });
             } else {
-                for (uint32_t e = e0; e < e1; ++e) {
+                relax_cell_vertex(e0, e1, dv, bits, tau, s_lab, lg, j, [&](uint32_t e) {
                     const uint32_t le = e - ebase;
-                    const uint2 x = le < CELL_BUF ? cur[le] : gent[e];
-                    const uint32_t lt = s_lab[((x.x & LOCAL_MASK) << lg) + j];
-                    dv = min(dv, sat_add(lt, x.y));
-                    bits.see(e - e0, x.x, lt <= tau);
-                }
+                    return le < CELL_BUF ? cur[le] : gent[e];
+                });
             }
             if (act) {
                 s_lab[(i << lg) + j] = dv;
@@ -1003,6 +1025,8 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     HIPCHK(hipSetDevice(device));
     n = P.n;
     n_core = P.n_core;
+    id_bits = 1;   // bits of a vertex id in an edge key (n < 2^29)
+    while (id_bits < 29 && (uint64_t(1) << id_bits) < uint64_t(n)) ++id_bits;
     num_cells = P.num_cells;
     core_lvl = P.core_lvl;
     core_lvl_entries.resize(core_lvl.size());
@@ -1351,7 +1375,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     uint64_t *d_cmask = reinterpret_cast<uint64_t *>(B.d_list);
     uint32_t *d_clist = B.d_list + 2 * size_t(num_cells), *d_items = d_clist + num_cells;
     CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_perm, d_core_cell, d_core_ecc,
-                d_taus, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk};
+                d_taus, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, id_bits};
     const bool prof_on = C.prof.on;
     // the core sweep (table and core levels, one launch per level) has only per-context kernel
     // arguments; with use_graph it is captured once per signature and replayed.  The cell
@@ -1359,7 +1383,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     // phase events of the profile sit between whole launches in both cases.
     const bool use_graph = A.use_graph;
     GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
-                 A.cell_stage, A.cell_block, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
+                 A.cell_stage, A.cell_block, A.table_x, A.table_levels, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
                                  uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
                                  uint64_t(uintptr_t(B.d_keys)), uint64_t(uintptr_t(B.d_flags)),
                                  uint64_t(uintptr_t(B.d_counters)), uint64_t(uintptr_t(B.d_list)),
@@ -1397,25 +1421,26 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     }
     // core sweep: the table levels as one (min,+) product, then one launch per level
     size_t nlev = core_lvl.size() - 1;
-    size_t top = nlev_table;
+    const uint32_t tx = A.table_x;
+    size_t top = A.table_levels;
     const uint32_t lg = num_cells > 0 ? cell_lg : 0;
     if (replay) {
         HIPCHK(hipGraphLaunch(C.graph_exec, s));
     } else {
-        if (TX > 0) {
-            k_fill<<<dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (TX * K + 255) / 256))), dim3(256), 0, s>>>(
-                B.d_dcore, INF, uint64_t(TX) * K);
-            uint32_t tiles = (TX + 63) / 64;
+        if (tx > 0) {
+            k_fill<<<dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (tx * K + 255) / 256))), dim3(256), 0, s>>>(
+                B.d_dcore, INF, uint64_t(tx) * K);
+            uint32_t tiles = (tx + 63) / 64;
             // splits of each lane's upward list: enough wavefronts to cover the chip
             uint32_t splits = std::max<uint32_t>(1, std::min<uint32_t>(64, 4096 / std::max<uint32_t>(1, tiles * K)));
-            k_top_table<<<dim3(tiles * K * splits), dim3(64), 0, s>>>(d_table, TX, d_xptr, d_xpos, d_xval, B.d_dcore,
-                                                                       lk, tiles, splits);
+            k_top_table<<<dim3(tiles * K * splits), dim3(64), 0, s>>>(d_table, tx, TX, d_xptr, d_xpos, d_xval,
+                                                                       B.d_dcore, lk, tiles, splits);
             {
                 // sub-lanes per vertex from the mean entry count of the table vertices
-                uint32_t deg = (core_lvl_entries[nlev_table] + TX - 1) / TX;
+                uint32_t deg = (core_lvl_entries[top] + tx - 1) / tx;
                 uint32_t ls = 0;
                 while ((1u << ls) < deg && (K << (ls + 1)) <= 64u) ++ls;
-                k_top_finish<<<dim3(uint32_t(((uint64_t(TX) << (lk + ls)) + 255) / 256)), dim3(256), 0, s>>>(CA, TX, ls);
+                k_top_finish<<<dim3(uint32_t(((uint64_t(tx) << (lk + ls)) + 255) / 256)), dim3(256), 0, s>>>(CA, tx, ls);
             }
         }
         const uint32_t blk = A.block;
@@ -1450,7 +1475,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                                                                           d_items, B.d_counters);
         CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
                     d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
-                    uint32_t(cap), A.lane_base, lk, lg, num_cells};
+                    uint32_t(cap), A.lane_base, lk, lg, num_cells, id_bits};
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
         if (staged)
             k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
@@ -1483,7 +1508,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
 int DevGraph::sort_keys(SweepCtx &C, uint32_t cnt_all) {
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
-    int end_bit = 58 + int(ilog2(std::max<uint32_t>(1, C.lane_base + C.K)));
+    int end_bit = 2 * int(id_bits) + int(ilog2(std::max<uint32_t>(1, C.lane_base + C.K)));
     if (end_bit > 64) end_bit = 64;
     size_t tmp = 0;
     int r;
@@ -1527,7 +1552,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         prof.calls++;
         HIPCHK(hipEventElapsedTime(&ms, prof.ev[0], prof.ev[1]));
         prof.core_ms += ms;
-        prof.core_launches += (TX > 0 ? 3 : 0) + (C.nlev - C.top);
+        prof.core_launches += (C.top > 0 ? 3 : 0) + (C.nlev - C.top);
         prof.core_entries += core_entries;
         // offsets + entries + cell ids and eccentricities + k labels written and read back once
         prof.core_bytes += 4ull * (n_core + 1) + 8ull * core_entries + 8ull * n_core + uint64_t(K) * 8ull * n_core;
@@ -1572,7 +1597,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
             if (r) return r;
             k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(
                 B.d_keys_sorted, cnt_all, reinterpret_cast<uint2 *>(R.dev_pairs) + R.dev_base, R.dev_off,
-                R.dev_base);
+                R.dev_base, id_bits);
             if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
         }
         HIPCHK(hipStreamSynchronize(s));
@@ -1594,7 +1619,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         // the pairs overwrite the unsorted keys (same size)
         k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(B.d_keys_sorted, cnt_all,
                                                                     reinterpret_cast<uint2 *>(B.d_keys),
-                                                                    B.d_lane_off, 0u);
+                                                                    B.d_lane_off, 0u, id_bits);
         if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
         uint32_t *dst = nullptr;
         if (R.sink) {

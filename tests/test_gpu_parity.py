@@ -337,3 +337,31 @@ def test_staged_cell_kernel(road50k, k):
     for j in range(0, k, max(1, k // 3)):
         want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
         np.testing.assert_array_equal(ref[iso.MODE_CELLS][j], want)
+
+
+def test_results_identical_across_table_sizes(road50k):
+    """The level-merge threshold moves core levels between the distance-table product and the
+    per-level launches (and where the upward searches stop); results must not change.  1 = no
+    table at all."""
+    g, orc, G = road50k
+    built = G.info()["top_table"]
+    say(f"table built at load: {built} vertices")
+    src, tau = synth.batch_queries(g.n, 20, seed=91, lo_min=1, hi_min=120)
+    G.set_tuning()
+    ref = {m: G.query_batch(src, tau, m) for m in (iso.MODE_CELLS, iso.MODE_PLAIN)}
+    d_ref, _ = G.distances(int(src[2]), int(tau[2]), iso.MODE_PLAIN)
+    for tm in (1, 2, 64, 700, built, 16384):
+        for graph in (0, 1):
+            say(f"table_max={tm} use_graph={graph}")
+            G.set_tuning(table_max=tm, use_graph=graph, lanes_per_launch=8)
+            for m in (iso.MODE_CELLS, iso.MODE_PLAIN):
+                out = G.query_batch(src, tau, m)
+                for j in range(len(src)):
+                    np.testing.assert_array_equal(out[j], ref[m][j], err_msg=f"table_max {tm} mode {m} lane {j}")
+            d, _ = G.distances(int(src[2]), int(tau[2]), iso.MODE_PLAIN)
+            np.testing.assert_array_equal(d, d_ref)
+    G.set_tuning()
+    np.testing.assert_array_equal(d_ref, clamp_u32(orc.distances(int(src[2]))))
+    for j in (0, 7, 19):
+        want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
+        np.testing.assert_array_equal(ref[iso.MODE_CELLS][j], want)

@@ -32,6 +32,12 @@ MUTANTS = {
     "isodij_no_out_sweep": ("            if (is_settled(ws, g->out_head[e]))\n"
                             "                buf = push_key(buf, &cnt, &cap, v, g->out_head[e]);",
                             "            ;"),
+    "in_range_drops_one": ("for (uint64_t i = 0; i < settled; ++i) buf[i] = ws->order[i];\n"
+                           "    qsort(buf, settled, sizeof(uint32_t), cmp_u32);\n    *verts_out = buf;\n"
+                           "    return settled;",
+                           "for (uint64_t i = 0; i < settled; ++i) buf[i] = ws->order[i];\n"
+                           "    qsort(buf, settled, sizeof(uint32_t), cmp_u32);\n    *verts_out = buf;\n"
+                           "    return settled ? settled - 1 : 0;"),
     "relax_wrong_weight": ("uint64_t nd = it.key + g->out_w[e];\n            if (nd < get_dist(ws, v)) {\n"
                            "                set_dist(ws, v, nd);\n                heap_push(ws, nd, v);\n            }\n        }\n    }\n    return",
                            "uint64_t nd = it.key + g->out_w[e] / 2;\n            if (nd < get_dist(ws, v)) {\n"
@@ -56,6 +62,9 @@ def _pins_pass(libpath) -> bool:
             if not np.array_equal(orc.iso_dijkstra(0, tau)[0], want):
                 return False
             if not np.array_equal(orc.edges_by_definition(as_u64(bf), tau), want):
+                return False
+            inr = [v for v in range(g.n) if bf[v] is not None and bf[v] <= tau]
+            if not np.array_equal(orc.in_range(0, tau), np.array(inr, dtype=np.uint32)):
                 return False
     # closed form
     g = synth.uniform_grid(21, 3)

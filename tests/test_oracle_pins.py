@@ -76,6 +76,9 @@ def test_bellman_ford_random_digraphs(seed):
             np.testing.assert_array_equal(e2, want)
             assert settled2 == settled
             np.testing.assert_array_equal(orc.edges_by_definition(as_u64(bf), tau), want)
+            # the vertices in range (Section 3), against the brute-force distances
+            inr = [v for v in range(n) if bf[v] is not None and bf[v] <= tau]
+            np.testing.assert_array_equal(orc.in_range(s, tau), np.array(inr, dtype=np.uint32))
 
 
 # ---------------------------------------------------------------- library routine
@@ -121,6 +124,7 @@ def test_uniform_grid_closed_form(c):
             edges, _, settled = orc.isochrone(s, tau)
             assert len(edges) == 8 * (2 * r + 1), (r, tau)
             assert settled == 2 * r * (r + 1) + 1          # |{L1 <= r}| in Z^2
+            np.testing.assert_array_equal(orc.in_range(s, tau), np.flatnonzero(l1 <= r).astype(np.uint32))
             lt, lh = l1[edges[:, 0]], l1[edges[:, 1]]
             assert np.all(np.minimum(lt, lh) == r) and np.all(np.maximum(lt, lh) == r + 1)
 
@@ -134,6 +138,7 @@ def test_tau_zero_is_star_of_source(name):
     for s in [0, 1, 63, 2080, 4095]:
         edges, _, settled = orc.isochrone(s, 0)
         assert settled == 1
+        np.testing.assert_array_equal(orc.in_range(s, 0), [s])
         star = {(s, int(h)) for h in g.head[g.tail == s]} | {(int(t), s) for t in g.tail[g.head == s]}
         assert set(map(tuple, edges.tolist())) == star
 
@@ -170,6 +175,7 @@ def test_tau_beyond_every_distance():
     assert np.all(d != INF)
     edges, _, settled = orc.isochrone(7, int(d.max()))
     assert settled == g.n and len(edges) == 0
+    np.testing.assert_array_equal(orc.in_range(7, int(d.max())), np.arange(g.n, dtype=np.uint32))
     # with unreachable vertices the only survivors are arcs entering the reachable part
     for seed in range(8):
         rg = synth.random_digraph(25, 40, seed=100 + seed, zero_frac=0.0, simple=True)
