@@ -417,6 +417,21 @@ def main():
     qps_plain = np_steps * lanes / (time.perf_counter() - t0)
     log(f"plain batched (device output): {qps_plain:.1f} queries/s")
 
+    # the other output of Section 3: vertices in range, as one bitmap row per query over the
+    # original ids, left in HBM (one call per batch of `lanes` queries)
+    W = (info["n"] + 63) // 64
+    vbits = torch.empty((lanes, W), dtype=torch.int64, device="cuda:0")
+    vs_, vt_ = window(args.warmup * lanes, max(2, args.steps // 4) * lanes)
+    G.query_batch_vertices_device(vs_[:lanes], vt_[:lanes], iso.MODE_CELLS, vbits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(0, len(vs_), lanes):
+        G.query_batch_vertices_device(vs_[b:b + lanes], vt_[b:b + lanes], iso.MODE_CELLS, vbits)
+    torch.cuda.synchronize()
+    qps_vert = len(vs_) / (time.perf_counter() - t0)
+    in_range = int(np.bitwise_count(vbits.cpu().numpy().view(np.uint64)).sum())
+    log(f"vertices in range (device bitmaps): {qps_vert:.1f} queries/s; last batch {in_range} (vertex, query) pairs")
+
     # single-query latency (one query per call)
     lat = {}
     single_qps = {}
@@ -497,6 +512,10 @@ def main():
                          "note": "iso_query_batch, edges copied to host memory (PCIe included)",
                          "call_ms_p50": round(1000 * percentile(times, 50), 3),
                          "call_ms_p99": round(1000 * percentile(times, 99), 3)},
+        "vertex_output_qps": {"value": round(qps_vert, 2), "queries_per_call": lanes,
+                              "bitmap_bytes_per_call": lanes * W * 8, "in_range_pairs_last_call": in_range,
+                              "note": "iso_query_batch_vertices_device: the vertices in range of each query "
+                                      "as a bitmap over the original ids, left in HBM"},
         "queries_per_sweep_qps": sweep,
         "timed_call": dict(batch_stats, edges_in_hbm=int(edges_total)),
         "serving": serve,

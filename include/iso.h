@@ -166,6 +166,30 @@ int iso_query_batch_device(iso_graph *g, size_t k, const uint32_t *sources, cons
                            uint64_t *total, void *stream);
 
 /*
+ * The other output that Section 3 says every approach can serve: the set of
+ * vertices in range, d(s, v) <= tau, instead of the isochrone edges.  In
+ * ISO_MODE_CELLS the internal vertices of a cell that is not swept for a
+ * query are in range exactly when one of the cell's core vertices is (the
+ * flag rule of Section 5 then guarantees d(u) + ecc(u) <= tau for all of
+ * them), so they are output without being swept.
+ *
+ * iso_query_batch_vertices_device: k (1..64) queries in one sweep.  bits is
+ * caller-owned device memory on the graph's device (e.g. a torch tensor)
+ * holding k rows of W = ceil(n / 64) words, checked to lie inside one device
+ * allocation (ISO_EINVAL before any work otherwise); bit (v mod 64) of word
+ * bits[j * W + v / 64] is set iff original vertex v is in range of query j,
+ * and every bit of the k rows is written.  stream as in
+ * iso_query_batch_device; the call returns after the writes are complete.
+ */
+int iso_query_batch_vertices_device(iso_graph *g, size_t k, const uint32_t *sources,
+                                    const uint32_t *taus, int mode, uint64_t *bits, void *stream);
+
+/* The vertices in range of one query as sorted original ids (library-allocated,
+ * release with iso_free); *count of them. */
+int iso_query_vertices(iso_graph *g, uint32_t source, uint32_t tau, int mode,
+                       uint32_t **vertices, size_t *count);
+
+/*
  * Distance labels of one query (test hook).  dist (n entries, caller host
  * memory) receives min(d(s, v), ISO_INF) for every vertex the sweep labelled
  * (all vertices in ISO_MODE_PLAIN; core vertices and the vertices of active

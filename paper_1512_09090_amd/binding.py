@@ -129,6 +129,10 @@ def lib():
                                   C.POINTER(C.c_size_t)]
     L.iso_query_batch_device.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.c_void_p, C.c_uint64,
                                          C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p]
+    L.iso_query_batch_vertices_device.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.c_void_p,
+                                                  C.c_void_p]
+    L.iso_query_vertices.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.POINTER(_U32P),
+                                     C.POINTER(C.c_size_t)]
     L.iso_query_distances.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, _U32P, C.POINTER(C.c_uint8)]
     L.iso_last_query_stats.argtypes = [C.c_void_p, C.POINTER(QueryStats)]
     L.iso_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
@@ -303,6 +307,33 @@ class Graph:
             raise e
         _check(st)
         return total.value
+
+    def query_vertices(self, source: int, tau: int, mode: int = MODE_PLAIN) -> np.ndarray:
+        """Vertices with d(source, v) <= tau, sorted original ids (uint32)."""
+        ptr = _U32P()
+        cnt = C.c_size_t()
+        _check(lib().iso_query_vertices(self._h, int(source), int(tau), int(mode), C.byref(ptr), C.byref(cnt)))
+        try:
+            n = cnt.value
+            return np.ctypeslib.as_array(ptr, shape=(n,)).copy() if n else np.zeros(0, dtype=np.uint32)
+        finally:
+            lib().iso_free(ptr)
+
+    def query_batch_vertices_device(self, sources, taus, mode, bits, stream=None):
+        """Vertices in range of k <= 64 queries as bitmaps in `bits`, a contiguous 64-bit torch
+        tensor of shape (k, ceil(n / 64)) on the graph's device: bit v % 64 of bits[j, v // 64]
+        is set iff vertex v is in range of query j."""
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(bits.device).cuda_stream
+        s, sp = _u32(sources)
+        t, tp = _u32(taus)
+        k, W = s.size, (self.n + 63) // 64
+        if bits.element_size() != 8 or not bits.is_contiguous() or bits.device.type != "cuda" or \
+                bits.numel() < k * W:
+            raise IsoError(ISO_EINVAL, f"bits must be a contiguous 64-bit device tensor of {k} x {W} words")
+        _check(lib().iso_query_batch_vertices_device(self._h, k, sp, tp, int(mode), C.c_void_p(bits.data_ptr()),
+                                                     C.c_void_p(stream)))
 
     def distances(self, source: int, tau: int, mode: int = MODE_PLAIN):
         """(dist uint32[n] with 2^32-1 where not labelled, swept bool[n])."""

@@ -216,6 +216,7 @@ struct iso_graph {
     std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> up_out;   // one search result buffer per worker
     size_t out_cap = 1 << 20;
+    uint64_t *vbits_dev = nullptr;   // device bitmap of iso_query_vertices (ceil(n / 64) words)
 };
 
 

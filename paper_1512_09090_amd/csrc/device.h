@@ -36,6 +36,9 @@ struct RunArgs {
     size_t out_cap = 0;          // capacity of the edge-key buffer
     uint32_t table_x = 0;        // top table used: core positions [0, table_x), the first table_levels levels
     uint32_t table_levels = 0;
+    // vertices in range instead of edges (vbits set): per lane j < lanes, row j of ceil(n / 64)
+    // words of vbits gets bit v % 64 of word v / 64 for every original id v in range; no edges
+    uint64_t *vbits = nullptr;
     std::vector<uint32_t> taus;      // k_pow2 (padding lanes: INF)
     std::vector<uint32_t> src_cell;  // k_pow2 (padding lanes: NO_CELL)
     // upward-search labels per lane: positions and labels inside the top table X
@@ -72,11 +75,12 @@ struct QueryBufs {
              *d_src_cell = nullptr, *d_flags = nullptr, *d_list = nullptr, *d_counters = nullptr,
              *d_dist = nullptr;
     uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
+    uint64_t *d_vmask = nullptr, *d_cin = nullptr;   // vertex output: lanes in range per position; per cell
     uint32_t *d_lane_off = nullptr;   // MAX_LANES + 1 lane starts of the decoded edges
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
     size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
            sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0,
-           sz_lane_off = 0;
+           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0;
     void release();
 };
 
@@ -111,7 +115,7 @@ struct SweepCtx {
     bool pending = false;
     uint32_t K = 1, lk = 0, lg = 0, lanes = 0, lane_base = 0, nlev = 0, top = 0;
     size_t cap = 0;
-    bool mode_plain = true, want_dist = false;
+    bool mode_plain = true, want_dist = false, vertex_mode = false;
     uint32_t *h_counters = nullptr;   // pinned: keys produced, active cells
     int create(int device);
     void release();
@@ -127,6 +131,7 @@ struct DevGraph {
     uint32_t *d_down_off = nullptr;
     uint2 *d_down_arc = nullptr;
     uint32_t *d_perm = nullptr, *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
+    uint32_t *d_pos = nullptr;   // original id -> position (vertex output)
     // top-of-hierarchy table: X = core positions [0, TX) covering the first nlev_table levels;
     // d_table[y * TX + x] = shortest downward path y -> x inside X
     uint32_t TX = 0, nlev_table = 0;

@@ -330,6 +330,10 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
 
 void iso_free_graph(iso_graph *g) {
     if (!g) return;
+    if (g->vbits_dev) {
+        hipSetDevice(g->D.device);
+        hipFree(g->vbits_dev);
+    }
     g->D.release();
     delete g;
 }
@@ -605,6 +609,84 @@ int iso_query_batch_device(iso_graph *g, size_t k, const uint32_t *sources, cons
     }
     *total = dev.total;
     return r;
+}
+
+// One sweep of k <= 64 queries whose output is the vertices in range: bitmap rows of
+// ceil(n / 64) words per query at `bits` (device).  With `caller` set, its queued work is
+// waited for first.
+static int vertices_sweep(iso_graph *g, size_t k, const uint32_t *src, const uint32_t *tau, int mode,
+                          uint64_t *bits, bool wait, hipStream_t caller) {
+    const double t0 = now_ms();
+    g->last = iso_query_stats{};
+    isodev::RunArgs A;
+    std::vector<uint32_t> settled(k, 0);
+    build_run_args(g, src, tau, uint32_t(k), mode == ISO_MODE_PLAIN, false, A, settled.data());
+    A.out_cap = g->out_cap;
+    A.vbits = bits;
+    const double t1 = now_ms();
+    if (wait) {
+        int r = wait_for_caller(g->D, caller, false);
+        if (r) return r;
+    }
+    isodev::RunResult R;
+    int r = g->D.run(g->D.main, A, R);
+    if (r) return r;
+    g->last.lanes = uint32_t(k);
+    g->last.active_cells = R.active_cells;
+    for (uint32_t x : settled) g->last.upward_settled += x;
+    g->last.t_upward_ms = t1 - t0;
+    g->last.t_device_ms = now_ms() - t1;
+    g->last.t_total_ms = now_ms() - t0;
+    return ISO_OK;
+}
+
+int iso_query_batch_vertices_device(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus,
+                                    int mode, uint64_t *bits, void *stream) {
+    if (!bits || !sources || !taus) return fail(ISO_EINVAL, "NULL argument");
+    if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    if (k < 1 || k > isodev::MAX_LANES) return fail(ISO_EINVAL, "k must be in [1, 64]");
+    for (size_t j = 0; j < k; ++j) {
+        int r = check_query(g, sources[j], taus[j], mode);
+        if (r) return r;
+    }
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    const size_t W = (size_t(g->P.n) + 63) / 64;
+    if (!device_range_ok(bits, k * W * sizeof(uint64_t), g->D.device))
+        return fail(ISO_EINVAL, "bits is not k * ceil(n / 64) words of device memory on the graph's device");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    return vertices_sweep(g, k, sources, taus, mode, bits, true, (hipStream_t)stream);
+}
+
+int iso_query_vertices(iso_graph *g, uint32_t source, uint32_t tau, int mode, uint32_t **vertices, size_t *count) {
+    if (vertices) *vertices = nullptr;
+    if (!vertices || !count) return fail(ISO_EINVAL, "NULL output pointer");
+    int r = check_query(g, source, tau, mode);
+    if (r) return r;
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    const size_t W = (size_t(g->P.n) + 63) / 64;
+    if (!g->vbits_dev && hipMalloc((void **)&g->vbits_dev, W * sizeof(uint64_t)) != hipSuccess) {
+        g->vbits_dev = nullptr;
+        return fail(ISO_ENOMEM, "device allocation of the vertex bitmap failed");
+    }
+    if ((r = vertices_sweep(g, 1, &source, &tau, mode, g->vbits_dev, false, nullptr))) return r;
+    std::vector<uint64_t> h(W);
+    if (hipMemcpy(h.data(), g->vbits_dev, W * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(ISO_EDEVICE, "copying the vertex bitmap failed");
+    size_t cnt = 0;
+    for (uint64_t w : h) cnt += size_t(__builtin_popcountll(w));
+    uint32_t *out = (uint32_t *)std::malloc(std::max<size_t>(1, cnt) * sizeof(uint32_t));
+    if (!out) return fail(ISO_ENOMEM, "out of host memory for the result");
+    size_t k = 0;
+    for (size_t i = 0; i < W; ++i)
+        for (uint64_t w = h[i]; w; w &= w - 1) out[k++] = uint32_t(i * 64 + size_t(__builtin_ctzll(w)));
+    *vertices = out;
+    *count = cnt;
+    return ISO_OK;
 }
 
 int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode, uint32_t *dist,

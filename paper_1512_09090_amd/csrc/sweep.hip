@@ -383,12 +383,12 @@ __global__ void k_cell_masks(const uint32_t *__restrict__ cell_core_off, const u
                              const uint64_t *__restrict__ vin, const uint64_t *__restrict__ vout,
                              const uint8_t *__restrict__ uncovered, const uint32_t *__restrict__ cell_off,
                              const uint32_t *__restrict__ src_cell, uint32_t k, uint32_t num_cells,
-                             uint32_t all_cells, uint64_t *__restrict__ cmask) {
+                             uint32_t all_cells, uint64_t *__restrict__ cmask, uint64_t *__restrict__ cin) {
     const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = __lane_id();
     if (c >= num_cells) return;   // uniform over the wavefront
     const uint32_t sc = lane < k ? src_cell[lane] : NO_CELL;
     const uint64_t real = __ballot(sc != NO_CELL), src = __ballot(sc == c);
-    uint64_t m = 0;
+    uint64_t m = 0, some_in = 0;
     if (cell_off[c + 1] > cell_off[c]) {
         if (all_cells) {
             m = real;
@@ -404,9 +404,60 @@ __global__ void k_cell_masks(const uint32_t *__restrict__ cell_core_off, const u
                 out |= (uint64_t)__shfl_xor((unsigned long long)out, (int)o);
             }
             m = ((in & (uncovered[c] ? real : out)) | src) & real;
+            some_in = in & real;
         }
     }
-    if (lane == 0) cmask[c] = m;
+    if (lane == 0) {
+        cmask[c] = m;
+        if (cin) cin[c] = some_in;
+    }
+}
+
+// Vertices in range, the alternative output of Section 3, as a 64-bit lane mask per position
+// (bit j: d_j <= tau_j).  Core positions from their final labels (one ballot per group of K
+// lanes; the loop count is the same for every lane of a wavefront).
+__global__ void k_vmask_core(const uint32_t *__restrict__ dcore, const uint32_t *__restrict__ taus,
+                             uint32_t n_core, uint32_t lk, uint64_t *__restrict__ vmask) {
+    const uint32_t K = 1u << lk;
+    const uint64_t total = ((uint64_t(n_core) << lk) + 63u) & ~uint64_t(63);
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint32_t v = uint32_t(t >> lk), j = uint32_t(t) & (K - 1);
+        const bool act = v < n_core;
+        const uint64_t b = __ballot(act && dcore[(uint64_t(v) << lk) + j] <= taus[j]);
+        if (act && j == 0) {
+            const uint32_t sh = __lane_id() & ~(K - 1);
+            vmask[v] = lk == 6 ? b : ((b >> sh) & ((1ull << K) - 1ull));
+        }
+    }
+}
+
+// Internal positions of every cell: the lanes for which the cell is not swept but some core
+// vertex of it is in range.  For those the flag rule left o unset and the cell is covered, so
+// every core vertex u has d(u) + ecc(u) <= tau and every internal vertex, reached inside the
+// cell from some u, is in range.  (A cell with no core vertex in range has no internal vertex
+// in range unless it is swept.)  The swept lanes are ORed in by the cell sweep.
+__global__ void k_vmask_cells(const uint64_t *__restrict__ cin, const uint64_t *__restrict__ cmask,
+                              const uint32_t *__restrict__ cell_off, uint32_t num_cells,
+                              uint64_t *__restrict__ vmask) {
+    const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = __lane_id();
+    if (c >= num_cells) return;
+    const uint64_t full = cin[c] & ~cmask[c];
+    for (uint32_t p = cell_off[c] + lane; p < cell_off[c + 1]; p += 64) vmask[p] = full;
+}
+
+// Lane masks by position -> one bitmap row of W words per lane over the original ids: each
+// wavefront takes 64 consecutive ids, i.e. one word of every row (one ballot per lane).
+__global__ void k_vmask_out(const uint64_t *__restrict__ vmask, const uint32_t *__restrict__ pos, uint32_t n,
+                            uint32_t W, uint32_t lanes, uint64_t *__restrict__ bits) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x, word = v >> 6, lane = __lane_id();
+    const uint64_t w = v < n ? vmask[pos[v]] : 0ull;
+    uint64_t mine = 0;
+    for (uint32_t j = 0; j < lanes; ++j) {
+        const uint64_t b = __ballot((w >> j) & 1ull);
+        if (lane == j) mine = b;
+    }
+    if (lane < lanes && word < W) bits[uint64_t(lane) * W + word] = mine;
 }
 
 // Active cells (nonzero lane mask) in a list, and work items: the lanes of a cell are cut into
@@ -473,6 +524,7 @@ struct CellArgs {
     const uint64_t *cmask;
     const uint4 *cmeta;
     uint32_t *dist_out;
+    uint64_t *vmask;   // vertex output: lane masks by position (nullptr: edges only)
     uint64_t *out_keys;
     uint32_t *out_count;
     uint32_t out_cap, lane_base, lk, lg, num_cells, ib;
@@ -528,6 +580,17 @@ __device__ __forceinline__ void relax_cell_vertex(uint32_t e0, uint32_t e1, uint
             if (e + u < e1) bits.see(e + u - e0, x[u].x, lt[u] <= tau);
         }
     }
+}
+
+// Vertex output: the lanes of an item for which internal vertex p is in range (its label dv
+// final), ORed over the G lane slots of the vertex (consecutive threads) into p's lane mask
+// with one atomic per vertex (items of one cell hold different lanes).  Every thread of the
+// wavefront must call it.
+__device__ __forceinline__ void or_in_range(uint64_t *vmask, bool act, bool live, uint32_t p, uint32_t dv,
+                                            uint32_t tau, uint32_t jj, uint32_t j, uint32_t lg) {
+    uint64_t in = act && live && dv <= tau ? (1ull << jj) : 0ull;
+    for (uint32_t o = 1; o < (1u << lg); o <<= 1) in |= (uint64_t)__shfl_xor((unsigned long long)in, (int)o);
+    if (act && j == 0 && in) atomicOr((unsigned long long *)&vmask[p], (unsigned long long)in);
 }
 
 constexpr uint32_t CELL_BUF = 512;         // entries per LDS level buffer (two buffers)
@@ -798,6 +861,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
                 s_lab[(i << lg) + j] = dv;
                 if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
             }
+            if (A.vmask) or_in_range(A.vmask, act, live, cb + i, dv, tau, jj, j, lg);
             // isochrone edges at vertex i (its tails are on earlier levels or in the core) go to
             // the candidate list
             emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
@@ -918,6 +982,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
             s_lab[(i << lg) + j] = dv;
             if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
         }
+        if (A.vmask) or_in_range(A.vmask, act, live, cb + i, dv, tau, jj, j, lg);
         emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent, ref,
                          cb, lanes, q);
     };
@@ -1039,6 +1104,7 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy((uint32_t **)&d_down_arc, P.down_arc.data(), 2 * size_t(P.down_off[n_core]), bytes)))
         return r;
     if ((r = dev_alloc_copy(&d_perm, P.perm, bytes))) return r;
+    if ((r = dev_alloc_copy(&d_pos, P.pos, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_cell, P.core_cell, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_ecc, P.core_ecc, bytes))) return r;
     // table of downward distances inside the top levels X = [0, TX), TX <= TABLE_MAX
@@ -1237,7 +1303,7 @@ void DevGraph::release() {
     if (aux_ready) aux.release();
     aux_ready = false;
     hipSetDevice(device);
-    void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
+    void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
                     d_table, d_blob, d_cblob, d_cmeta};
     for (void *p : ptrs) if (p) hipFree(p);
@@ -1246,7 +1312,7 @@ void DevGraph::release() {
 
 void QueryBufs::release() {
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
-                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off};
+                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin};
     for (void *p : ptrs) if (p) hipFree(p);
     if (h_pinned) hipHostFree(h_pinned);
     *this = QueryBufs();
@@ -1324,6 +1390,11 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     if ((r = ensure((void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8))) return r;
     if ((r = ensure((void **)&B.d_lane_off, B.sz_lane_off, (MAX_LANES + 1) * 4))) return r;
     if (A.want_dist && (r = ensure((void **)&B.d_dist, B.sz_dist, size_t(n) * K * 4))) return r;
+    const bool vmode = A.vbits != nullptr;
+    if (vmode) {
+        if ((r = ensure((void **)&B.d_vmask, B.sz_vmask, size_t(n) * 8))) return r;
+        if ((r = ensure((void **)&B.d_cin, B.sz_cin, size_t(std::max(1u, num_cells)) * 8))) return r;
+    }
     // per-call host inputs staged in one pinned buffer: counters back, taus, source cells,
     // upward entries
     size_t stage = (16 + 2 * size_t(K) + 3 * size_t(nu) + (K + 1) + 2 * size_t(nx)) * 4;
@@ -1467,15 +1538,22 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         HIPCHK(hipGraphLaunch(C.graph_exec, s));
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
+    if (vmode && n_core > 0)   // vertex output: lane masks of the core positions
+        k_vmask_core<<<dim3(uint32_t(std::min<uint64_t>(65536, ((uint64_t(n_core) << lk) + 255) / 256))), dim3(256),
+                       0, s>>>(B.d_dcore, d_taus, n_core, lk, B.d_vmask);
     if (num_cells > 0) {
         k_cell_masks<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(d_cell_core_off, d_cell_core, vin, vout,
                                                                       d_uncovered, d_cell_off, d_src, K, num_cells,
-                                                                      A.mode_plain ? 1u : 0u, d_cmask);
+                                                                      A.mode_plain ? 1u : 0u, d_cmask,
+                                                                      vmode ? B.d_cin : nullptr);
         k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(d_cmask, num_cells, cell_lg, d_clist,
                                                                           d_items, B.d_counters);
+        if (vmode)   // internal positions: the cells left out because they lie wholly in range
+            k_vmask_cells<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(B.d_cin, d_cmask, d_cell_off, num_cells,
+                                                                           B.d_vmask);
         CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
-                    d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, B.d_keys, out_count,
-                    uint32_t(cap), A.lane_base, lk, lg, num_cells, id_bits};
+                    d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, vmode ? B.d_vmask : nullptr,
+                    B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg, num_cells, id_bits};
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
         if (staged)
             k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
@@ -1485,6 +1563,10 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         HIPCHK(hipEventRecord(C.prof.ev[2], s));
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[3], s));
+    if (vmode) {   // lane masks by position -> one bitmap row per lane over the original ids
+        const uint32_t W = (n + 63) / 64;
+        k_vmask_out<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(B.d_vmask, d_pos, n, W, A.lanes, A.vbits);
+    }
     HIPCHK(hipGetLastError());
     if (nu) k_uset_clear<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
     HIPCHK(hipMemcpyAsync(C.h_counters, B.d_counters, 16, hipMemcpyDeviceToHost, s));
@@ -1498,6 +1580,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     C.cap = cap;
     C.mode_plain = A.mode_plain;
     C.want_dist = A.want_dist;
+    C.vertex_mode = vmode;
     C.nlev = uint32_t(nlev);
     C.top = uint32_t(top);
     return 0;
@@ -1580,6 +1663,11 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
                 prof.cell_bytes += 4ull * cell_words[c] + lanes * 4ull * cell_core_refs[c];
             }
         }
+    }
+    if (C.vertex_mode) {   // the vertex bitmaps are written; the edge keys are not used
+        R.overflow = false;
+        R.count = 0;
+        return 0;
     }
     if (R.overflow) return 0;   // caller grows the buffer and launches again
     const auto tr0 = std::chrono::steady_clock::now();
