@@ -184,12 +184,18 @@ def test_road1m_config():
 @pytest.mark.slow
 @pytest.mark.timeout(1500)
 def test_road18m_benchmark_batch_sampled():
-    """The benchmark's workload at full size in the benchmark's launch configuration: one batch
-    of its first 64 queries (cells mode, default tuning); sampled lanes equal the oracle exactly,
-    two lanes equal single queries in both modes, every lane's output is sorted, unique and in
-    range."""
+    """The benchmark's workload at full size in the benchmark's launch configuration: the first
+    128 of its queries through iso_query_batch_device (two 64-query sweeps overlapping on two
+    streams, default tuning, edges left in device memory); sampled lanes of both sweeps equal the
+    oracle exactly, two lanes equal single queries in both modes, every lane's output is sorted,
+    unique and in range.  Then the vertex output of the first 64 queries: sampled lanes equal the
+    oracle's vertices in range, and for every lane each isochrone edge has exactly one endpoint
+    in the set."""
     import os
 
+    import torch
+
+    torch.cuda.init()
     name = "road18m"
     cfg = synth.CONFIGS[name]
     g = synth.config_graph(name)
@@ -198,22 +204,43 @@ def test_road18m_benchmark_batch_sampled():
     os.makedirs(cache, exist_ok=True)
     G = iso.Graph.from_synth(g, num_cells=cfg["cells"], device=0,
                              prep_path=os.path.join(cache, f"{name}-c{cfg['cells']}-v1.prep"), verbose=True)
-    src, tau = synth.config_queries(name, 64)
-    out = G.query_batch(src, tau, iso.MODE_CELLS)
-    say(f"batch done: {sum(len(o) for o in out)} edges")
+    src, tau = synth.config_queries(name, 128)
+    pairs = torch.empty((128 * 60_000, 2), dtype=torch.int32, device="cuda:0")
+    offsets = torch.empty(129, dtype=torch.int32, device="cuda:0")
+    total = G.query_batch_device(src, tau, iso.MODE_CELLS, pairs, offsets)
+    flat = pairs[:total].cpu().numpy().view(np.uint32)
+    off = offsets.cpu().numpy().view(np.uint32).astype(np.int64)
+    out = [flat[off[j]:off[j + 1]] for j in range(128)]
+    say(f"batch done: {total} edges")
     for j, e in enumerate(out):
         assert e.shape[1] == 2 and (e < g.n).all()
         if len(e) > 1:
             key = e[:, 0].astype(np.uint64) << np.uint64(32) | e[:, 1].astype(np.uint64)
             assert (np.diff(key) > 0).all(), f"lane {j} not sorted and unique"
-    for j in (0, 63):
+    for j in (0, 64):
         for mode in (iso.MODE_CELLS, iso.MODE_PLAIN):
             np.testing.assert_array_equal(G.query(int(src[j]), int(tau[j]), mode), out[j], err_msg=f"lane {j}")
     orc = Oracle.from_graph(g)
-    for j in (0, 21, 42, 63):
+    for j in (0, 63, 64, 127):
         say(f"oracle lane {j} (tau {int(tau[j])} ms)")
         want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
         np.testing.assert_array_equal(out[j], want, err_msg=f"lane {j}")
+    # vertices in range
+    W = (g.n + 63) // 64
+    bits = torch.full((64, W), -1, dtype=torch.int64, device="cuda:0")
+    G.query_batch_vertices_device(src[:64], tau[:64], iso.MODE_CELLS, bits)
+    b = bits.cpu().numpy().view(np.uint64)
+    del bits
+    for j in (0, 63):
+        say(f"oracle vertices lane {j}")
+        got = np.flatnonzero(np.unpackbits(b[j].view(np.uint8), bitorder="little")[:g.n]).astype(np.uint32)
+        np.testing.assert_array_equal(got, orc.in_range(int(src[j]), int(tau[j])), err_msg=f"vertices lane {j}")
+    for j in range(64):
+        e = out[j].astype(np.int64)
+        if len(e) == 0:
+            continue
+        inr = lambda v: (b[j][v >> 6] >> (v & 63).astype(np.uint64)) & np.uint64(1)  # noqa: E731
+        assert np.all(inr(e[:, 0]) != inr(e[:, 1])), f"lane {j}: an edge without exactly one endpoint in range"
 
 
 def _identical_across_tuning(road50k, combos):
