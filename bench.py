@@ -432,6 +432,32 @@ def main():
     in_range = int(np.bitwise_count(vbits.cpu().numpy().view(np.uint64)).sum())
     log(f"vertices in range (device bitmaps): {qps_vert:.1f} queries/s; last batch {in_range} (vertex, query) pairs")
 
+    # one-to-many (RPHAST, the paper's Table 1 workload): a ball of 2^14 targets, sources drawn
+    # from the ball, distances left in HBM (one call per batch of `lanes` sources)
+    _, ball = synth.target_ball(g, 1 << 14, seed=16)
+    tg = G.select_targets(ball)
+    tinfo = tg.info()
+    rng = np.random.default_rng(17)
+    tsrc = ball[rng.integers(0, ball.size, size=max(2, args.steps // 4) * lanes)]
+    tdist = torch.empty((lanes, ball.size), dtype=torch.int32, device="cuda:0")
+    tg.query_device(tsrc[:lanes], tdist)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(0, tsrc.size, lanes):
+        tg.query_device(tsrc[b:b + lanes], tdist)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    one_to_many = {"targets": int(ball.size), "select_ms": round(tinfo["select_ms"], 3),
+                   "restricted_vertices": tinfo["vertices"], "restricted_arcs": tinfo["arcs"],
+                   "level_groups": tinfo["groups"], "sources_per_call": lanes,
+                   "value": round(tsrc.size / el, 2), "unit": "sources/s",
+                   "ms_per_call": round(1000 * el / (tsrc.size // lanes), 4),
+                   "note": "iso_targets_query_device: d(s, t) for every target of a 2^14 ball (breadth-first "
+                           "from a random centre), sources from the ball; paper's Table 1 context (one core): "
+                           "selection 1.29 ms, 0.16 ms per source"}
+    tg.close()
+    log(f"one-to-many: {one_to_many}")
+
     # single-query latency (one query per call)
     lat = {}
     single_qps = {}
@@ -516,6 +542,7 @@ def main():
                               "bitmap_bytes_per_call": lanes * W * 8, "in_range_pairs_last_call": in_range,
                               "note": "iso_query_batch_vertices_device: the vertices in range of each query "
                                       "as a bitmap over the original ids, left in HBM"},
+        "one_to_many": one_to_many,
         "queries_per_sweep_qps": sweep,
         "timed_call": dict(batch_stats, edges_in_hbm=int(edges_total)),
         "serving": serve,

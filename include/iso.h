@@ -190,6 +190,35 @@ int iso_query_vertices(iso_graph *g, uint32_t source, uint32_t tau, int mode,
                        uint32_t **vertices, size_t *count);
 
 /*
+ * One-to-many distances on the same hierarchy: RPHAST (Section 2), the
+ * restricted PHAST the paper times in Table 1.  iso_targets_select runs the
+ * target selection once: a search from the targets against the direction of
+ * the downward arcs collects every vertex with a downward path to a target
+ * (the restricted downward graph), which is uploaded grouped by level.  Each
+ * query then runs the upward search and sweeps only those vertices (the top
+ * table's vertices through the table product).  The selection depends on the
+ * tuning's table_max at selection time; a later query with another table
+ * prefix fails with ISO_ESTATE.  A target set must be freed before its graph.
+ *
+ * iso_targets_query: k >= 1 sources, dist (caller host memory, k * count
+ * words) receives d(sources[j], targets[i]) at dist[j * count + i], ISO_INF
+ * where a target is unreachable.  iso_targets_query_device: the same into
+ * caller-owned device memory (checked to lie inside one device allocation),
+ * waiting for the caller's stream first; it returns after the writes.
+ */
+typedef struct iso_targets iso_targets;
+int iso_targets_select(iso_graph *g, const uint32_t *targets, size_t count, iso_targets **out);
+int iso_targets_query(iso_graph *g, const iso_targets *t, size_t k, const uint32_t *sources,
+                      uint32_t *dist);
+int iso_targets_query_device(iso_graph *g, const iso_targets *t, size_t k, const uint32_t *sources,
+                             uint32_t *dist, void *stream);
+/* Size of the restricted graph: vertices below the top table, their entries, level groups, and
+ * the host time of the selection (search, layout and upload) in ms. */
+int iso_targets_get_info(const iso_targets *t, uint64_t *vertices, uint64_t *arcs, uint32_t *groups,
+                         double *select_ms);
+void iso_targets_free(iso_targets *t);
+
+/*
  * Distance labels of one query (test hook).  dist (n entries, caller host
  * memory) receives min(d(s, v), ISO_INF) for every vertex the sweep labelled
  * (all vertices in ISO_MODE_PLAIN; core vertices and the vertices of active

@@ -133,6 +133,13 @@ def lib():
                                                   C.c_void_p]
     L.iso_query_vertices.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.POINTER(_U32P),
                                      C.POINTER(C.c_size_t)]
+    L.iso_targets_select.argtypes = [C.c_void_p, _U32P, C.c_size_t, C.POINTER(C.c_void_p)]
+    L.iso_targets_query.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, _U32P, _U32P]
+    L.iso_targets_query_device.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, _U32P, C.c_void_p, C.c_void_p]
+    L.iso_targets_get_info.argtypes = [C.c_void_p, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                       C.POINTER(C.c_uint32), C.POINTER(C.c_double)]
+    L.iso_targets_free.argtypes = [C.c_void_p]
+    L.iso_targets_free.restype = None
     L.iso_query_distances.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, _U32P, C.POINTER(C.c_uint8)]
     L.iso_last_query_stats.argtypes = [C.c_void_p, C.POINTER(QueryStats)]
     L.iso_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
@@ -335,6 +342,10 @@ class Graph:
         _check(lib().iso_query_batch_vertices_device(self._h, k, sp, tp, int(mode), C.c_void_p(bits.data_ptr()),
                                                      C.c_void_p(stream)))
 
+    def select_targets(self, targets) -> "Targets":
+        """RPHAST target selection for a one-to-many target set (original ids)."""
+        return Targets(self, targets)
+
     def distances(self, source: int, tau: int, mode: int = MODE_PLAIN):
         """(dist uint32[n] with 2^32-1 where not labelled, swept bool[n])."""
         dist = np.empty(self.n, dtype=np.uint32)
@@ -365,6 +376,50 @@ class Graph:
         t = Tuning()
         _check(lib().iso_get_tuning(self._h, C.byref(t)))
         return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+
+class Targets:
+    """A selected target set (iso_targets): distances from any sources to its targets."""
+
+    def __init__(self, graph: "Graph", targets):
+        t, tp = _u32(targets)
+        self.graph, self.count, self._h = graph, int(t.size), C.c_void_p()
+        _check(lib().iso_targets_select(graph._h, tp, t.size, C.byref(self._h)))
+
+    def info(self) -> dict:
+        v, a, g, ms = C.c_uint64(), C.c_uint64(), C.c_uint32(), C.c_double()
+        _check(lib().iso_targets_get_info(self._h, C.byref(v), C.byref(a), C.byref(g), C.byref(ms)))
+        return {"vertices": v.value, "arcs": a.value, "groups": g.value, "select_ms": ms.value}
+
+    def query(self, sources) -> np.ndarray:
+        """(k, count) uint32: d(sources[j], targets[i]), 2^32-1 where unreachable."""
+        s, sp = _u32(sources)
+        out = np.empty((s.size, self.count), dtype=np.uint32)
+        _check(lib().iso_targets_query(self.graph._h, self._h, s.size, sp, out.ctypes.data_as(_U32P)))
+        return out
+
+    def query_device(self, sources, dist, stream=None):
+        """The same into `dist`, a contiguous 32-bit torch tensor of k * count entries on the device."""
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(dist.device).cuda_stream
+        s, sp = _u32(sources)
+        if dist.element_size() != 4 or not dist.is_contiguous() or dist.device.type != "cuda" or \
+                dist.numel() < s.size * self.count:
+            raise IsoError(ISO_EINVAL, f"dist must be a contiguous 32-bit device tensor of {s.size * self.count} entries")
+        _check(lib().iso_targets_query_device(self.graph._h, self._h, s.size, sp, C.c_void_p(dist.data_ptr()),
+                                              C.c_void_p(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().iso_targets_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

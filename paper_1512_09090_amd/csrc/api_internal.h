@@ -217,6 +217,14 @@ struct iso_graph {
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> up_out;   // one search result buffer per worker
     size_t out_cap = 1 << 20;
     uint64_t *vbits_dev = nullptr;   // device bitmap of iso_query_vertices (ceil(n / 64) words)
+    uint32_t *tdist_dev = nullptr;   // device distances of iso_targets_query
+    size_t tdist_cap = 0;            // its capacity in words
+};
+
+struct iso_targets {
+    iso_graph *g = nullptr;
+    isodev::TargetSet T;
+    double select_ms = 0;
 };
 
 

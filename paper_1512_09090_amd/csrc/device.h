@@ -22,6 +22,8 @@ constexpr uint32_t TABLE_DEFAULT = 4096;        // vertices of the levels merged
 constexpr uint32_t MAX_LANES = 64;
 constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a 6-bit lane chunk
 
+struct TargetSet;
+
 struct RunArgs {
     uint32_t lanes = 1;          // real queries in this launch (<= k_pow2)
     uint32_t k_pow2 = 1;         // label row width (power of two >= lanes)
@@ -39,6 +41,10 @@ struct RunArgs {
     // vertices in range instead of edges (vbits set): per lane j < lanes, row j of ceil(n / 64)
     // words of vbits gets bit v % 64 of word v / 64 for every original id v in range; no edges
     uint64_t *vbits = nullptr;
+    // one-to-many instead (tg set): distances from each lane's source to the target set's
+    // targets, row j of tg_out (tg->count words) for lane j < lanes; no cells, no edges
+    const TargetSet *tg = nullptr;
+    uint32_t *tg_out = nullptr;
     std::vector<uint32_t> taus;      // k_pow2 (padding lanes: INF)
     std::vector<uint32_t> src_cell;  // k_pow2 (padding lanes: NO_CELL)
     // upward-search labels per lane: positions and labels inside the top table X
@@ -66,6 +72,25 @@ struct RunResult {
     std::vector<uint32_t> dcore, dist, active_list;   // only with want_dist
 };
 
+// A target set's restricted downward graph (RPHAST) on the device.  Rows of the label array:
+// [0, tx) the top-table vertices (rows = positions), then the restricted vertices below the
+// table, grouped by level (core levels top first, then the cells' local levels top first, every
+// cell's level l in one group) so that no entry joins two rows of one group.
+struct TargetSet {
+    int device = -1;
+    uint32_t count = 0;                  // targets
+    uint32_t tx = 0, table_levels = 0;   // top-table prefix the restriction was built for
+    uint32_t nr = 0;                     // restricted vertices below the table
+    uint64_t arcs = 0;                   // their entries (finite lengths only)
+    std::vector<uint32_t> group;         // group bounds in rows, from tx to tx + nr
+    uint32_t *d_off = nullptr;           // nr + 1: entries of row tx + i
+    uint2 *d_arc = nullptr;              // (row of the tail, length)
+    uint32_t *d_rpos = nullptr;          // nr: position of row tx + i
+    uint32_t *d_row = nullptr;           // count: row of each target
+    uint64_t bytes = 0;
+    void release();
+};
+
 struct QueryBufs {
     uint32_t *d_xin = nullptr;   // per-lane upward labels inside the table: ptr (k+1), pos, val
     size_t sz_xin = 0;
@@ -76,11 +101,12 @@ struct QueryBufs {
              *d_dist = nullptr;
     uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
     uint64_t *d_vmask = nullptr, *d_cin = nullptr;   // vertex output: lanes in range per position; per cell
+    uint32_t *d_rlab = nullptr;                        // one-to-many: labels of a target set's rows
     uint32_t *d_lane_off = nullptr;   // MAX_LANES + 1 lane starts of the decoded edges
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
     size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
            sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0,
-           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0;
+           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0, sz_rlab = 0;
     void release();
 };
 
@@ -115,7 +141,7 @@ struct SweepCtx {
     bool pending = false;
     uint32_t K = 1, lk = 0, lg = 0, lanes = 0, lane_base = 0, nlev = 0, top = 0;
     size_t cap = 0;
-    bool mode_plain = true, want_dist = false, vertex_mode = false;
+    bool mode_plain = true, want_dist = false, vertex_mode = false, one_to_many = false;
     uint32_t *h_counters = nullptr;   // pinned: keys produced, active cells
     int create(int device);
     void release();
@@ -173,6 +199,10 @@ struct DevGraph {
     int launch(SweepCtx &C, const RunArgs &A);
     int finish(SweepCtx &C, RunResult &R);
     int sort_keys(SweepCtx &C, uint32_t cnt_all);
+    // RPHAST target selection: the restricted graph of the targets (original ids) for the top
+    // table prefix [0, tx) of table_levels levels, uploaded to the device.
+    int select_targets(const iso::Prep &P, const uint32_t *targets, uint32_t count, uint32_t tx,
+                       uint32_t table_levels, TargetSet &T);
     int run(SweepCtx &C, const RunArgs &A, RunResult &R);
     // device bytes a context needs for k lanes and an edge capacity (admission control)
     size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const;

@@ -330,9 +330,10 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
 
 void iso_free_graph(iso_graph *g) {
     if (!g) return;
-    if (g->vbits_dev) {
+    if (g->vbits_dev || g->tdist_dev) {
         hipSetDevice(g->D.device);
-        hipFree(g->vbits_dev);
+        if (g->vbits_dev) hipFree(g->vbits_dev);
+        if (g->tdist_dev) hipFree(g->tdist_dev);
     }
     g->D.release();
     delete g;
@@ -687,6 +688,130 @@ int iso_query_vertices(iso_graph *g, uint32_t source, uint32_t tau, int mode, ui
     *vertices = out;
     *count = cnt;
     return ISO_OK;
+}
+
+int iso_targets_select(iso_graph *g, const uint32_t *targets, size_t count, iso_targets **out) {
+    if (out) *out = nullptr;
+    if (!g || !out || (count && !targets)) return fail(ISO_EINVAL, "NULL argument");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    if (count >= (size_t(1) << 31)) return fail(ISO_EINVAL, "too many targets");
+    for (size_t i = 0; i < count; ++i)
+        if (targets[i] >= g->P.n) return fail(ISO_EINVAL, "target out of range");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    const double t0 = now_ms();
+    std::unique_ptr<iso_targets> t(new iso_targets());
+    t->g = g;
+    uint32_t tx = 0, levels = 0;
+    g->D.table_cut(g->tuning.table_max, tx, levels);
+    int r = 0;
+    try {
+        r = g->D.select_targets(g->P, targets, uint32_t(count), tx, levels, t->T);
+    } catch (const std::bad_alloc &) {
+        r = ISO_ENOMEM;
+    }
+    if (r) {
+        t->T.release();
+        return r == ISO_ENOMEM ? fail(ISO_ENOMEM, "out of memory selecting the targets") : r;
+    }
+    t->select_ms = now_ms() - t0;
+    *out = t.release();
+    return ISO_OK;
+}
+
+// Sweeps of up to lanes_per_launch sources against a target set, distances into `dist`
+// (device, k * count words).
+static int targets_sweeps(iso_graph *g, const iso_targets *t, size_t k, const uint32_t *src, uint32_t *dist) {
+    const double t0 = now_ms();
+    g->last = iso_query_stats{};
+    const size_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
+    std::vector<uint32_t> zero(per, 0u), settled(per, 0u);
+    for (size_t b = 0; b < k; b += per) {
+        const uint32_t lanes = uint32_t(std::min(per, k - b));
+        isodev::RunArgs A;
+        const double tu = now_ms();
+        build_run_args(g, src + b, zero.data(), lanes, true, false, A, settled.data());
+        g->last.t_upward_ms += now_ms() - tu;
+        if (A.table_x != t->T.tx)
+            return fail(ISO_ESTATE, "the top table prefix changed since the targets were selected; select again");
+        A.out_cap = g->out_cap;
+        A.tg = &t->T;
+        A.tg_out = dist + b * t->T.count;
+        isodev::RunResult R;
+        int r = g->D.run(g->D.main, A, R);
+        if (r) return r;
+        g->last.lanes += lanes;
+        for (uint32_t j = 0; j < lanes; ++j) g->last.upward_settled += settled[j];
+    }
+    g->last.t_total_ms = now_ms() - t0;
+    g->last.t_device_ms = g->last.t_total_ms - g->last.t_upward_ms;
+    return ISO_OK;
+}
+
+static int targets_check(iso_graph *g, const iso_targets *t, size_t k, const uint32_t *sources) {
+    if (!g || !t || (k && !sources)) return fail(ISO_EINVAL, "NULL argument");
+    if (t->g != g) return fail(ISO_EINVAL, "target set of another graph");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    for (size_t j = 0; j < k; ++j)
+        if (sources[j] >= g->P.n) return fail(ISO_EINVAL, "source out of range");
+    return ISO_OK;
+}
+
+int iso_targets_query_device(iso_graph *g, const iso_targets *t, size_t k, const uint32_t *sources, uint32_t *dist,
+                             void *stream) {
+    int r = targets_check(g, t, k, sources);
+    if (r) return r;
+    const size_t words = k * size_t(t->T.count);
+    if (words == 0) return ISO_OK;
+    if (!dist) return fail(ISO_EINVAL, "NULL argument");
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    if (!device_range_ok(dist, words * sizeof(uint32_t), g->D.device))
+        return fail(ISO_EINVAL, "dist is not k * count words of device memory on the graph's device");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    if ((r = wait_for_caller(g->D, (hipStream_t)stream, false))) return r;
+    return targets_sweeps(g, t, k, sources, dist);
+}
+
+int iso_targets_query(iso_graph *g, const iso_targets *t, size_t k, const uint32_t *sources, uint32_t *dist) {
+    int r = targets_check(g, t, k, sources);
+    if (r) return r;
+    const size_t words = k * size_t(t->T.count);
+    if (words == 0) return ISO_OK;
+    if (!dist) return fail(ISO_EINVAL, "NULL argument");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    if (g->tdist_cap < words) {
+        if (g->tdist_dev) hipFree(g->tdist_dev);
+        g->tdist_dev = nullptr;
+        g->tdist_cap = 0;
+        if (hipMalloc((void **)&g->tdist_dev, words * sizeof(uint32_t)) != hipSuccess) {
+            g->tdist_dev = nullptr;
+            return fail(ISO_ENOMEM, "device allocation of the distances failed");
+        }
+        g->tdist_cap = words;
+    }
+    if ((r = targets_sweeps(g, t, k, sources, g->tdist_dev))) return r;
+    if (hipMemcpy(dist, g->tdist_dev, words * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(ISO_EDEVICE, "copying the distances failed");
+    return ISO_OK;
+}
+
+int iso_targets_get_info(const iso_targets *t, uint64_t *vertices, uint64_t *arcs, uint32_t *groups,
+                         double *select_ms) {
+    if (!t) return fail(ISO_EINVAL, "NULL argument");
+    if (vertices) *vertices = t->T.nr;
+    if (arcs) *arcs = t->T.arcs;
+    if (groups) *groups = t->T.group.empty() ? 0u : uint32_t(t->T.group.size() - 1);
+    if (select_ms) *select_ms = t->select_ms;
+    return ISO_OK;
+}
+
+void iso_targets_free(iso_targets *t) {
+    if (!t) return;
+    t->T.release();
+    delete t;
 }
 
 int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode, uint32_t *dist,

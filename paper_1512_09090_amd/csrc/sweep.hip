@@ -460,6 +460,45 @@ __global__ void k_vmask_out(const uint64_t *__restrict__ vmask, const uint32_t *
     if (lane < lanes && word < W) bits[uint64_t(lane) * W + word] = mine;
 }
 
+// One-to-many (RPHAST): one level group of a target set's restricted downward graph, thread per
+// (row, lane): the row's upward label (slot table, by position) and the minimum over its
+// entries of tail label + length.  Entries are read four at a time (loads issued together).
+__global__ void __launch_bounds__(256) k_rphast_level(const uint32_t *__restrict__ off,
+                                                      const uint2 *__restrict__ arc,
+                                                      const uint32_t *__restrict__ rpos,
+                                                      const uint32_t *__restrict__ uslot,
+                                                      const uint32_t *__restrict__ uval, uint32_t *__restrict__ lab,
+                                                      uint32_t tx, uint32_t rbeg, uint32_t rend, uint32_t lk) {
+    const uint32_t K = 1u << lk;
+    const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t r = rbeg + uint32_t(t >> lk), j = uint32_t(t) & (K - 1);
+    if (r >= rend) return;
+    const uint32_t i = r - tx;
+    const uint32_t s = uslot[rpos[i]];
+    uint32_t d = s != NO_SLOT ? uval[(s << lk) + j] : INF;
+    const uint32_t e1 = off[i + 1];
+    for (uint32_t e = off[i]; e < e1; e += 4) {
+        uint2 a[4];
+        uint32_t l[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) a[u] = arc[min(e + u, e1 - 1)];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) l[u] = lab[(uint64_t(a[u].x) << lk) + j];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) d = min(d, sat_add(l[u], a[u].y));
+    }
+    lab[(uint64_t(r) << lk) + j] = d;
+}
+
+// Distances of the lanes to the targets: out[j * count + i] = label of target i's row.
+__global__ void k_rphast_out(const uint32_t *__restrict__ lab, const uint32_t *__restrict__ row, uint32_t count,
+                             uint32_t lk, uint32_t lanes, uint32_t *__restrict__ out) {
+    const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t j = uint32_t(t / count), i = uint32_t(t % count);
+    if (j >= lanes) return;
+    out[uint64_t(j) * count + i] = lab[(uint64_t(row[i]) << lk) + j];
+}
+
 // Active cells (nonzero lane mask) in a list, and work items: the lanes of a cell are cut into
 // items of at most G = 1 << lg lanes; item c << 6 | q covers the lanes of rank [qG, qG + G) in
 // the mask.  A cell's items are consecutive in the item list.
@@ -1068,6 +1107,93 @@ static int dev_alloc_copy(T **dst, const std::vector<T> &src, uint64_t &bytes) {
     return dev_alloc_copy(dst, src.data(), src.size(), bytes);
 }
 
+void TargetSet::release() {
+    if (device < 0) return;
+    hipSetDevice(device);
+    void *ptrs[] = {d_off, d_arc, d_rpos, d_row};
+    for (void *p : ptrs) if (p) hipFree(p);
+    *this = TargetSet();
+}
+
+// RPHAST target selection: a breadth-first search from the targets against the direction of
+// the downward entries (from a vertex to the tails of its entries) collects every vertex with
+// a downward path to a target; only these need labels.  The search does not continue inside
+// the top table, whose labels all come from the table product.  The collected vertices below
+// the table are grouped by level and laid out as rows after the table's, each with its entries
+// of finite length re-pointed at rows.
+int DevGraph::select_targets(const iso::Prep &P, const uint32_t *targets, uint32_t count, uint32_t tx,
+                             uint32_t table_levels, TargetSet &T) {
+    T = TargetSet();
+    T.device = device;
+    T.count = count;
+    T.tx = tx;
+    T.table_levels = table_levels;
+    std::vector<uint32_t> row(P.n, NO_SLOT);   // position -> row (NO_SLOT: not collected yet)
+    std::vector<uint32_t> found, stack;
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint32_t p = P.pos[targets[i]];
+        if (p >= tx && row[p] == NO_SLOT) {
+            row[p] = 0;
+            stack.push_back(p);
+        }
+    }
+    while (!stack.empty()) {
+        const uint32_t p = stack.back();
+        stack.pop_back();
+        found.push_back(p);
+        for (uint32_t e = P.down_off[p]; e < P.down_off[p + 1]; ++e) {
+            const uint32_t u = P.down_arc[2 * uint64_t(e)] & TAIL_MASK;
+            if (u >= tx && row[u] == NO_SLOT) {
+                row[u] = 0;
+                stack.push_back(u);
+            }
+        }
+    }
+    // group key: core level, then (after every core level) the cell-local level
+    const uint32_t ncl = uint32_t(P.core_lvl.size() - 1);
+    auto key = [&](uint32_t p) -> uint32_t {
+        if (p < P.n_core)
+            return uint32_t(std::upper_bound(P.core_lvl.begin(), P.core_lvl.end(), p) - P.core_lvl.begin()) - 1;
+        const uint32_t c = P.cell_of[P.perm[p]];
+        const auto b = P.cell_lvl.begin() + P.cell_lvl_ptr[c], e = P.cell_lvl.begin() + P.cell_lvl_ptr[c + 1];
+        return ncl + uint32_t(std::upper_bound(b, e, p) - b) - 1;
+    };
+    std::vector<std::pair<uint32_t, uint32_t>> kp(found.size());
+    for (size_t i = 0; i < found.size(); ++i) kp[i] = {key(found[i]), found[i]};
+    std::sort(kp.begin(), kp.end());
+    T.nr = uint32_t(kp.size());
+    std::vector<uint32_t> rpos(T.nr), off(size_t(T.nr) + 1, 0);
+    for (uint32_t i = 0; i < T.nr; ++i) {
+        rpos[i] = kp[i].second;
+        row[kp[i].second] = tx + i;
+        if (i == 0 || kp[i].first != kp[i - 1].first) T.group.push_back(tx + i);
+    }
+    T.group.push_back(tx + T.nr);
+    std::vector<uint2> arc;
+    for (uint32_t i = 0; i < T.nr; ++i) {
+        const uint32_t p = rpos[i];
+        for (uint32_t e = P.down_off[p]; e < P.down_off[p + 1]; ++e) {
+            const uint32_t u = P.down_arc[2 * uint64_t(e)] & TAIL_MASK, w = P.down_arc[2 * uint64_t(e) + 1];
+            if (w == INF) continue;   // a dummy entry (reverse arc only) carries no path
+            arc.push_back(make_uint2(u < tx ? u : row[u], w));
+        }
+        off[i + 1] = uint32_t(arc.size());
+    }
+    T.arcs = arc.size();
+    std::vector<uint32_t> trow(count);
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint32_t p = P.pos[targets[i]];
+        trow[i] = p < tx ? p : row[p];
+    }
+    HIPCHK(hipSetDevice(device));
+    int r;
+    if ((r = dev_alloc_copy(&T.d_off, off, T.bytes))) return r;
+    if ((r = dev_alloc_copy(&T.d_arc, arc, T.bytes))) return r;
+    if ((r = dev_alloc_copy(&T.d_rpos, rpos, T.bytes))) return r;
+    if ((r = dev_alloc_copy(&T.d_row, trow, T.bytes))) return r;
+    return 0;
+}
+
 // Workgroups of a cell-sweep variant that fit one compute unit with `lds` bytes of LDS each
 // (cached per variant and size).
 int DevGraph::cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t &per_cu) {
@@ -1312,7 +1438,7 @@ void DevGraph::release() {
 
 void QueryBufs::release() {
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
-                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin};
+                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin, d_rlab};
     for (void *p : ptrs) if (p) hipFree(p);
     if (h_pinned) hipHostFree(h_pinned);
     *this = QueryBufs();
@@ -1438,6 +1564,49 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                                                                                           uint64_t(nu) * K);
         k_uset_claim<<<dim3(g), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
         k_uset_write<<<dim3(g), dim3(256), 0, s>>>(B.d_uslot, d_upos, d_ulane, d_ulab, B.d_uval, nu, lk);
+    }
+    if (A.tg) {   // one-to-many: the table product, then the target set's level groups
+        const TargetSet &T = *A.tg;
+        const uint64_t rows = uint64_t(T.tx) + T.nr;
+        if ((r = ensure((void **)&B.d_rlab, B.sz_rlab, std::max<uint64_t>(1, rows) * K * 4))) return r;
+        if (T.tx > 0) {
+            k_fill<<<dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (T.tx * K + 255) / 256))), dim3(256), 0,
+                     s>>>(B.d_rlab, INF, uint64_t(T.tx) * K);
+            const uint32_t tiles = (T.tx + 63) / 64;
+            const uint32_t splits =
+                std::max<uint32_t>(1, std::min<uint32_t>(64, 4096 / std::max<uint32_t>(1, tiles * K)));
+            k_top_table<<<dim3(tiles * K * splits), dim3(64), 0, s>>>(d_table, T.tx, TX, d_xptr, d_xpos, d_xval,
+                                                                       B.d_rlab, lk, tiles, splits);
+        }
+        for (size_t gi = 0; gi + 1 < T.group.size(); ++gi) {
+            const uint32_t rb = T.group[gi], re = T.group[gi + 1];
+            const uint64_t threads = uint64_t(re - rb) << lk;
+            k_rphast_level<<<dim3(uint32_t((threads + 255) / 256)), dim3(256), 0, s>>>(
+                T.d_off, T.d_arc, T.d_rpos, B.d_uslot, B.d_uval, B.d_rlab, T.tx, rb, re, lk);
+        }
+        if (T.count) {
+            const uint64_t threads = uint64_t(A.lanes) * T.count;
+            k_rphast_out<<<dim3(uint32_t((threads + 255) / 256)), dim3(256), 0, s>>>(B.d_rlab, T.d_row, T.count, lk,
+                                                                                    A.lanes, A.tg_out);
+        }
+        HIPCHK(hipGetLastError());
+        if (nu) k_uset_clear<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
+        HIPCHK(hipMemcpyAsync(C.h_counters, B.d_counters, 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(C.done, s));
+        C.pending = true;
+        C.K = K;
+        C.lk = lk;
+        C.lg = 0;
+        C.lanes = A.lanes;
+        C.lane_base = A.lane_base;
+        C.cap = cap;
+        C.mode_plain = true;
+        C.want_dist = false;
+        C.vertex_mode = false;
+        C.one_to_many = true;
+        C.nlev = 0;
+        C.top = 0;
+        return 0;
     }
     uint64_t *vin = reinterpret_cast<uint64_t *>(B.d_flags), *vout = vin + n_core;
     // counters: edges emitted, active cells, work items; the list buffer holds the cells' lane
@@ -1581,6 +1750,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     C.mode_plain = A.mode_plain;
     C.want_dist = A.want_dist;
     C.vertex_mode = vmode;
+    C.one_to_many = false;
     C.nlev = uint32_t(nlev);
     C.top = uint32_t(top);
     return 0;
@@ -1612,6 +1782,10 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
     C.pending = false;
     HIPCHK(hipSetDevice(device));
     HIPCHK(hipEventSynchronize(C.done));
+    if (C.one_to_many) {   // the distances are written; no edges, no phase profile
+        R = RunResult();
+        return 0;
+    }
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
     const uint32_t K = C.K;

@@ -15,4 +15,5 @@ from .roadgen import (  # noqa: F401
     CONFIGS,
     batch_queries,
     serving_trace,
+    target_ball,
 )

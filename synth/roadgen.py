@@ -241,3 +241,32 @@ def serving_trace(n: int, rate_hz: float, duration_s: float, seed: int = 15,
     src = rng.integers(0, n, size=cnt, dtype=np.int64).astype(np.uint32)
     tau = _round_half_away(np.exp(rng.uniform(np.log(lo_min), np.log(hi_min), size=cnt)) * 60_000.0)
     return t, src, tau.astype(np.uint32)
+
+
+def target_ball(g: Graph, size: int, seed: int = 16):
+    """A compact target set for one-to-many queries: a random centre c and the first `size`
+    vertices of a breadth-first traversal from c over the outgoing arcs (hop count, no
+    lengths).  Stands in for the paper's forward Dijkstra ball of the same size.  Returns
+    (c, targets) with the targets in traversal order (c first); fewer than `size` if c reaches
+    fewer vertices."""
+    rng = np.random.default_rng(seed)
+    n = g.n
+    tail, head = g.tail, g.head
+    if tail.size and np.any(tail[1:] < tail[:-1]):
+        order = np.argsort(tail, kind="stable")
+        tail, head = tail[order], head[order]
+    off = np.searchsorted(tail, np.arange(n + 1, dtype=np.int64)).astype(np.int64)
+    c = int(rng.integers(0, n))
+    seen = {c}
+    out = [c]
+    frontier = [c]
+    while len(out) < size and frontier:
+        nxt = []
+        for v in frontier:
+            for x in head[off[v]:off[v + 1]].tolist():
+                if x not in seen:
+                    seen.add(x)
+                    nxt.append(x)
+        out.extend(nxt)
+        frontier = nxt
+    return c, np.array(out[:size], dtype=np.uint32)
