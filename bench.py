@@ -410,12 +410,24 @@ def main():
     np_steps = max(2, args.steps // 4)
     ps_, pt_ = window(args.warmup * lanes, np_steps * lanes)
     dev.run(ps_[:lanes], pt_[:lanes], iso.MODE_PLAIN)
+    G.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dev.run(ps_, pt_, iso.MODE_PLAIN)
     torch.cuda.synchronize()
     qps_plain = np_steps * lanes / (time.perf_counter() - t0)
-    log(f"plain batched (device output): {qps_plain:.1f} queries/s")
+    prof_plain = G.profile_read()
+    G.profile_enable(False)
+    # the plain sweep (every cell for every query) with its own algorithmic bytes per launch
+    plain_phases = {}
+    for key in ("core", "cell"):
+        ms_, by_, la_ = prof_plain[f"{key}_ms"], prof_plain[f"{key}_bytes"], prof_plain[f"{key}_launches"]
+        if ms_ > 0:
+            gbs = (by_ / 1e9) / (ms_ / 1e3)
+            plain_phases[f"{key}_sweep"] = {"avg_launch_ms": round(ms_ / max(1, la_), 4),
+                                           "algorithmic_bytes_per_launch": int(by_ / max(1, la_)),
+                                           "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"plain batched (device output): {qps_plain:.1f} queries/s; phases {plain_phases}")
 
     # the other output of Section 3: vertices in range, as one bitmap row per query over the
     # original ids, left in HBM (one call per batch of `lanes` queries)
@@ -534,6 +546,9 @@ def main():
         "latency_ms": lat,
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
+        "plain_sweep_roofline": dict(plain_phases, unit="GB/s", peak=HBM_PEAK_GBS,
+                                     note="plain mode (every cell swept for every query), two overlapping "
+                                          "streams, HIP events per launch"),
         "host_api_qps": {"one_batch_per_call": round(qps_host, 2), "one_call": round(qps_host_pipe, 2),
                          "note": "iso_query_batch, edges copied to host memory (PCIe included)",
                          "call_ms_p50": round(1000 * percentile(times, 50), 3),

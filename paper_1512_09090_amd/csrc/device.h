@@ -203,6 +203,7 @@ struct DevGraph {
     // table prefix [0, tx) of table_levels levels, uploaded to the device.
     int select_targets(const iso::Prep &P, const uint32_t *targets, uint32_t count, uint32_t tx,
                        uint32_t table_levels, TargetSet &T);
+    std::vector<uint32_t> sel_row;   // target selection scratch: position -> row
     int run(SweepCtx &C, const RunArgs &A, RunResult &R);
     // device bytes a context needs for k lanes and an edge capacity (admission control)
     size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const;

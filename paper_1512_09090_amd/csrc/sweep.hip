@@ -1128,8 +1128,18 @@ int DevGraph::select_targets(const iso::Prep &P, const uint32_t *targets, uint32
     T.count = count;
     T.tx = tx;
     T.table_levels = table_levels;
-    std::vector<uint32_t> row(P.n, NO_SLOT);   // position -> row (NO_SLOT: not collected yet)
+    // position -> row (NO_SLOT: not collected yet); kept across selections, and only the
+    // entries a selection touches are reset at its end
+    std::vector<uint32_t> &row = sel_row;
+    if (row.size() != P.n) row.assign(P.n, NO_SLOT);
     std::vector<uint32_t> found, stack;
+    struct Reset {   // also on an exception: every marked position is in found or on the stack
+        std::vector<uint32_t> &row, &found, &stack;
+        ~Reset() {
+            for (uint32_t p : found) row[p] = NO_SLOT;
+            for (uint32_t p : stack) row[p] = NO_SLOT;
+        }
+    } reset{row, found, stack};
     for (uint32_t i = 0; i < count; ++i) {
         const uint32_t p = P.pos[targets[i]];
         if (p >= tx && row[p] == NO_SLOT) {
@@ -1139,8 +1149,8 @@ int DevGraph::select_targets(const iso::Prep &P, const uint32_t *targets, uint32
     }
     while (!stack.empty()) {
         const uint32_t p = stack.back();
+        found.push_back(p);   // before the pop: a marked position is always in one of the two
         stack.pop_back();
-        found.push_back(p);
         for (uint32_t e = P.down_off[p]; e < P.down_off[p + 1]; ++e) {
             const uint32_t u = P.down_arc[2 * uint64_t(e)] & TAIL_MASK;
             if (u >= tx && row[u] == NO_SLOT) {
