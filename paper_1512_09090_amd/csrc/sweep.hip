@@ -851,20 +851,58 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
         }
     }
     __syncthreads();
-    // entries of level 0 into buffer 0
+    // The leading levels hold a few vertices each: while a level fits the vertex slots of one
+    // wavefront and the entries so far fit one buffer, wavefront 0 sweeps it alone (below).
+    // Their entries go to buffer 0 in one round of loads, and the entries of the first level
+    // after them (l0) to buffer 1, where the level pipeline starts.
+    const uint32_t wslots = 64u >> lg, eb0 = s_off[s_lvl[0]];
+    uint32_t l0 = 0;
+    while (l0 < nl && s_lvl[l0 + 1] - s_lvl[l0] <= wslots && s_off[s_lvl[l0 + 1]] - eb0 <= CELL_BUF) ++l0;
     uint2 r[CELL_REGS];
     {
-        uint32_t eb = s_off[s_lvl[0]], n = min(s_off[s_lvl[1]] - eb, CELL_BUF);
+        const uint32_t n0 = s_off[s_lvl[l0]] - eb0;   // <= CELL_BUF
+        const uint32_t eb1 = l0 < nl ? s_off[s_lvl[l0]] : eb0;
+        const uint32_t n1 = l0 < nl ? min(s_off[s_lvl[l0 + 1]] - eb1, CELL_BUF) : 0u;
 #pragma unroll
         for (uint32_t k = 0; k < CELL_REGS; ++k) {
             uint32_t idx = tid + k * T;
-            if (k * T < CELL_BUF && idx < n) s_buf[idx] = gent[eb + idx];
+            if (k * T < CELL_BUF && idx < n0) s_buf[idx] = gent[eb0 + idx];
+            if (k * T < CELL_BUF && idx < n1) s_buf[CELL_BUF + idx] = gent[eb1 + idx];
         }
     }
     __syncthreads();
-    for (uint32_t l = 0; l < nl; ++l) {
-        const uint2 *cur = s_buf + (l & 1) * CELL_BUF;
-        uint2 *nxt = s_buf + ((l + 1) & 1) * CELL_BUF;
+    if (l0 > 0 && tid < 64) {
+        // the wavefront's lanes see each other's label writes through the in-order LDS accesses
+        // of one wavefront (a wavefront-scope fence between levels), not a workgroup barrier
+        for (uint32_t l = 0; l < l0; ++l) {
+            const uint32_t i = s_lvl[l] + (tid >> lg);
+            const bool act = i < s_lvl[l + 1];
+            const uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
+            uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
+            CellBits bits;
+            relax_cell_vertex(e0, e1, dv, bits, tau, s_lab, lg, j, [&](uint32_t e) { return s_buf[e - eb0]; });
+            if (act) {
+                s_lab[(i << lg) + j] = dv;
+                if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
+            }
+            if (A.vmask) or_in_range(A.vmask, act, live, cb + i, dv, tau, jj, j, lg);
+            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
+                             ref, cb, lanes, q);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (l0 == nl) {   // the whole cell fit one wavefront: write the candidates out
+        __syncthreads();
+        const uint32_t n = s_ctl[0];
+        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        return;
+    }
+    if (l0) __syncthreads();
+    for (uint32_t l = l0; l < nl; ++l) {
+        const uint32_t par = (l - l0 + 1) & 1u;   // level l0 is in buffer 1
+        const uint2 *cur = s_buf + par * CELL_BUF;
+        uint2 *nxt = s_buf + (par ^ 1u) * CELL_BUF;
         const uint32_t a = s_lvl[l], bnd = s_lvl[l + 1];
         const uint32_t ebase = s_off[a];
         const bool in_buf = s_off[bnd] - ebase <= CELL_BUF;
