@@ -292,7 +292,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="road18m")
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--latency-queries", type=int, default=100)
@@ -329,7 +329,9 @@ def main():
     if args.copy_probe_mb:
         copy_probe(args.copy_probe_mb)
     info = G.info()
-    src, tau = synth.config_queries(args.workload, 1000)
+    # the seeded query list of the workload, long enough that the warm-up and the timed batches
+    # hold different queries
+    src, tau = synth.config_queries(args.workload, max(1000, (max(1, args.warmup) + args.steps) * max(64, args.lanes)))
     lanes = args.lanes
     G.set_tuning(lanes_per_launch=lanes)
     tuning_note = "defaults"
@@ -500,6 +502,8 @@ def main():
                 "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
                 "note": "timed region: consecutive sweeps overlap on two streams, so a launch's duration "
                         "includes device time shared with the other sweep's kernels"}
+    if roofline["traffic"]:   # counter bytes per launch over the same launch time
+        roofline["traffic_gbs"] = round(roofline["traffic"] / 1e9 / (roofline["avg_launch_ms"] / 1e3), 1)
     key = {"core_sweep": "core", "cell_sweep": "cell"}[dom]
     iso_ms, iso_launches = prof_iso[f"{key}_ms"], prof_iso[f"{key}_launches"]
     if iso_ms > 0:

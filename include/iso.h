@@ -259,7 +259,7 @@ typedef struct {
     uint32_t table_max;         /* level-merge threshold: the top core levels are merged into one (min,+)
                                    product with the distance table of their vertices while they hold at
                                    most this many vertices; the levels below get one launch each.  0 =
-                                   4096; 1 = no table (every core level is its own launch and the upward
+                                   16384; 1 = no table (every core level is its own launch and the upward
                                    search runs to its end); 2..16384, capped at the table built at load
                                    (iso_graph_info top_table) */
 } iso_tuning;

@@ -26,7 +26,7 @@ SPACE = {
     "block": [128, 256, 512],
     "cell_lds_kb": [24, 40, 64, 96],
     "use_graph": [0, 1],
-    "table_max": [0, 1024, 8192, 16384],
+    "table_max": [0, 1024, 4096, 8192],
 }
 DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 0, "cell_block": 0,
            "table_max": 0}

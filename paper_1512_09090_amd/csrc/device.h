@@ -18,7 +18,7 @@ namespace isodev {
 
 constexpr size_t LDS_MAX = 160 * 1024;          // LDS of one gfx950 compute unit
 constexpr uint32_t TABLE_MAX = 16384;           // vertices of the top-of-hierarchy distance table built at load
-constexpr uint32_t TABLE_DEFAULT = 4096;        // vertices of the levels merged into it by default
+constexpr uint32_t TABLE_DEFAULT = TABLE_MAX;   // vertices of the levels merged into it by default
 constexpr uint32_t MAX_LANES = 64;
 constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a 6-bit lane chunk
 
@@ -102,16 +102,18 @@ struct QueryBufs {
     uint64_t *d_keys = nullptr, *d_keys_sorted = nullptr;
     uint64_t *d_vmask = nullptr, *d_cin = nullptr;   // vertex output: lanes in range per position; per cell
     uint32_t *d_rlab = nullptr;                        // one-to-many: labels of a target set's rows
+    uint64_t *d_prof = nullptr;                        // profile: cell-sweep sums (k_prof_cells)
     uint32_t *d_lane_off = nullptr;   // MAX_LANES + 1 lane starts of the decoded edges
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
     size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
            sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0,
-           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0, sz_rlab = 0;
+           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0, sz_rlab = 0, sz_prof = 0;
     void release();
 };
 
 struct Profile {
     bool on = false;
+    bool acc_ready = false;   // the device sums (QueryBufs::d_prof) were cleared since enabling
     double core_ms = 0, active_ms = 0, cell_ms = 0, sort_ms = 0;
     uint64_t core_launches = 0, cell_launches = 0, calls = 0, core_bytes = 0, cell_bytes = 0;
     uint64_t core_entries = 0, cell_entries = 0, cell_vertices = 0, cells_swept = 0, cell_lanes = 0,

@@ -883,6 +883,14 @@ int iso_profile_read(const iso_graph *g, iso_profile *o) {
     *o = iso_profile{};
     for (const isodev::SweepCtx *C : {&g->D.main, &g->D.aux}) {   // both sweep contexts of query calls
         const auto &P = C->prof;
+        if (P.acc_ready && C->bufs.d_prof) {   // the cell-sweep sums kept on the device
+            uint64_t acc[5] = {0, 0, 0, 0, 0};
+            if (hipSetDevice(g->D.device) != hipSuccess ||
+                hipMemcpy(acc, C->bufs.d_prof, sizeof acc, hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(ISO_EDEVICE, "reading the profile sums failed");
+            o->cell_bytes += acc[0]; o->cells_swept += acc[1]; o->cell_lanes += acc[2];
+            o->cell_vertices += acc[3]; o->cell_entries += acc[4];
+        }
         o->core_ms += P.core_ms; o->active_ms += P.active_ms; o->cell_ms += P.cell_ms; o->sort_ms += P.sort_ms;
         o->core_launches += P.core_launches; o->cell_launches += P.cell_launches; o->calls += P.calls;
         o->core_bytes += P.core_bytes; o->cell_bytes += P.cell_bytes;

@@ -77,6 +77,33 @@ __global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *_
     for (uint32_t l = from; l <= j; ++l) lane_off[l] = base + i;
 }
 
+// Phase profile of the cell sweep, summed on the device so that a sweep needs no copy back:
+// per active cell its lanes, internal vertices and entries, and its algorithmic bytes (the
+// cell's data streamed once, each active lane reading each referenced core label once), added
+// into acc[0..4] = bytes, cells, lanes, vertices, entries.  Every thread reaches the reduction.
+__host__ __device__ __forceinline__ uint32_t blob_words(uint32_t cnt, uint32_t nl, uint32_t nrefs, uint32_t ne);
+__global__ void k_prof_cells(const uint32_t *__restrict__ clist, const uint32_t *__restrict__ counters,
+                             const uint64_t *__restrict__ cmask, const uint4 *__restrict__ cmeta,
+                             unsigned long long *__restrict__ acc) {
+    const uint32_t n = counters[1];
+    unsigned long long v[5] = {0, 0, 0, 0, 0};
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t c = clist[i];
+        const uint4 m = cmeta[c];
+        const unsigned long long l = (unsigned long long)__popcll(cmask[c]);
+        v[0] += 4ull * blob_words(m.x, m.y, m.z, m.w) + l * 4ull * m.z;
+        v[1] += 1;
+        v[2] += l;
+        v[3] += m.x;
+        v[4] += m.w;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 5; ++k) {
+        for (uint32_t o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], (int)o);
+        if (__lane_id() == 0 && v[k]) atomicAdd(&acc[k], v[k]);
+    }
+}
+
 __global__ void k_fill(uint32_t *__restrict__ p, uint32_t value, uint64_t count) {
     uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
@@ -1486,7 +1513,7 @@ void DevGraph::release() {
 
 void QueryBufs::release() {
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
-                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin, d_rlab};
+                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin, d_rlab, d_prof};
     for (void *p : ptrs) if (p) hipFree(p);
     if (h_pinned) hipHostFree(h_pinned);
     *this = QueryBufs();
@@ -1780,6 +1807,15 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         HIPCHK(hipEventRecord(C.prof.ev[2], s));
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[3], s));
+    if (prof_on && num_cells > 0) {   // after the last phase event: not part of any phase's time
+        if ((r = ensure((void **)&B.d_prof, B.sz_prof, 8 * sizeof(uint64_t)))) return r;
+        if (!C.prof.acc_ready) {
+            k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_prof), 0u, 16);
+            C.prof.acc_ready = true;
+        }
+        k_prof_cells<<<dim3(64), dim3(256), 0, s>>>(d_clist, B.d_counters, d_cmask, d_cmeta,
+                                                   reinterpret_cast<unsigned long long *>(B.d_prof));
+    }
     if (vmode) {   // lane masks by position -> one bitmap row per lane over the original ids
         const uint32_t W = (n + 63) / 64;
         k_vmask_out<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(B.d_vmask, d_pos, n, W, A.lanes, A.vbits);
@@ -1867,23 +1903,8 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
             HIPCHK(hipEventElapsedTime(&ms, prof.ev[2], prof.ev[3]));
             prof.cell_ms += ms;
             prof.cell_launches++;
-            std::vector<uint32_t> lst(n_active);
-            std::vector<uint64_t> masks(num_cells);
-            if (n_active) {
-                HIPCHK(hipMemcpy(lst.data(), B.d_list + 2 * size_t(num_cells), size_t(n_active) * 4,
-                                 hipMemcpyDeviceToHost));
-                HIPCHK(hipMemcpy(masks.data(), B.d_list, size_t(num_cells) * 8, hipMemcpyDeviceToHost));
-            }
             prof.cell_items += C.h_counters[2];
-            for (uint32_t c : lst) {
-                const uint64_t lanes = uint64_t(__builtin_popcountll(masks[c]));
-                prof.cells_swept++;
-                prof.cell_lanes += lanes;
-                prof.cell_vertices += cell_cnt[c];
-                prof.cell_entries += cell_entries[c];
-                // the cell's arcs streamed once; each lane reads each referenced core label once
-                prof.cell_bytes += 4ull * cell_words[c] + lanes * 4ull * cell_core_refs[c];
-            }
+            // the per-cell counts and bytes are summed on the device (k_prof_cells)
         }
     }
     if (C.vertex_mode) {   // the vertex bitmaps are written; the edge keys are not used
