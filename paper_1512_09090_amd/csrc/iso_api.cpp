@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <unordered_map>
+#include <deque>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -360,9 +361,9 @@ int iso_graph_get_info(const iso_graph *g, iso_graph_info *info) {
 }
 
 // k queries in sweeps of up to lanes_per_launch lanes.  With more than one sweep, two sweep
-// contexts alternate: the host upward searches and the launch of sweep i overlap the device
-// work of sweep i - 1, whose edges are then collected.  (Phase timings of the profile then
-// include the device time that the two sweeps share.)
+// contexts alternate: the host upward searches of sweep i overlap the device work of sweeps
+// i - 1 and i - 2; then sweep i - 2's edges are collected and sweep i is launched on its
+// context.  (Phase timings of the profile then include the device time that sweeps share.)
 // With `dev` set the edges stay on the device instead (iso_query_batch_device): sweep i decodes its
 // lanes into dev->pairs after the edges of the sweeps before it and writes their starts to
 // dev->off; a sweep that would pass dev->cap is counted but not written, and the call then
@@ -463,48 +464,51 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         g->last.t_sort_ms += R.t_result_ms;
         return ISO_OK;
     };
-    std::unique_ptr<Sweep> prev;
-    auto drain = [&]() {   // leave a launched sweep's context idle after an error
-        if (!prev) return;
-        isodev::RunResult R;
-        D.finish(*prev->C, R);
-        prev.reset();
+    // Sweeps in flight, oldest first: sweep i runs on context i mod nctx, whose previous sweep
+    // (i - nctx) is collected only after sweep i's upward searches, so that those overlap the
+    // device work of the sweeps before it.
+    isodev::SweepCtx *ctxs[2] = {&D.main, &D.aux};
+    const size_t nctx = overlap ? 2 : 1;
+    std::deque<std::unique_ptr<Sweep>> inflight;
+    auto drain = [&]() {   // leave every launched sweep's context idle after an error
+        while (!inflight.empty()) {
+            isodev::RunResult R;
+            D.finish(*inflight.front()->C, R);
+            inflight.pop_front();
+        }
     };
     for (size_t i = 0; i < nsweeps; ++i) {
         auto W = std::make_unique<Sweep>();
         W->b = i * per;
         W->lanes = uint32_t(std::min<size_t>(per, k - W->b));
-        W->C = overlap && (i & 1) ? &D.aux : &D.main;
+        W->C = ctxs[i % nctx];
         W->settled.assign(W->lanes, 0);
         const double tu = now_ms();
         build_run_args(g, src + W->b, tau + W->b, W->lanes, mode == ISO_MODE_PLAIN, false, W->A, W->settled.data());
         W->A.out_cap = g->out_cap;
         g->last.t_upward_ms += now_ms() - tu;
+        if (inflight.size() == nctx) {   // frees W's context
+            int r = collect(*inflight.front());
+            inflight.pop_front();
+            if (r) {
+                drain();
+                return r;
+            }
+        }
         int r = D.launch(*W->C, W->A);
         if (r) {
             drain();
             return r;
         }
-        if (prev) {
-            r = collect(*prev);
-            prev.reset();
-            if (r) {
-                prev = std::move(W);
-                drain();
-                return r;
-            }
-        }
-        prev = std::move(W);
-        if (!overlap) {   // one context: collect before the next sweep is launched
-            r = collect(*prev);
-            prev.reset();
-            if (r) return r;
-        }
+        inflight.push_back(std::move(W));
     }
-    if (prev) {
-        int r = collect(*prev);
-        prev.reset();
-        if (r) return r;
+    while (!inflight.empty()) {
+        int r = collect(*inflight.front());
+        inflight.pop_front();
+        if (r) {
+            drain();
+            return r;
+        }
     }
     g->last.edges = out.n;
     if (dev) {
