@@ -346,3 +346,39 @@ def test_result_buffer_views_own_library_memory():
         assert empty.shape == (0, 2) and len(freed) == 2
     finally:
         binding._lib = saved
+
+
+def test_device_only_entry_points_refuse_hostless_graphs():
+    """The device-output, vertex-output and one-to-many entry points on a graph loaded without a
+    device, and their argument checks, fail with status codes before any device work."""
+    import ctypes
+
+    g = synth.config_graph("grid64")
+    G = iso.Graph.from_synth(g, num_cells=16, device=-1)
+    L = iso.lib()
+    src = np.array([1, 2], dtype=np.uint32)
+    tau = np.array([100, 200], dtype=np.uint32)
+    sp = src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    tp = tau.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    with pytest.raises(iso.IsoError) as e:
+        G.query_vertices(1, 100, iso.MODE_CELLS)
+    assert e.value.code == iso.ISO_EDEVICE
+    words = np.zeros(2 * 64, dtype=np.uint64)
+    rc = L.iso_query_batch_vertices_device(G._h, 2, sp, tp, iso.MODE_CELLS, ctypes.c_void_p(words.ctypes.data), None)
+    assert rc == iso.ISO_EDEVICE
+    total = ctypes.c_uint64()
+    offs = np.zeros(3, dtype=np.uint32)
+    rc = L.iso_query_batch_device(G._h, 2, sp, tp, iso.MODE_CELLS, ctypes.c_void_p(words.ctypes.data), 10,
+                                  ctypes.c_void_p(offs.ctypes.data), ctypes.byref(total), None)
+    assert rc == iso.ISO_EDEVICE
+    rc = L.iso_query_batch_device(G._h, 2, sp, tp, iso.MODE_CELLS, None, 10, None, ctypes.byref(total), None)
+    assert rc == iso.ISO_EINVAL                  # NULL offsets
+    with pytest.raises(iso.IsoError) as e:
+        G.select_targets(np.array([1, 2, 3], dtype=np.uint32))
+    assert e.value.code == iso.ISO_EDEVICE
+    h = ctypes.c_void_p()
+    rc = L.iso_targets_select(G._h, None, 3, ctypes.byref(h))
+    assert rc == iso.ISO_EINVAL and not h.value  # NULL targets with a count
+    L.iso_targets_free(None)                     # freeing nothing is a no-op
+    rc = L.iso_targets_get_info(None, None, None, None, None)
+    assert rc == iso.ISO_EINVAL
