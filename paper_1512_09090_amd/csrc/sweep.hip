@@ -535,7 +535,12 @@ __global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t m = c < num_cells ? cmask[c] : 0ull;
     const bool act = m != 0;
-    const uint32_t nch = act ? (uint32_t(__popcll(m)) + (1u << lg) - 1u) >> lg : 0u;
+    // full items of G = 1 << lg lanes, then the rest: a narrow item of G / 2 slots when it fits
+    // (a G-lane workgroup spends about as long per item whatever the lanes it holds, and a
+    // narrow item has twice the vertex slots per level)
+    const uint32_t L = uint32_t(__popcll(m)), full = L >> lg, rest = L & ((1u << lg) - 1u);
+    const bool narrow = lg > 0 && rest > 0 && rest <= (1u << (lg - 1));
+    const uint32_t nch = act ? full + (rest > 0 ? 1u : 0u) : 0u;
     const uint64_t amask = __ballot(act);
     if (amask == 0) return;
     const uint32_t lane = __lane_id();
@@ -556,7 +561,8 @@ __global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_
     if (act) {
         list[lbase + (uint32_t)__popcll(amask & ((1ull << lane) - 1ull))] = c;
         const uint32_t first = ibase + incl - nch;
-        for (uint32_t q = 0; q < nch; ++q) items[first + q] = (c << 6) | q;
+        for (uint32_t q = 0; q < full; ++q) items[first + q] = (c << 7) | q;
+        if (rest) items[first + full] = narrow ? (c << 7) | 64u | (2u * full) : (c << 7) | full;
     }
 }
 
@@ -670,7 +676,8 @@ __host__ __device__ __forceinline__ uint32_t cell_lds_words(uint32_t cnt, uint32
 }
 
 // Output key of a candidate: head = internal vertex i, tail = the local index in i's k-th entry
-// (internal or core reference), both mapped to original ids.
+// (internal or core reference), both mapped to original ids.  q is the rank of the work item's
+// first lane among the cell's active lanes; the candidate's lane slot j is added to it.
 template <class ENT, class REF>
 __device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, const uint32_t *s_off, uint32_t cnt,
                                              ENT ent, REF ref, uint32_t cb, uint64_t lanes, uint32_t q) {
@@ -678,7 +685,7 @@ __device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, c
     const uint32_t lt = ent(s_off[i] + k).x & LOCAL_MASK;
     const uint32_t ov = A.perm[cb + i];
     const uint32_t ot = A.perm[lt < cnt ? cb + lt : ref(lt - cnt)];
-    const uint32_t lane = A.lane_base + nth_set_bit(lanes, (q << A.lg) + j);
+    const uint32_t lane = A.lane_base + nth_set_bit(lanes, q + j);
     return (word >> 31) ? edge_key(lane, ov, ot, A.ib) : edge_key(lane, ot, ov, A.ib);
 }
 
@@ -794,9 +801,11 @@ __device__ __forceinline__ void level_end(uint32_t l, uint32_t nl, uint32_t *s_c
 // a vertex's label is final.  Slots of an item beyond its lane count repeat its first lane
 // and neither write distances nor emit edges.
 __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t *smem, uint32_t it) {
-    const uint32_t lk = A.lk, lg = A.lg;
+    const uint32_t lk = A.lk;
     const uint32_t code = A.items[it];
-    const uint32_t c = code >> 6, q = code & 63u;
+    // code = cell << 7 | narrow << 6 | index; a narrow item holds half the lane slots (G / 2)
+    const uint32_t c = code >> 7, lg = (code & 64u) ? A.lg - 1u : A.lg;
+    const uint32_t q = (code & 63u) << lg;   // rank of the item's first lane among the cell's
     const uint64_t lanes = A.cmask[c];
     const uint4 meta = A.cmeta[c];
     const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z;
@@ -815,9 +824,9 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
     const uint32_t tid = threadIdx.x;
     const uint32_t G = 1u << lg;
     const uint32_t j = tid & (G - 1);             // slot within the item
-    const uint32_t rank = (q << lg) + j;
+    const uint32_t rank = q + j;
     const bool live = rank < uint32_t(__popcll(lanes));
-    const uint32_t jj = nth_set_bit(lanes, live ? rank : (q << lg));   // lane within the batch
+    const uint32_t jj = nth_set_bit(lanes, live ? rank : q);   // lane within the batch
     const uint32_t tau = A.taus[jj];
     const bool has_up = A.src_cell[jj] == c;
     const uint32_t T = blockDim.x, per_iter = T >> lg;
@@ -993,9 +1002,11 @@ __host__ __device__ __forceinline__ uint32_t staged_lds_words(uint32_t words, ui
 // isochrone edge is written: each level costs LDS accesses and one barrier.  The copy keeps up
 // to eight 16-byte loads per thread in flight.
 __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *smem, uint32_t it) {
-    const uint32_t lk = A.lk, lg = A.lg;
+    const uint32_t lk = A.lk;
     const uint32_t code = A.items[it];
-    const uint32_t c = code >> 6, q = code & 63u;
+    // code = cell << 7 | narrow << 6 | index; a narrow item holds half the lane slots (G / 2)
+    const uint32_t c = code >> 7, lg = (code & 64u) ? A.lg - 1u : A.lg;
+    const uint32_t q = (code & 63u) << lg;   // rank of the item's first lane among the cell's
     const uint64_t lanes = A.cmask[c];
     const uint4 meta = A.cmeta[c];
     const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z;
@@ -1009,9 +1020,9 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
     const uint32_t tid = threadIdx.x;
     const uint32_t G = 1u << lg;
     const uint32_t j = tid & (G - 1);
-    const uint32_t rank = (q << lg) + j;
+    const uint32_t rank = q + j;
     const bool live = rank < uint32_t(__popcll(lanes));
-    const uint32_t jj = nth_set_bit(lanes, live ? rank : (q << lg));
+    const uint32_t jj = nth_set_bit(lanes, live ? rank : q);
     const uint32_t tau = A.taus[jj];
     const bool has_up = A.src_cell[jj] == c;
     const uint32_t per_iter = blockDim.x >> lg;
