@@ -20,7 +20,7 @@ constexpr size_t LDS_MAX = 160 * 1024;          // LDS of one gfx950 compute uni
 constexpr uint32_t TABLE_MAX = 16384;           // vertices of the top-of-hierarchy distance table built at load
 constexpr uint32_t TABLE_DEFAULT = TABLE_MAX;   // vertices of the levels merged into it by default
 constexpr uint32_t MAX_LANES = 64;
-constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a 6-bit lane chunk
+constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a width shift and a lane chunk
 
 struct TargetSet;
 

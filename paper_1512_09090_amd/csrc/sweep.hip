@@ -535,11 +535,12 @@ __global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t m = c < num_cells ? cmask[c] : 0ull;
     const bool act = m != 0;
-    // full items of G = 1 << lg lanes, then the rest: a narrow item of G / 2 slots when it fits
-    // (a G-lane workgroup spends about as long per item whatever the lanes it holds, and a
-    // narrow item has twice the vertex slots per level)
+    // full items of G = 1 << lg lanes, then the rest in one item of the fewest lane slots that
+    // hold it, G / 2^shift with shift <= 3 (a workgroup spends about as long per item whatever
+    // lanes it holds, and fewer lane slots leave more vertex slots per level)
     const uint32_t L = uint32_t(__popcll(m)), full = L >> lg, rest = L & ((1u << lg) - 1u);
-    const bool narrow = lg > 0 && rest > 0 && rest <= (1u << (lg - 1));
+    uint32_t shift = 0;
+    while (shift < 3 && shift < lg && rest > 0 && rest <= (1u << (lg - shift - 1))) ++shift;
     const uint32_t nch = act ? full + (rest > 0 ? 1u : 0u) : 0u;
     const uint64_t amask = __ballot(act);
     if (amask == 0) return;
@@ -561,8 +562,8 @@ __global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_
     if (act) {
         list[lbase + (uint32_t)__popcll(amask & ((1ull << lane) - 1ull))] = c;
         const uint32_t first = ibase + incl - nch;
-        for (uint32_t q = 0; q < full; ++q) items[first + q] = (c << 7) | q;
-        if (rest) items[first + full] = narrow ? (c << 7) | 64u | (2u * full) : (c << 7) | full;
+        for (uint32_t q = 0; q < full; ++q) items[first + q] = (c << 8) | q;
+        if (rest) items[first + full] = (c << 8) | (shift << 6) | (full << shift);
     }
 }
 
@@ -803,8 +804,8 @@ __device__ __forceinline__ void level_end(uint32_t l, uint32_t nl, uint32_t *s_c
 __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t *smem, uint32_t it) {
     const uint32_t lk = A.lk;
     const uint32_t code = A.items[it];
-    // code = cell << 7 | narrow << 6 | index; a narrow item holds half the lane slots (G / 2)
-    const uint32_t c = code >> 7, lg = (code & 64u) ? A.lg - 1u : A.lg;
+    // code = cell << 8 | shift << 6 | index: the item has G >> shift lane slots
+    const uint32_t c = code >> 8, lg = A.lg - ((code >> 6) & 3u);
     const uint32_t q = (code & 63u) << lg;   // rank of the item's first lane among the cell's
     const uint64_t lanes = A.cmask[c];
     const uint4 meta = A.cmeta[c];
@@ -1004,8 +1005,8 @@ __host__ __device__ __forceinline__ uint32_t staged_lds_words(uint32_t words, ui
 __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *smem, uint32_t it) {
     const uint32_t lk = A.lk;
     const uint32_t code = A.items[it];
-    // code = cell << 7 | narrow << 6 | index; a narrow item holds half the lane slots (G / 2)
-    const uint32_t c = code >> 7, lg = (code & 64u) ? A.lg - 1u : A.lg;
+    // code = cell << 8 | shift << 6 | index: the item has G >> shift lane slots
+    const uint32_t c = code >> 8, lg = A.lg - ((code >> 6) & 3u);
     const uint32_t q = (code & 63u) << lg;   // rank of the item's first lane among the cell's
     const uint64_t lanes = A.cmask[c];
     const uint4 meta = A.cmeta[c];
