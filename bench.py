@@ -309,6 +309,9 @@ def main():
                     help="offered Poisson rates (queries/s) for the serving section; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-sweep", action="store_true", help="skip the queries-per-sweep comparison")
+    ap.add_argument("--cd-minutes", default="5,15,45",
+                    help="limits (minutes) of the isoPHAST-CD comparison; empty to skip")
+    ap.add_argument("--cd-queries", type=int, default=40)
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the warm-up and the timed cells-mode batches (for profiler runs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -489,6 +492,34 @@ def main():
         lat[name]["last_query"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
         log(f"single {name}: {lat[name]}")
 
+    # isoPHAST-CD (core isoDijkstra on the host) against the core sweep at fixed limits: single
+    # queries and batches of `lanes`, the same sources for both modes
+    core_search = {}
+    if args.cd_minutes:
+        cd_src = synth.batch_queries(info["n"], max(args.cd_queries, lanes), seed=515)[0]
+        cd_dev = DeviceBatches(iso, G, 64.0)
+        for minutes in [int(x) for x in args.cd_minutes.split(",") if x]:
+            t_lim = np.full(len(cd_src), minutes * 60_000, dtype=np.uint32)
+            row = {}
+            for name, mode in (("cd", iso.MODE_CD), ("cells", iso.MODE_CELLS)):
+                G.query(int(cd_src[0]), int(t_lim[0]), mode)
+                ts = []
+                for j in range(args.cd_queries):
+                    a = time.perf_counter()
+                    G.query(int(cd_src[j]), int(t_lim[j]), mode)
+                    ts.append(1000.0 * (time.perf_counter() - a))
+                cd_dev.run(cd_src[:lanes], t_lim[:lanes], mode)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                for _ in range(3):
+                    cd_dev.run(cd_src[:lanes], t_lim[:lanes], mode)
+                torch.cuda.synchronize()
+                row[name] = {"single_p50_ms": round(percentile(ts, 50), 3),
+                             "single_p99_ms": round(percentile(ts, 99), 3),
+                             "batch_qps": round(3 * lanes / (time.perf_counter() - a), 1)}
+            core_search[f"{minutes}min"] = row
+            log(f"isoPHAST-CD vs CP at {minutes} min: {row}")
+
     # roofline of the dominant device phase in the timed region
     phases = {"core_sweep": (prof["core_ms"], prof["core_bytes"], prof["core_launches"]),
               "cell_sweep": (prof["cell_ms"], prof["cell_bytes"], prof["cell_launches"])}
@@ -562,6 +593,9 @@ def main():
                               "note": "iso_query_batch_vertices_device: the vertices in range of each query "
                                       "as a bitmap over the original ids, left in HBM"},
         "one_to_many": one_to_many,
+        "core_search_mode": dict(core_search, note="isoPHAST-CD (isoDijkstra over the core on the host, stopped at "
+                                 "tau) against the core sweep (isoPHAST-CP), fixed tau, same sources; single queries "
+                                 "through iso_query, batches through iso_query_batch_device"),
         "queries_per_sweep_qps": sweep,
         "timed_call": dict(batch_stats, edges_in_hbm=int(edges_total)),
         "serving": serve,

@@ -60,7 +60,13 @@ typedef enum {
 
 typedef enum {
     ISO_MODE_PLAIN = 0, /* sweep every vertex (PHAST one-to-all, Section 2) */
-    ISO_MODE_CELLS = 1  /* sweep the core, then the active cells only (isoPHAST-CP, Section 5) */
+    ISO_MODE_CELLS = 1, /* sweep the core, then the active cells only (isoPHAST-CP, Section 5) */
+    ISO_MODE_CD = 2     /* isoPHAST-CD (Section 5): the core labels come from an isoDijkstra search on
+                           the host over the core graph, stopped at tau, instead of a sweep of the
+                           core; the active cells and their sweeps are those of ISO_MODE_CELLS, and so
+                           is the answer.  Needs a partition.  Suited to small limits: its cost grows
+                           with the core vertices in range, the core sweep's with the whole core.
+                           Not for iso_query_distances (core labels above tau are left unset). */
 } iso_mode;
 
 typedef struct iso_graph iso_graph;
@@ -130,7 +136,8 @@ int iso_graph_get_info(const iso_graph *g, iso_graph_info *info);
 /*
  * One isochrone query (Section 3).  *edges receives count arcs sorted by
  * (tail, head) without duplicates; release with iso_free.  mode selects the
- * full sweep or the cell-restricted sweep; both return the same set.
+ * full sweep, the cell-restricted sweep or the core search (iso_mode); all
+ * return the same set.
  */
 int iso_query(iso_graph *g, uint32_t source, uint32_t tau, int mode,
               iso_edge **edges, size_t *count);
@@ -223,7 +230,8 @@ void iso_targets_free(iso_targets *t);
  * memory) receives min(d(s, v), ISO_INF) for every vertex the sweep labelled
  * (all vertices in ISO_MODE_PLAIN; core vertices and the vertices of active
  * cells in ISO_MODE_CELLS) and ISO_INF elsewhere; swept (optional, n bytes)
- * receives 1 for labelled vertices and 0 otherwise.
+ * receives 1 for labelled vertices and 0 otherwise.  ISO_MODE_CD gives
+ * ISO_EINVAL.
  */
 int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode,
                         uint32_t *dist, uint8_t *swept);
@@ -341,7 +349,7 @@ typedef struct {
     uint32_t max_lanes;         /* queries per sweep, 1..64 (0 = 64) */
     uint32_t max_inflight;      /* sweeps in flight at once, 1..4 (0 = 2) */
     uint64_t device_budget;     /* device bytes for the sweep contexts (0 = no limit) */
-    int mode;                   /* ISO_MODE_PLAIN or ISO_MODE_CELLS */
+    int mode;                   /* ISO_MODE_PLAIN, ISO_MODE_CELLS or ISO_MODE_CD */
 } iso_server_config;
 typedef struct {
     double t_queue_ms;          /* submit -> its sweep was launched */

@@ -15,7 +15,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "iso.h")
 
 ISO_OK, ISO_EINVAL, ISO_ENOMEM, ISO_EDEVICE, ISO_EFORMAT, ISO_EBUSY, ISO_ESTATE, ISO_EAGAIN, ISO_ESPACE = \
     0, -1, -2, -3, -4, -6, -7, -8, -9
-MODE_PLAIN, MODE_CELLS = 0, 1
+MODE_PLAIN, MODE_CELLS, MODE_CD = 0, 1, 2
 INF = 0xFFFFFFFF
 TAU_MAX = 0xFFFFFFFE
 

@@ -140,6 +140,93 @@ struct UpwardSearch {
     }
 };
 
+// isoPHAST-CD (Section 5): the core graph as out-arcs over core positions: the upward arcs of
+// the core and its downward entries turned around (finite lengths only).  Together they are
+// the contraction hierarchy of the core graph, which keeps every distance between core
+// vertices, so a Dijkstra search on them gives the core distances.
+struct CoreGraph {
+    std::vector<uint32_t> off;   // n_core + 1
+    std::vector<uint64_t> arc;   // head << 32 | length
+    void build(const iso::Prep &P) {
+        const uint32_t nc = P.n_core;
+        off.assign(size_t(nc) + 1, 0);
+        for (uint32_t x = 0; x < nc; ++x) off[x + 1] += P.up_off[x + 1] - P.up_off[x];
+        for (uint32_t v = 0; v < nc; ++v)
+            for (uint32_t e = P.down_off[v]; e < P.down_off[v + 1]; ++e)
+                if (P.down_arc[2 * uint64_t(e) + 1] != iso::INF) off[(P.down_arc[2 * uint64_t(e)] & iso::TAIL_MASK) + 1]++;
+        for (uint32_t x = 0; x < nc; ++x) off[x + 1] += off[x];
+        arc.resize(off[nc]);
+        std::vector<uint32_t> fill(off.begin(), off.end() - 1);
+        for (uint32_t x = 0; x < nc; ++x)
+            for (uint32_t e = P.up_off[x]; e < P.up_off[x + 1]; ++e)
+                arc[fill[x]++] = (uint64_t(P.up_head[e]) << 32) | P.up_w[e];
+        for (uint32_t v = 0; v < nc; ++v)
+            for (uint32_t e = P.down_off[v]; e < P.down_off[v + 1]; ++e) {
+                const uint32_t w = P.down_arc[2 * uint64_t(e) + 1];
+                if (w == iso::INF) continue;   // a dummy entry (reverse arc only)
+                const uint32_t u = P.down_arc[2 * uint64_t(e)] & iso::TAIL_MASK;
+                arc[fill[u]++] = (uint64_t(v) << 32) | w;
+            }
+    }
+};
+
+// isoDijkstra on the core graph (stopping criterion of Section 3) from the core vertices an
+// upward search reached, with their labels.  Returns the settled vertices (label <= tau, exact)
+// as (position, label) pairs; the labels of the others are upper bounds or missing, which the
+// query treats as out of range (Section 5).  Labels are stamped per call (no O(n_core) reset).
+struct CoreDijkstra {
+    std::vector<uint32_t> dist, stamp;
+    std::vector<uint8_t> done;
+    uint32_t epoch = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> heap;   // (label, position), a min-heap
+    void run(const CoreGraph &G, const std::vector<std::pair<uint32_t, uint32_t>> &seeds, uint32_t tau,
+             std::vector<std::pair<uint32_t, uint32_t>> &out) {
+        const size_t nc = G.off.size() - 1;
+        if (dist.size() != nc) {
+            dist.assign(nc, iso::INF);
+            stamp.assign(nc, 0);
+            done.assign(nc, 0);
+            epoch = 0;
+        }
+        if (++epoch == 0) {   // wrapped: clear the stamps once
+            std::fill(stamp.begin(), stamp.end(), 0u);
+            epoch = 1;
+        }
+        auto label = [&](uint32_t v) { return stamp[v] == epoch ? dist[v] : iso::INF; };
+        auto cmp = [](const std::pair<uint32_t, uint32_t> &a, const std::pair<uint32_t, uint32_t> &b) {
+            return a.first > b.first;
+        };
+        heap.clear();
+        out.clear();
+        for (const auto &sd : seeds)
+            if (sd.second < label(sd.first)) {
+                dist[sd.first] = sd.second;
+                stamp[sd.first] = epoch;
+                done[sd.first] = 0;
+                heap.push_back({sd.second, sd.first});
+            }
+        std::make_heap(heap.begin(), heap.end(), cmp);
+        while (!heap.empty() && heap.front().first <= tau) {
+            std::pop_heap(heap.begin(), heap.end(), cmp);
+            const auto [d, u] = heap.back();
+            heap.pop_back();
+            if (d != dist[u] || done[u]) continue;   // stale entry
+            done[u] = 1;
+            out.push_back({u, d});
+            for (uint32_t e = G.off[u]; e < G.off[u + 1]; ++e) {
+                const uint32_t x = uint32_t(G.arc[e] >> 32), nd = iso::sat_add(d, uint32_t(G.arc[e]));
+                if (nd < label(x)) {
+                    dist[x] = nd;
+                    if (stamp[x] != epoch) done[x] = 0;
+                    stamp[x] = epoch;
+                    heap.push_back({nd, x});
+                    std::push_heap(heap.begin(), heap.end(), cmp);
+                }
+            }
+        }
+    }
+};
+
 // Persistent host worker threads: run(use, f) calls f(w) for w in [0, use) on the pool's
 // threads (the caller is worker 0) and returns when every call has returned.  One run at a
 // time (a graph is used by one call, or by its server, at a time).
@@ -217,6 +304,9 @@ struct iso_graph {
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> up_out;   // one search result buffer per worker
     size_t out_cap = 1 << 20;
     uint64_t *vbits_dev = nullptr;   // device bitmap of iso_query_vertices (ceil(n / 64) words)
+    std::unique_ptr<CoreGraph> coreg;         // isoPHAST-CD: core graph (built on first use)
+    std::vector<CoreDijkstra> cdj;            // one workspace per host thread
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> cd_out;   // per worker: settled core labels
     uint32_t *tdist_dev = nullptr;   // device distances of iso_targets_query
     size_t tdist_cap = 0;            // its capacity in words
 };
@@ -231,7 +321,7 @@ struct iso_targets {
 // Upward searches of `lanes` queries (up to g->threads host threads) and the device inputs
 // of one sweep.  settled (optional, lanes entries) receives the upward search sizes.
 void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
-                    bool want_dist, isodev::RunArgs &A, uint32_t *settled);
+                    bool want_dist, isodev::RunArgs &A, uint32_t *settled, bool core_dijkstra = false);
 // Process-wide pool of pinned host blocks for results (device copies into pinned memory run
 // at full link speed).  pinned_get returns a block of at least `bytes` (its capacity in cap)
 // or nullptr; pinned_put takes a block back and returns false for pointers it does not own.

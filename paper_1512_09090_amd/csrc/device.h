@@ -38,6 +38,9 @@ struct RunArgs {
     size_t out_cap = 0;          // capacity of the edge-key buffer
     uint32_t table_x = 0;        // top table used: core positions [0, table_x), the first table_levels levels
     uint32_t table_levels = 0;
+    // isoPHAST-CD: the slot entries hold every core label a host search settled (no table
+    // entries); the device fills the core labels from them instead of sweeping the core levels
+    bool core_dijkstra = false;
     // vertices in range instead of edges (vbits set): per lane j < lanes, row j of ceil(n / 64)
     // words of vbits gets bit v % 64 of word v / 64 for every original id v in range; no edges
     uint64_t *vbits = nullptr;

@@ -46,7 +46,7 @@ uint32_t pow2_at_least(uint32_t x) {
 }  // namespace
 
 void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t lanes, bool plain,
-                    bool want_dist, isodev::RunArgs &A, uint32_t *settled) {
+                    bool want_dist, isodev::RunArgs &A, uint32_t *settled, bool core_dijkstra) {
     const iso::Prep &P = g->P;
     A = isodev::RunArgs();
     A.block = g->tuning.block;
@@ -67,12 +67,30 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     A.xval.assign(lanes, {});
     A.spos.assign(lanes, {});
     A.sval.assign(lanes, {});
+    A.core_dijkstra = core_dijkstra;
+    if (core_dijkstra) {   // isoPHAST-CD: the core graph and one search workspace per worker
+        if (!g->coreg) {
+            auto cg = std::make_unique<CoreGraph>();
+            cg->build(P);
+            g->coreg = std::move(cg);
+        }
+        if (g->cdj.size() < g->up.size()) {
+            g->cdj.resize(g->up.size());
+            g->cd_out.resize(g->up.size());
+        }
+    }
     {
         std::atomic<uint32_t> next{0};
-        g->D.table_cut(g->tuning.table_max, A.table_x, A.table_levels);
-        const uint32_t TX = A.table_x;   // the upward searches stop at the table's vertices
+        if (core_dijkstra) {
+            A.table_x = A.table_levels = 0;
+        } else {
+            g->D.table_cut(g->tuning.table_max, A.table_x, A.table_levels);
+        }
+        // the upward searches stop at the table's vertices, or (isoPHAST-CD) at the core
+        const uint32_t TX = core_dijkstra ? P.n_core : A.table_x;
         const std::function<void(int)> work = [&](int w) {
             std::vector<std::pair<uint32_t, uint32_t>> &U = g->up_out[w];
+            std::vector<std::pair<uint32_t, uint32_t>> seeds;
             for (;;) {
                 uint32_t j = next.fetch_add(1);
                 if (j >= lanes) break;
@@ -81,6 +99,25 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
                 auto &xp = A.xpos[j], &xv = A.xval[j], &sp = A.spos[j], &sv = A.sval[j];
                 sp.reserve(U.size());
                 sv.reserve(U.size());
+                if (core_dijkstra) {
+                    // internal vertices of the source's cell keep their upward labels; the core
+                    // vertices reached seed the core search, whose settled labels join them
+                    seeds.clear();
+                    for (const auto &pr : U) {
+                        if (pr.first < TX) {
+                            seeds.push_back(pr);
+                        } else {
+                            sp.push_back(pr.first);
+                            sv.push_back(pr.second);
+                        }
+                    }
+                    g->cdj[w].run(*g->coreg, seeds, tau[j], g->cd_out[w]);
+                    for (const auto &pr : g->cd_out[w]) {
+                        sp.push_back(pr.first);
+                        sv.push_back(pr.second);
+                    }
+                    continue;
+                }
                 for (const auto &pr : U) {
                     if (pr.first < TX) {
                         xp.push_back(pr.first);
@@ -205,8 +242,8 @@ int check_query(iso_graph *g, uint32_t s, uint32_t tau, int mode) {
     if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
     if (s >= g->P.n) return fail(ISO_EINVAL, "source out of range");
     if (tau > ISO_TAU_MAX) return fail(ISO_EINVAL, "tau must be <= 2^32 - 2");
-    if (mode != ISO_MODE_PLAIN && mode != ISO_MODE_CELLS) return fail(ISO_EINVAL, "unknown mode");
-    if (mode == ISO_MODE_CELLS && g->P.num_cells == 0) return fail(ISO_EINVAL, "cells mode needs a partition");
+    if (mode != ISO_MODE_PLAIN && mode != ISO_MODE_CELLS && mode != ISO_MODE_CD) return fail(ISO_EINVAL, "unknown mode");
+    if (mode != ISO_MODE_PLAIN && g->P.num_cells == 0) return fail(ISO_EINVAL, "cells mode needs a partition");
     if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
     return ISO_OK;
 }
@@ -484,7 +521,8 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         W->C = ctxs[i % nctx];
         W->settled.assign(W->lanes, 0);
         const double tu = now_ms();
-        build_run_args(g, src + W->b, tau + W->b, W->lanes, mode == ISO_MODE_PLAIN, false, W->A, W->settled.data());
+        build_run_args(g, src + W->b, tau + W->b, W->lanes, mode == ISO_MODE_PLAIN, false, W->A, W->settled.data(),
+                       mode == ISO_MODE_CD);
         W->A.out_cap = g->out_cap;
         g->last.t_upward_ms += now_ms() - tu;
         if (inflight.size() == nctx) {   // frees W's context
@@ -625,7 +663,7 @@ static int vertices_sweep(iso_graph *g, size_t k, const uint32_t *src, const uin
     g->last = iso_query_stats{};
     isodev::RunArgs A;
     std::vector<uint32_t> settled(k, 0);
-    build_run_args(g, src, tau, uint32_t(k), mode == ISO_MODE_PLAIN, false, A, settled.data());
+    build_run_args(g, src, tau, uint32_t(k), mode == ISO_MODE_PLAIN, false, A, settled.data(), mode == ISO_MODE_CD);
     A.out_cap = g->out_cap;
     A.vbits = bits;
     const double t1 = now_ms();
@@ -823,6 +861,7 @@ int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode, u
     if (!dist) return fail(ISO_EINVAL, "NULL output pointer");
     int r = check_query(g, source, tau, mode);
     if (r) return r;
+    if (mode == ISO_MODE_CD) return fail(ISO_EINVAL, "the core-search mode leaves core labels above tau unset");
     BusyGuard guard(g);
     if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
     g->last = iso_query_stats{};

@@ -100,7 +100,7 @@ void launcher_loop(iso_server *s) {
         f.ctx = ctx;
         f.tickets = tickets;
         build_run_args(g, src.data(), tau.data(), uint32_t(src.size()), s->cfg.mode == ISO_MODE_PLAIN, false,
-                       f.args, nullptr);
+                       f.args, nullptr, s->cfg.mode == ISO_MODE_CD);
         f.args.out_cap = s->out_cap;
         int r = g->D.launch(*ctx, f.args);
         if (r) {
@@ -190,8 +190,9 @@ int iso_server_start(iso_graph *g, const iso_server_config *cfg, iso_server **ou
     if (!g || !cfg || !out) return api_fail(ISO_EINVAL, "NULL argument");
     *out = nullptr;
     if (!g->on_device) return api_fail(ISO_EDEVICE, "graph was loaded without a device");
-    if (cfg->mode != ISO_MODE_PLAIN && cfg->mode != ISO_MODE_CELLS) return api_fail(ISO_EINVAL, "unknown mode");
-    if (cfg->mode == ISO_MODE_CELLS && g->P.num_cells == 0) return api_fail(ISO_EINVAL, "cells mode needs a partition");
+    if (cfg->mode != ISO_MODE_PLAIN && cfg->mode != ISO_MODE_CELLS && cfg->mode != ISO_MODE_CD)
+        return api_fail(ISO_EINVAL, "unknown mode");
+    if (cfg->mode != ISO_MODE_PLAIN && g->P.num_cells == 0) return api_fail(ISO_EINVAL, "cells mode needs a partition");
     uint32_t lanes = cfg->max_lanes ? cfg->max_lanes : 64;
     uint32_t inflight = cfg->max_inflight ? cfg->max_inflight : 2;
     if (lanes > isodev::MAX_LANES || inflight > 4) return api_fail(ISO_EINVAL, "max_lanes <= 64, max_inflight <= 4");

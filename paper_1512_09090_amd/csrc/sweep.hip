@@ -127,6 +127,20 @@ __global__ void k_uset_clear(uint32_t *__restrict__ uslot, const uint32_t *__res
     if (i < nu) uslot[upos[i]] = NO_SLOT;
 }
 
+// isoPHAST-CD: the core labels come from the host's core search as slot entries; the label of
+// core position v for lane j is its entry, or INF where the search did not settle v within the
+// lane's limit (the query treats it as out of range).
+__global__ void k_core_from_slots(const uint32_t *__restrict__ uslot, const uint32_t *__restrict__ uval,
+                                  uint32_t *__restrict__ dcore, uint32_t n_core, uint32_t lk) {
+    const uint64_t total = uint64_t(n_core) << lk;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint32_t v = uint32_t(t >> lk), j = uint32_t(t) & ((1u << lk) - 1u);
+        const uint32_t sl = uslot[v];
+        dcore[t] = sl != NO_SLOT ? uval[(sl << lk) + j] : INF;
+    }
+}
+
 // Cell flags of a core vertex v for the K lanes of its group (relaxed rule: d <= tau is "in",
 // d + ecc > tau is "out"): two wavefront ballots; the group's first thread stores the group's
 // K-bit slices as v's lane masks (plain stores, no atomics).  The lanes of a group are
@@ -1562,6 +1576,10 @@ int DevGraph::run(SweepCtx &C, const RunArgs &A, RunResult &R) {
 int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     HIPCHK(hipSetDevice(device));
     const uint32_t K = A.k_pow2, lk = ilog2(K);
+    if (A.core_dijkstra && (uint64_t(n_core) << lk) > 0xFFFFFF00ull) {
+        set_error("core too large for the core-search mode at this batch width");
+        return -2;
+    }
     // upward labels: per-lane lists inside the table X (CSR over lanes), the others as
     // (position, lane, label) entries for the slot table
     std::vector<uint32_t> xptr(K + 1, 0), soff(K + 1, 0);
@@ -1708,7 +1726,8 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     // arguments; with use_graph it is captured once per signature and replayed.  The cell
     // flags, the active cells and the cell sweep (three launches) follow it eagerly, so the
     // phase events of the profile sit between whole launches in both cases.
-    const bool use_graph = A.use_graph;
+    const bool cd = A.core_dijkstra;
+    const bool use_graph = A.use_graph && !cd;   // isoPHAST-CD's core part is two launches: no graph
     GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
                  A.cell_stage, A.cell_block, A.table_x, A.table_levels, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
                                  uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
@@ -1751,7 +1770,21 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     const uint32_t tx = A.table_x;
     size_t top = A.table_levels;
     const uint32_t lg = num_cells > 0 ? cell_lg : 0;
-    if (replay) {
+    if (cd) {
+        // isoPHAST-CD: core labels from the host's core search, then flags and isochrone edges
+        // of every core vertex in one pass (all labels are final)
+        nlev = top = 0;
+        if (n_core > 0) {
+            const uint64_t words = uint64_t(n_core) << lk;
+            k_core_from_slots<<<dim3(uint32_t(std::min<uint64_t>(4096, (words + 255) / 256))), dim3(256), 0, s>>>(
+                B.d_uslot, B.d_uval, B.d_dcore, n_core, lk);
+            const uint32_t entries = core_lvl_entries.back();
+            uint32_t ls = level_ls(n_core, entries, K);
+            while (ls > 0 && (uint64_t(n_core) << (lk + ls)) > 0xFFFFFF00ull) --ls;   // 32-bit thread ids
+            k_top_finish<<<dim3(uint32_t(((uint64_t(n_core) << (lk + ls)) + 255) / 256)), dim3(256), 0, s>>>(
+                CA, n_core, ls);
+        }
+    } else if (replay) {
         HIPCHK(hipGraphLaunch(C.graph_exec, s));
     } else {
         if (tx > 0) {

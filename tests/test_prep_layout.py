@@ -280,9 +280,14 @@ def test_abi_error_paths():
     with pytest.raises(iso.IsoError) as e:
         G.query(0, 0xFFFFFFFF)
     assert e.value.code == iso.ISO_EINVAL
-    with pytest.raises(iso.IsoError) as e:
-        G.query(0, 10, iso.MODE_CELLS)          # no partition
-    assert e.value.code == iso.ISO_EINVAL
+    for mode in (iso.MODE_CELLS, iso.MODE_CD, 3, -1):   # no partition; unknown modes
+        with pytest.raises(iso.IsoError) as e:
+            G.query(0, 10, mode)
+        assert e.value.code == iso.ISO_EINVAL, mode
+    Gc = iso.Graph.from_synth(g, num_cells=16, device=-1)
+    with pytest.raises(iso.IsoError) as e:      # the core-search mode needs the device as well
+        Gc.query(0, 10, iso.MODE_CD)
+    assert e.value.code == iso.ISO_EDEVICE
     with pytest.raises(iso.IsoError) as e:
         G.set_tuning(lanes_per_launch=65)
     assert e.value.code == iso.ISO_EINVAL
