@@ -155,7 +155,11 @@ struct SweepCtx {
 struct DevGraph {
     int device = -1;
     uint32_t n = 0, n_core = 0, num_cells = 0;
-    uint32_t id_bits = 29;   // bits per vertex id in an edge key: lane << 2b | tail << b | head
+    // Edge keys: lane << rank_bits | the arc's rank among all arcs ordered by (tail, head) over
+    // original ids, so that sorted keys are in (lane, tail, head) order
+    uint32_t rank_bits = 1;
+    uint2 *d_arc_rank = nullptr;   // per downward entry: ranks of its forward and reverse arcs (INF: none)
+    uint2 *d_arc_pair = nullptr;   // per rank: (tail, head), original ids
     // core levels (host copy), and prefix sums used to size the LDS top block
     std::vector<uint32_t> core_lvl;
     std::vector<uint32_t> core_lvl_entries;   // down_off at each core level boundary
@@ -184,10 +188,12 @@ struct DevGraph {
     uint32_t *d_blob = nullptr;
     uint32_t *d_cblob = nullptr;   // word offset of each cell's blob
     uint4 *d_cmeta = nullptr;      // (internal count, levels, core refs, entries)
+    uint32_t *d_cell_ebase = nullptr;   // index of each cell's first downward entry
     uint32_t max_blob_words = 0, max_cell_labels = 0, max_cell_cnt = 0, max_cell_levels = 0;
     int num_cus = 0;                                   // compute units of the device
     std::map<uint64_t, uint32_t> occ_cache;            // cell-sweep workgroups per CU by (variant, LDS)
     int cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t &per_cu);
+    int upload_arc_ranks(const iso::Prep &P);
     uint64_t bytes = 0;
     SweepCtx main;   // context of the direct query calls
     SweepCtx aux;    // second context of a batch call, so that consecutive sweeps overlap (made on first use)

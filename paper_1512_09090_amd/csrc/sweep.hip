@@ -59,21 +59,23 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
     return s < a ? INF : s;
 }
 
-__device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t tail, uint32_t head, uint32_t ib) {
-    return (uint64_t(lane) << (2 * ib)) | (uint64_t(tail) << ib) | uint64_t(head);
+// Output key of an isochrone edge: the lane above the arc's rank in (tail, head) order.
+__device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t rank, uint32_t rb) {
+    return (uint64_t(lane) << rb) | uint64_t(rank);
 }
 
-// Sorted keys -> (tail, head) pairs, and the first position of every lane: lane_off[l] = base +
-// the first i whose lane is >= l (lane_off is filled with base + the key count beforehand).
+// Sorted keys -> (tail, head) pairs (the rank's entry of arc_pair), and the first position of
+// every lane: lane_off[l] = base + the first i whose lane is >= l (lane_off is filled with
+// base + the key count beforehand).
 __global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *__restrict__ pairs,
-                         uint32_t *__restrict__ lane_off, uint32_t base, uint32_t ib) {
+                         uint32_t *__restrict__ lane_off, uint32_t base, const uint2 *__restrict__ arc_pair,
+                         uint32_t rb) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t k = keys[i];
-    const uint32_t mask = (1u << ib) - 1u;
-    pairs[i] = make_uint2(uint32_t(k >> ib) & mask, uint32_t(k) & mask);
-    const uint32_t j = uint32_t(k >> (2 * ib));
-    const uint32_t from = i ? uint32_t(keys[i - 1] >> (2 * ib)) + 1u : 0u;
+    pairs[i] = arc_pair[uint32_t(k & ((uint64_t(1) << rb) - 1u))];
+    const uint32_t j = uint32_t(k >> rb);
+    const uint32_t from = i ? uint32_t(keys[i - 1] >> rb) + 1u : 0u;
     for (uint32_t l = from; l <= j; ++l) lane_off[l] = base + i;
 }
 
@@ -165,11 +167,12 @@ struct CoreArgs {
     const uint32_t *down_off;
     const uint2 *down_arc;
     uint32_t *dcore;
-    const uint32_t *uslot, *uval, *perm, *core_cell, *core_ecc, *taus;
-    uint64_t *vin, *vout;   // per core vertex: lanes with d <= tau, lanes with d + ecc > tau
+    const uint32_t *uslot, *uval, *core_cell, *core_ecc, *taus;
+    const uint2 *arc_rank;   // per downward entry: ranks of its forward and reverse arcs
+    uint64_t *vin, *vout;    // per core vertex: lanes with d <= tau, lanes with d + ecc > tau
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk, ib;
+    uint32_t out_cap, lane_base, lk, rb;
 };
 
 // Per (vertex, lane, sub-lane): bit k of `in` / `flag` tells whether the sub-lane's k-th entry
@@ -242,36 +245,32 @@ __device__ __forceinline__ void push_key(bool pred, uint64_t key, uint64_t *s_ke
 
 // Isochrone edges at core vertex v (label dv final) for lane j: the flagged entries of this
 // sub-lane whose tails lie on the other side of tau, from the bits recorded while relaxing
-// (entry loads and perm lookups only for those); sub-lanes with more than 32 entries walk
-// theirs again.  Wavefront-uniform loops.
+// (one load of the entry's arc ranks for each, INF for a direction that is no arc);
+// sub-lanes with more than 32 entries walk theirs again.  Wavefront-uniform loops.
 template <class ARC, class LAB>
-__device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &A, bool act, uint32_t v,
-                                              uint32_t beg, uint32_t end, uint32_t sub, uint32_t S,
-                                              uint32_t j, uint32_t dv, uint32_t tau, const EntryBits &eb,
-                                              uint64_t *s_keys, uint32_t *s_n) {
+__device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &A, bool act, uint32_t beg,
+                                              uint32_t end, uint32_t sub, uint32_t S, uint32_t j, uint32_t dv,
+                                              uint32_t tau, const EntryBits &eb, uint64_t *s_keys, uint32_t *s_n) {
     const bool vin = dv <= tau;
     uint32_t st = act && !eb.over ? (eb.flag & (vin ? ~eb.in : eb.in)) : 0u;
     const bool walk = act && eb.over;
     const uint32_t lane = A.lane_base + j;
-    const uint32_t ov = (st != 0 || walk) ? A.perm[v] : 0u;
     while (__any(st != 0)) {
         const bool have = st != 0;
         const uint32_t k = have ? uint32_t(__ffs(st) - 1) : 0u;
         st &= st - 1u;
-        const uint2 a = have ? arc(beg + sub + k * S) : make_uint2(0u, 0u);
-        const uint32_t ot = have ? A.perm[a.x & TAIL_MASK] : 0u;
-        push_key(have && (a.x & FLAG_FWD), edge_key(lane, ot, ov, A.ib), s_keys, s_n, A);
-        push_key(have && (a.x & FLAG_REV), edge_key(lane, ov, ot, A.ib), s_keys, s_n, A);
+        const uint2 rk = have ? A.arc_rank[beg + sub + k * S] : make_uint2(INF, INF);
+        push_key(rk.x != INF, edge_key(lane, rk.x, A.rb), s_keys, s_n, A);
+        push_key(rk.y != INF, edge_key(lane, rk.y, A.rb), s_keys, s_n, A);
     }
     uint32_t e = walk ? beg + sub : 0, stop = walk ? end : 0;
     while (__any(e < stop)) {
         const bool have = e < stop;
         const uint2 a = have ? arc(e) : make_uint2(0u, 0u);
-        const uint32_t tl = a.x & TAIL_MASK;
-        const bool str = have && (a.x & FLAGS) && ((lab(tl) <= tau) != vin);
-        const uint32_t ot = str ? A.perm[tl] : 0u;
-        push_key(str && (a.x & FLAG_FWD), edge_key(lane, ot, ov, A.ib), s_keys, s_n, A);
-        push_key(str && (a.x & FLAG_REV), edge_key(lane, ov, ot, A.ib), s_keys, s_n, A);
+        const bool str = have && (a.x & FLAGS) && ((lab(a.x & TAIL_MASK) <= tau) != vin);
+        const uint2 rk = str ? A.arc_rank[e] : make_uint2(INF, INF);
+        push_key(rk.x != INF, edge_key(lane, rk.x, A.rb), s_keys, s_n, A);
+        push_key(rk.y != INF, edge_key(lane, rk.y, A.rb), s_keys, s_n, A);
         e += S;
     }
 }
@@ -357,7 +356,7 @@ __global__ void __launch_bounds__(256) k_top_finish(CoreArgs A, uint32_t TX, uin
     auto lab = [&](uint32_t tl) { return dc[(tl << lk) + j]; };
     EntryBits eb;
     relax_group(arc, lab, beg, end, sub, S, K, INF, tau, eb);   // the labels are final: only the bits count
-    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, eb, s_keys, &s_n);
+    extract_group(arc, lab, A, act, beg, end, sub, S, j, dv, tau, eb, s_keys, &s_n);
     keys_end(s_keys, &s_n, &s_base, A);
 }
 
@@ -389,7 +388,7 @@ __device__ __forceinline__ void core_item(const CoreArgs &A, uint32_t t, uint32_
     uint32_t dv = relax_group(arc, lab, beg, end, sub, S, K, init, tau, eb);
     if (act && sub == 0) A.dcore[(v << lk) + j] = dv;
     store_vertex_masks(act, v, cell, ecc, dv, tau, j, sub, lk, lgs, A.vin, A.vout);
-    extract_group(arc, lab, A, act, v, beg, end, sub, S, j, dv, tau, eb, s_keys, s_n);
+    extract_group(arc, lab, A, act, beg, end, sub, S, j, dv, tau, eb, s_keys, s_n);
 }
 
 // Sub-lanes per vertex for a level: enough to cover its mean in-degree, at most 8, and the
@@ -606,15 +605,16 @@ __host__ __device__ __forceinline__ uint32_t blob_words(uint32_t cnt, uint32_t n
 }
 
 struct CellArgs {
-    const uint32_t *items, *n_items, *cblob, *blob, *cell_off, *dcore, *uslot, *uval, *perm, *taus,
+    const uint32_t *items, *n_items, *cblob, *blob, *cell_off, *cell_ebase, *dcore, *uslot, *uval, *taus,
         *src_cell;
     const uint64_t *cmask;
     const uint4 *cmeta;
+    const uint2 *arc_rank;   // per downward entry: ranks of its forward and reverse arcs
     uint32_t *dist_out;
     uint64_t *vmask;   // vertex output: lane masks by position (nullptr: edges only)
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk, lg, num_cells, ib;
+    uint32_t out_cap, lane_base, lk, lg, num_cells, rb;
 };
 
 // Cell workgroups have 256 or 512 threads (the cell_block knob); the item code reads blockDim.x.
@@ -690,26 +690,23 @@ __host__ __device__ __forceinline__ uint32_t cell_lds_words(uint32_t cnt, uint32
     return ((cnt + 1 + nl + 1 + 1u) & ~1u) + 4 * CELL_BUF + (labels << lg) + CAND_CAP + 4;
 }
 
-// Output key of a candidate: head = internal vertex i, tail = the local index in i's k-th entry
-// (internal or core reference), both mapped to original ids.  q is the rank of the work item's
-// first lane among the cell's active lanes; the candidate's lane slot j is added to it.
-template <class ENT, class REF>
-__device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, const uint32_t *s_off, uint32_t cnt,
-                                             ENT ent, REF ref, uint32_t cb, uint64_t lanes, uint32_t q) {
+// Output key of a candidate: the rank of the forward (tail -> internal vertex i) or reverse
+// arc of i's k-th entry, whose downward-entry index is the cell's first entry eb plus the
+// entry's offset in the cell.  q is the rank of the work item's first lane among the cell's
+// active lanes; the candidate's lane slot j is added to it.
+__device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, const uint32_t *s_off, uint32_t eb,
+                                             uint64_t lanes, uint32_t q) {
     const uint32_t i = word & 0xFFFu, k = (word >> 12) & (CAND_K_MAX - 1u), j = (word >> 25) & 63u;
-    const uint32_t lt = ent(s_off[i] + k).x & LOCAL_MASK;
-    const uint32_t ov = A.perm[cb + i];
-    const uint32_t ot = A.perm[lt < cnt ? cb + lt : ref(lt - cnt)];
+    const uint2 rk = A.arc_rank[eb + s_off[i] + k];
     const uint32_t lane = A.lane_base + nth_set_bit(lanes, q + j);
-    return (word >> 31) ? edge_key(lane, ov, ot, A.ib) : edge_key(lane, ot, ov, A.ib);
+    return edge_key(lane, (word >> 31) ? rk.y : rk.x, A.rb);
 }
 
 // Wavefront-aggregated append of a candidate to the LDS list (count in ctl[0]); every lane of
 // the wavefront must call it.  A candidate beyond the list's capacity is written out at once.
-template <class ENT, class REF>
 __device__ __forceinline__ void push_cand(bool pred, uint32_t word, uint32_t *s_cand, uint32_t *s_ctl,
-                                          const CellArgs &A, const uint32_t *s_off, uint32_t cnt, ENT ent, REF ref,
-                                          uint32_t cb, uint64_t lanes, uint32_t q) {
+                                          const CellArgs &A, const uint32_t *s_off, uint32_t eb, uint64_t lanes,
+                                          uint32_t q) {
     const uint64_t mask = __ballot(pred);
     if (mask == 0) return;
     const uint32_t lane = __lane_id();
@@ -722,7 +719,7 @@ __device__ __forceinline__ void push_cand(bool pred, uint32_t word, uint32_t *s_
         if (k < CAND_CAP) {
             s_cand[k] = word;
         } else {
-            const uint64_t key = cand_key(A, word, s_off, cnt, ent, ref, cb, lanes, q);
+            const uint64_t key = cand_key(A, word, s_off, eb, lanes, q);
             const uint32_t idx = atomicAdd(A.out_count, 1u);
             if (idx < A.out_cap) A.out_keys[idx] = key;
         }
@@ -731,16 +728,14 @@ __device__ __forceinline__ void push_cand(bool pred, uint32_t word, uint32_t *s_
 
 // Writes the first n listed candidates with one output reservation and empties the list.
 // Called by every thread with the same n, read from ctl[0] between two barriers.
-template <class ENT, class REF>
 __device__ __forceinline__ void flush_cands(uint32_t n, uint32_t *s_cand, uint32_t *s_ctl, const CellArgs &A,
-                                            const uint32_t *s_off, uint32_t cnt, ENT ent, REF ref, uint32_t cb,
-                                            uint64_t lanes, uint32_t q) {
+                                            const uint32_t *s_off, uint32_t eb, uint64_t lanes, uint32_t q) {
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_ctl[1] = atomicAdd(A.out_count, n);
     __syncthreads();
     const uint32_t base = s_ctl[1];
     for (uint32_t k = tid; k < n; k += blockDim.x) {
-        const uint64_t key = cand_key(A, s_cand[k], s_off, cnt, ent, ref, cb, lanes, q);
+        const uint64_t key = cand_key(A, s_cand[k], s_off, eb, lanes, q);
         if (base + k < A.out_cap) A.out_keys[base + k] = key;
     }
     __syncthreads();
@@ -752,12 +747,12 @@ __device__ __forceinline__ void flush_cands(uint32_t n, uint32_t *s_cand, uint32
 // flagged entries whose tails lie on the other side of tau, from the bits recorded while
 // relaxing; a vertex with more than 32 entries walks them again (ENT gives an entry, and
 // s_lab the labels).  Candidates go to the LDS list.  Wavefront-uniform loops.
-template <class ENT, class REF>
+template <class ENT>
 __device__ __forceinline__ void emit_cell_vertex(bool go, uint32_t i, uint32_t e0, uint32_t e1, uint32_t dv,
                                                  uint32_t tau, const CellBits &b, uint32_t j, uint32_t lg,
                                                  const uint32_t *s_lab, uint32_t *s_cand, uint32_t *s_ctl,
-                                                 const CellArgs &A, const uint32_t *s_off, uint32_t cnt, ENT ent,
-                                                 REF ref, uint32_t cb, uint64_t lanes, uint32_t q) {
+                                                 const CellArgs &A, const uint32_t *s_off, ENT ent, uint32_t eb,
+                                                 uint64_t lanes, uint32_t q) {
     const bool vin = dv <= tau;
     const uint32_t str = go && !b.over ? (vin ? ~b.in : b.in) : 0u;
     uint32_t sf = str & b.fwd, sr = str & b.rev;
@@ -766,8 +761,8 @@ __device__ __forceinline__ void emit_cell_vertex(bool go, uint32_t i, uint32_t e
         const uint32_t kf = hf ? uint32_t(__ffs(sf) - 1) : 0u, kr = hr ? uint32_t(__ffs(sr) - 1) : 0u;
         sf &= sf - 1u;
         sr &= sr - 1u;
-        push_cand(hf, cand_word(i, kf, j, false), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
-        push_cand(hr, cand_word(i, kr, j, true), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        push_cand(hf, cand_word(i, kf, j, false), s_cand, s_ctl, A, s_off, eb, lanes, q);
+        push_cand(hr, cand_word(i, kr, j, true), s_cand, s_ctl, A, s_off, eb, lanes, q);
     }
     uint32_t e = go && b.over ? e0 : 0u, ee = go && b.over ? e1 : 0u;
     while (__any(e < ee)) {
@@ -775,10 +770,8 @@ __device__ __forceinline__ void emit_cell_vertex(bool go, uint32_t i, uint32_t e
         const uint2 x = have ? ent(e) : make_uint2(0u, 0u);
         const uint32_t lt = x.x & LOCAL_MASK;
         const bool st = have && (x.x & FLAGS) && ((s_lab[(lt << lg) + j] <= tau) != vin);
-        push_cand(st && (x.x & FLAG_FWD), cand_word(i, e - e0, j, false), s_cand, s_ctl, A, s_off, cnt, ent, ref,
-                  cb, lanes, q);
-        push_cand(st && (x.x & FLAG_REV), cand_word(i, e - e0, j, true), s_cand, s_ctl, A, s_off, cnt, ent, ref,
-                  cb, lanes, q);
+        push_cand(st && (x.x & FLAG_FWD), cand_word(i, e - e0, j, false), s_cand, s_ctl, A, s_off, eb, lanes, q);
+        push_cand(st && (x.x & FLAG_REV), cand_word(i, e - e0, j, true), s_cand, s_ctl, A, s_off, eb, lanes, q);
         ++e;
     }
 }
@@ -789,20 +782,19 @@ __device__ __forceinline__ void emit_cell_vertex(bool go, uint32_t i, uint32_t e
 // each level's barrier in one of two LDS words (alternating with the level's parity), and
 // every thread decides on the word written a level before, so all decide alike without a
 // second barrier.
-template <class ENT, class REF>
 __device__ __forceinline__ void level_end(uint32_t l, uint32_t nl, uint32_t *s_cand, uint32_t *s_ctl,
-                                          const CellArgs &A, const uint32_t *s_off, uint32_t cnt, ENT ent, REF ref,
-                                          uint32_t cb, uint64_t lanes, uint32_t q) {
+                                          const CellArgs &A, const uint32_t *s_off, uint32_t eb, uint64_t lanes,
+                                          uint32_t q) {
     __syncthreads();
     if (l + 1 == nl) {
         const uint32_t n = s_ctl[0];   // no candidate is added after the last level
-        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, eb, lanes, q);
         return;
     }
     const uint32_t due = l ? s_ctl[2 + ((l - 1) & 1u)] : 0u;
     if (due > CAND_CAP / 4) {
         // every thread is between this level's barrier and the flush: the count is stable
-        flush_cands(min(s_ctl[0], CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        flush_cands(min(s_ctl[0], CAND_CAP), s_cand, s_ctl, A, s_off, eb, lanes, q);
         if (threadIdx.x == 0) s_ctl[2 + (l & 1u)] = 0;
     } else if (threadIdx.x == 0) {
         s_ctl[2 + (l & 1u)] = s_ctl[0];
@@ -835,7 +827,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
     uint32_t *s_cand = s_lab + ((cnt + nrefs) << lg);                                   // CAND_CAP
     uint32_t *s_ctl = s_cand + CAND_CAP;                                                // count, base
     auto ent = [&](uint32_t e) { return gent[e]; };
-    auto ref = [&](uint32_t r) { return grefs[r]; };
+    const uint32_t eb = A.cell_ebase[c];   // the cell's first downward entry
     const uint32_t tid = threadIdx.x;
     const uint32_t G = 1u << lg;
     const uint32_t j = tid & (G - 1);             // slot within the item
@@ -845,6 +837,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
     const uint32_t tau = A.taus[jj];
     const bool has_up = A.src_cell[jj] == c;
     const uint32_t T = blockDim.x, per_iter = T >> lg;
+    const uint32_t wfirst = (tid & ~63u) >> lg;   // the first vertex slot of the thread's wavefront
     // touch the whole blob once so that the per-level loads below hit the L2 instead of HBM
     // (16-byte loads, up to eight per thread in flight; indices past the end repeat the last
     // vector); the vectors that hold the offsets and level bounds are stored to LDS, the
@@ -937,8 +930,8 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
                 if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
             }
             if (A.vmask) or_in_range(A.vmask, act, live, cb + i, dv, tau, jj, j, lg);
-            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
-                             ref, cb, lanes, q);
+            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, ent, eb,
+                             lanes, q);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
@@ -946,7 +939,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
     if (l0 == nl) {   // the whole cell fit one wavefront: write the candidates out
         __syncthreads();
         const uint32_t n = s_ctl[0];
-        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, eb, lanes, q);
         return;
     }
     if (l0) __syncthreads();
@@ -969,6 +962,10 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             }
         }
         for (uint32_t base = a; base < bnd; base += per_iter) {
+            // a wavefront with no vertex of the level left stops here (wavefront-uniform; the
+            // loop body has no workgroup barrier), so small levels and narrow items do not cost
+            // the issue slots of idle wavefronts
+            if (base + wfirst >= bnd) break;
             uint32_t i = base + (tid >> lg);
             bool act = i < bnd;
             uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
@@ -992,8 +989,8 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             if (A.vmask) or_in_range(A.vmask, act, live, cb + i, dv, tau, jj, j, lg);
             // isochrone edges at vertex i (its tails are on earlier levels or in the core) go to
             // the candidate list
-            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent,
-                             ref, cb, lanes, q);
+            emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, ent, eb,
+                             lanes, q);
         }
         if (l + 1 < nl) {
 #pragma unroll
@@ -1002,7 +999,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
                 if (k * T < CELL_BUF && idx < n1) nxt[idx] = r[k];
             }
         }
-        level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        level_end(l, nl, s_cand, s_ctl, A, s_off, eb, lanes, q);
     }
 }
 
@@ -1085,10 +1082,9 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
     __syncthreads();
     const uint32_t *s_off = smem;
     const uint32_t *s_lvl = smem + cnt + 1;
-    const uint32_t *s_refs = smem + cnt + 1 + nl + 1;
     const uint2 *s_ent = reinterpret_cast<const uint2 *>(smem + blob_head_words(cnt, nl, nrefs));
     auto ent = [&](uint32_t e) { return s_ent[e]; };
-    auto ref = [&](uint32_t r) { return s_refs[r]; };
+    const uint32_t eb = A.cell_ebase[c];   // the cell's first downward entry
     // one vertex (slot i of the current level) for the thread's lane slot
     auto sweep_vertex = [&](uint32_t i, bool act) {
         uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
@@ -1113,8 +1109,8 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
             if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << lk) + jj] = dv;
         }
         if (A.vmask) or_in_range(A.vmask, act, live, cb + i, dv, tau, jj, j, lg);
-        emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, cnt, ent, ref,
-                         cb, lanes, q);
+        emit_cell_vertex(act && live, i, e0, e1, dv, tau, bits, j, lg, s_lab, s_cand, s_ctl, A, s_off, ent, eb,
+                         lanes, q);
     };
     // The sweep starts with the top of the cell's hierarchy, where levels hold a few vertices:
     // while a level fits the vertex slots of one wavefront, wavefront 0 sweeps it alone, and its
@@ -1134,7 +1130,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
     if (l0 == nl) {   // the whole cell fit one wavefront: write the candidates out
         __syncthreads();
         const uint32_t n = s_ctl[0];
-        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        if (n) flush_cands(min(n, CAND_CAP), s_cand, s_ctl, A, s_off, eb, lanes, q);
         return;
     }
     if (l0) __syncthreads();
@@ -1144,7 +1140,7 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
             const uint32_t i = base + (tid >> lg);
             sweep_vertex(i, i < bnd);
         }
-        level_end(l, nl, s_cand, s_ctl, A, s_off, cnt, ent, ref, cb, lanes, q);
+        level_end(l, nl, s_cand, s_ctl, A, s_off, eb, lanes, q);
     }
 }
 
@@ -1312,13 +1308,65 @@ int DevGraph::cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t
     return 0;
 }
 
+// Output keys of isochrone edges.  Every arc of the input is flagged on exactly one downward
+// entry: forward (the entry's tail -> the entry's vertex) or reverse.  The arcs are ranked by
+// (tail, head) over original ids (a counting sort by tail, then each tail's few heads sorted);
+// an edge key is lane << rank_bits | rank, so sorted keys come out in (lane, tail, head) order
+// with fewer bits than two vertex ids take, and decoding a key is one lookup in the rank's
+// (tail, head) table.  Per entry the device keeps the ranks of its two arcs (INF: no arc).
+int DevGraph::upload_arc_ranks(const iso::Prep &P) {
+    const uint64_t E = P.down_off[n];
+    std::vector<uint32_t> start(size_t(n) + 2, 0);
+    for (uint32_t v = 0; v < n; ++v)
+        for (uint64_t e = P.down_off[v]; e < P.down_off[v + 1]; ++e) {
+            const uint32_t x = P.down_arc[2 * e], t = x & TAIL_MASK;
+            if (x & FLAG_FWD) ++start[size_t(P.perm[t]) + 2];
+            if (x & FLAG_REV) ++start[size_t(P.perm[v]) + 2];
+        }
+    for (size_t i = 2; i < start.size(); ++i) start[i] += start[i - 1];
+    const uint64_t M = start[size_t(n) + 1];
+    if (M >= INF || E >= INF) {
+        set_error("too many arcs for 32-bit arc ranks");
+        return -1;
+    }
+    // bucket by original tail: (head << 33 | entry << 1 | reverse), then sort each bucket
+    std::vector<uint64_t> arcs(std::max<uint64_t>(1, M));
+    for (uint32_t v = 0; v < n; ++v)
+        for (uint64_t e = P.down_off[v]; e < P.down_off[v + 1]; ++e) {
+            const uint32_t x = P.down_arc[2 * e], t = x & TAIL_MASK;
+            const uint32_t ot = P.perm[t], ov = P.perm[v];
+            if (x & FLAG_FWD) arcs[start[size_t(ot) + 1]++] = (uint64_t(ov) << 33) | (e << 1);
+            if (x & FLAG_REV) arcs[start[size_t(ov) + 1]++] = (uint64_t(ot) << 33) | (e << 1) | 1u;
+        }
+    std::vector<uint2> rank(std::max<uint64_t>(1, E), make_uint2(INF, INF));
+    std::vector<uint2> pair(std::max<uint64_t>(1, M));
+    for (uint32_t u = 0; u < n; ++u) {
+        const uint32_t a = start[u], b = start[size_t(u) + 1];
+        std::sort(arcs.begin() + a, arcs.begin() + b);
+        for (uint32_t r = a; r < b; ++r) {
+            const uint64_t w = arcs[r];
+            const uint64_t e = (w >> 1) & ((uint64_t(1) << 32) - 1u);
+            if (w & 1u) rank[e].y = r;
+            else rank[e].x = r;
+            pair[r] = make_uint2(u, uint32_t(w >> 33));
+        }
+    }
+    rank_bits = 1;
+    while ((uint64_t(1) << rank_bits) < M) ++rank_bits;
+    std::vector<uint32_t> ebase(std::max<uint32_t>(1, num_cells), 0);
+    for (uint32_t c = 0; c < num_cells; ++c) ebase[c] = P.down_off[P.cell_off[c]];
+    int r;
+    if ((r = dev_alloc_copy(&d_arc_rank, rank, bytes))) return r;
+    if ((r = dev_alloc_copy(&d_arc_pair, pair, bytes))) return r;
+    if ((r = dev_alloc_copy(&d_cell_ebase, ebase, bytes))) return r;
+    return 0;
+}
+
 int DevGraph::upload(const iso::Prep &P, int device_) {
     device = device_;
     HIPCHK(hipSetDevice(device));
     n = P.n;
     n_core = P.n_core;
-    id_bits = 1;   // bits of a vertex id in an edge key (n < 2^29)
-    while (id_bits < 29 && (uint64_t(1) << id_bits) < uint64_t(n)) ++id_bits;
     num_cells = P.num_cells;
     core_lvl = P.core_lvl;
     core_lvl_entries.resize(core_lvl.size());
@@ -1489,6 +1537,7 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_blob, blob, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cblob, cblob, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cmeta, cmeta, bytes))) return r;
+    if ((r = upload_arc_ranks(P))) return r;
     max_cell_levels = 0;
     for (uint32_t c = 0; c < num_cells; ++c) max_cell_levels = std::max(max_cell_levels, uint32_t(cmeta[c].y));
     HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1532,8 +1581,9 @@ void DevGraph::release() {
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
-                    d_table, d_blob, d_cblob, d_cmeta};
+                    d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair};
     for (void *p : ptrs) if (p) hipFree(p);
+    (void)hipGetLastError();   // a failed free must not surface in another handle's next check
     device = -1;
 }
 
@@ -1719,8 +1769,8 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     uint32_t *out_count = B.d_counters, *n_items = B.d_counters + 2;
     uint64_t *d_cmask = reinterpret_cast<uint64_t *>(B.d_list);
     uint32_t *d_clist = B.d_list + 2 * size_t(num_cells), *d_items = d_clist + num_cells;
-    CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_perm, d_core_cell, d_core_ecc,
-                d_taus, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, id_bits};
+    CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_core_cell, d_core_ecc, d_taus,
+                d_arc_rank, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, rank_bits};
     const bool prof_on = C.prof.on;
     // the core sweep (table and core levels, one launch per level) has only per-context kernel
     // arguments; with use_graph it is captured once per signature and replayed.  The cell
@@ -1840,9 +1890,10 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         if (vmode)   // internal positions: the cells left out because they lie wholly in range
             k_vmask_cells<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(B.d_cin, d_cmask, d_cell_off, num_cells,
                                                                            B.d_vmask);
-        CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, B.d_dcore, B.d_uslot, B.d_uval, d_perm,
-                    d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr, vmode ? B.d_vmask : nullptr,
-                    B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg, num_cells, id_bits};
+        CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot, B.d_uval,
+                    d_taus, d_src, d_cmask, d_cmeta, d_arc_rank, A.want_dist ? B.d_dist : nullptr,
+                    vmode ? B.d_vmask : nullptr, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg, num_cells,
+                    rank_bits};
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
         if (staged)
             k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
@@ -1885,12 +1936,12 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     return 0;
 }
 
-// Radix sort of a finished sweep's keys into d_keys_sorted (lane bits above 58, then tail,
-// then head); records the profile's sort-start event.
+// Radix sort of a finished sweep's keys into d_keys_sorted (the lane above the arc rank, so
+// the order is lane, tail, head); records the profile's sort-start event.
 int DevGraph::sort_keys(SweepCtx &C, uint32_t cnt_all) {
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
-    int end_bit = 2 * int(id_bits) + int(ilog2(std::max<uint32_t>(1, C.lane_base + C.K)));
+    int end_bit = int(rank_bits) + int(ilog2(std::max<uint32_t>(1, C.lane_base + C.K)));
     if (end_bit > 64) end_bit = 64;
     size_t tmp = 0;
     int r;
@@ -1973,7 +2024,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
             if (r) return r;
             k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(
                 B.d_keys_sorted, cnt_all, reinterpret_cast<uint2 *>(R.dev_pairs) + R.dev_base, R.dev_off,
-                R.dev_base, id_bits);
+                R.dev_base, d_arc_pair, rank_bits);
             if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
         }
         HIPCHK(hipStreamSynchronize(s));
@@ -1985,7 +2036,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         R.t_result_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tr0).count();
         return 0;
     }
-    // sort the keys (lane bits above 58, then tail, then head), decode them into (tail, head)
+    // sort the keys (lane, then arc rank: tail, then head), decode them into (tail, head)
     // pairs and lane starts on the device, copy both back
     R.lane_off.assign(size_t(K) + 1, 0);
     if (cnt_all) {
@@ -1995,7 +2046,7 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         // the pairs overwrite the unsorted keys (same size)
         k_decode<<<dim3((cnt_all + 255) / 256), dim3(256), 0, s>>>(B.d_keys_sorted, cnt_all,
                                                                     reinterpret_cast<uint2 *>(B.d_keys),
-                                                                    B.d_lane_off, 0u, id_bits);
+                                                                    B.d_lane_off, 0u, d_arc_pair, rank_bits);
         if (prof.on) HIPCHK(hipEventRecord(prof.ev[5], s));
         uint32_t *dst = nullptr;
         if (R.sink) {

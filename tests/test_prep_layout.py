@@ -298,6 +298,35 @@ def test_abi_error_paths():
         assert e.value.code == iso.ISO_EINVAL, bad
 
 
+@pytest.mark.parametrize("kind", ["grid_cells", "random_cells", "oneway_cells", "oneway_plain"])
+def test_every_arc_flagged_on_exactly_one_entry(kind):
+    """The downward entries' arc flags (Section 5: original-arc flags, dummy entries) name every
+    arc of the input exactly once, forward or reverse; isochrone-edge keys rank arcs through
+    these flags, so a missing or repeated arc would drop or duplicate an output edge."""
+    if kind == "grid_cells":
+        g = synth.config_graph("grid64")
+        G = iso.Graph.from_synth(g, num_cells=16, device=-1)
+    elif kind == "random_cells":
+        g = synth.random_digraph(300, 900, seed=701, wmax=40, zero_frac=0.1)
+        cells = np.random.default_rng(1).integers(0, 5, size=g.n).astype(np.uint32)
+        G = iso.Graph(g.n, g.tail, g.head, g.w, cell_of=cells, num_cells=5, device=-1)
+    else:
+        g = synth.road_graph(20_000, 32, oneway_frac=0.3)
+        G = iso.Graph.from_synth(g, num_cells=64 if kind == "oneway_cells" else 0, device=-1)
+    L = G.layout()
+    perm = L["perm"].astype(np.int64)
+    off = L["down_off"].astype(np.int64)
+    x = L["down_arc"][:, 0].astype(np.int64)
+    v = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    t = x & 0x3FFFFFFF
+    f, r = (x & 0x80000000) != 0, (x & 0x40000000) != 0
+    flagged = np.concatenate([perm[t[f]] << 32 | perm[v[f]], perm[v[r]] << 32 | perm[t[r]]])
+    loops = g.tail == g.head
+    want = np.unique(g.tail[~loops].astype(np.int64) << 32 | g.head[~loops].astype(np.int64))
+    assert len(flagged) == len(want)
+    np.testing.assert_array_equal(np.sort(flagged), want)
+
+
 def test_parallel_arcs_and_self_loops_are_merged():
     tail = np.array([0, 0, 0, 1, 1, 2], dtype=np.uint32)
     head = np.array([1, 1, 0, 2, 2, 0], dtype=np.uint32)
