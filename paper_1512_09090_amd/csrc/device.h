@@ -24,6 +24,9 @@ constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item 
 
 struct TargetSet;
 
+// Resident cell workgroups per CU for sweeps that overlap on two streams.
+constexpr uint32_t OVERLAP_CELL_PER_CU = 2;
+
 struct RunArgs {
     uint32_t lanes = 1;          // real queries in this launch (<= k_pow2)
     uint32_t k_pow2 = 1;         // label row width (power of two >= lanes)
@@ -33,6 +36,9 @@ struct RunArgs {
     uint32_t cell_stage = 0;         // 1: whole cell staged in LDS
     uint32_t cell_block = 512;       // threads per cell workgroup
     size_t cell_lds_bytes = 40 * 1024;
+    // resident cell workgroups per CU (0: as many as fit).  A sweep that overlaps another
+    // sweep's kernels runs faster with fewer (measured: 2 of 3 on road18m), one alone with all.
+    uint32_t cell_per_cu = 0;
     bool mode_plain = true;
     bool want_dist = false;
     size_t out_cap = 0;          // capacity of the edge-key buffer

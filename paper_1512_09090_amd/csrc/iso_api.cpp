@@ -524,6 +524,7 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         build_run_args(g, src + W->b, tau + W->b, W->lanes, mode == ISO_MODE_PLAIN, false, W->A, W->settled.data(),
                        mode == ISO_MODE_CD);
         W->A.out_cap = g->out_cap;
+        if (overlap) W->A.cell_per_cu = isodev::OVERLAP_CELL_PER_CU;   // the sweeps share the GPU
         g->last.t_upward_ms += now_ms() - tu;
         if (inflight.size() == nctx) {   // frees W's context
             int r = collect(*inflight.front());

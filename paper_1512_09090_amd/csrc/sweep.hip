@@ -1147,9 +1147,11 @@ __device__ __forceinline__ void cell_item_staged(const CellArgs &A, uint32_t *sm
 // The cell sweep: a grid of resident workgroups walks the work items.  XCD x (block index
 // = x mod 8) takes the x-th eighth of the item list, so the items of one cell, which are
 // consecutive, run on the same XCD and share its L2; its workgroups stride through that
-// range.  No workgroup waits for another.
+// range.  No workgroup waits for another.  At least 6 wavefronts per SIMD (at most 80 VGPRs),
+// so that three 512-thread workgroups fit a CU when the LDS of a work item allows it.
 template <bool STAGED>
-__global__ void __launch_bounds__(CELL_THREADS_MAX) k_cell_sweep(CellArgs A) {
+__global__ void __launch_bounds__(CELL_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(6)))
+k_cell_sweep(CellArgs A) {
     extern __shared__ uint32_t smem[];
     const uint32_t total = *A.n_items;
     const uint32_t rows = (total + 7u) >> 3;
@@ -1804,6 +1806,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         }
         uint32_t per_cu = 0;
         if ((r = cell_occupancy(staged, A.cell_block, lds, per_cu))) return r;
+        if (A.cell_per_cu) per_cu = std::min(per_cu, A.cell_per_cu);
         uint64_t most = uint64_t(num_cells) << (lk - cell_lg);
         uint64_t want = std::min<uint64_t>(uint64_t(per_cu) * uint64_t(std::max(1, num_cus)), most);
         cell_grid = uint32_t(std::max<uint64_t>(8, (want + 7) / 8 * 8));
