@@ -270,6 +270,10 @@ typedef struct {
                                    16384; 1 = no table (every core level is its own launch and the upward
                                    search runs to its end); 2..16384, capped at the table built at load
                                    (iso_graph_info top_table) */
+    uint32_t stall;             /* 1 = stall-on-demand in the upward search (Section 2, CH): a reached vertex
+                                   with a shorter path through a downward arc from a reached higher vertex
+                                   is neither expanded nor handed to the sweep (default); 0 = off.  The
+                                   answer is the same either way */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);

@@ -29,7 +29,7 @@ SPACE = {
     "table_max": [0, 1024, 4096, 8192],
 }
 DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 0, "cell_block": 0,
-           "table_max": 0}
+           "table_max": 0, "stall": 1}
 
 
 def measure(G: Graph, sources, taus, mode=MODE_CELLS, repeats: int = 2) -> float:

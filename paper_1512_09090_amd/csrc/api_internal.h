@@ -80,6 +80,14 @@ struct UpwardSearch {
         for (auto &kv : keep) *slot(kv.first) = kv.second;
     }
     static uint32_t hash(uint32_t v) { return (v * 0x9E3779B1u) ^ (v >> 15); }
+    uint32_t find(uint32_t v) const {   // label of v, INF if absent
+        uint32_t h = hash(v) & mask;
+        while (key[h] != EMPTY) {
+            if (key[h] == v) return val[h];
+            h = (h + 1) & mask;
+        }
+        return iso::INF;
+    }
     uint32_t *slot(uint32_t v) {   // label slot of v (inserted with INF if absent)
         uint32_t h = hash(v) & mask;
         while (key[h] != EMPTY && key[h] != v) h = (h + 1) & mask;
@@ -99,8 +107,14 @@ struct UpwardSearch {
     // out: (position, label) pairs sorted by position; returns the number of reached vertices.
     // Vertices at positions below `stop` (the top-of-hierarchy table) are recorded but not
     // expanded: the table covers every path continuing inside that set.
+    // With `down` given, stall-on-demand (a standard CH search pruning, Section 2): a vertex u
+    // with a downward entry from a reached higher vertex v such that label(v) + length < label(u)
+    // is neither recorded nor expanded.  Then d(s, u) < label(u), so u lies on the upward part of
+    // no shortest up-down path, and the downward sweep gives u its distance through that entry.
+    // label(v) may still fall later (positions are processed bottom-up), which only makes the
+    // test more conservative.
     uint32_t run(const UpwardGraph &G, uint32_t src_pos, std::vector<std::pair<uint32_t, uint32_t>> &out,
-                 uint32_t stop = 0) {
+                 uint32_t stop = 0, const iso::Prep *down = nullptr) {
         for (uint32_t s : used) { key[s] = EMPTY; val[s] = iso::INF; }
         used.clear();
         out.clear();
@@ -117,8 +131,18 @@ struct UpwardSearch {
                     uint32_t u = uint32_t(wi * 64 + b);
                     bits[wi] &= ~(1ull << b);
                     uint32_t du = *slot(u);
-                    out.push_back({u, du});
                     ++settled;
+                    if (down && du != 0) {
+                        bool stalled = false;
+                        for (uint32_t e = down->down_off[u]; e < down->down_off[u + 1] && !stalled; ++e) {
+                            const uint32_t w = down->down_arc[2 * uint64_t(e) + 1];
+                            if (w == iso::INF) continue;   // a dummy entry (reverse arc only)
+                            const uint32_t dv = find(down->down_arc[2 * uint64_t(e)] & iso::TAIL_MASK);
+                            stalled = dv != iso::INF && iso::sat_add(dv, w) < du;
+                        }
+                        if (stalled) continue;
+                    }
+                    out.push_back({u, du});
                     if (u < stop) continue;
                     auto relax = [&](uint64_t a) {
                         uint32_t x = uint32_t(a >> 32);
@@ -297,7 +321,7 @@ struct iso_graph {
     int threads = 1;
     std::atomic<bool> busy{false};
     iso_query_stats last{};
-    iso_tuning tuning{64, 256, 64, 1, 0, 0, 0, 0};   // the autotuner's choice on an 18M-vertex road graph
+    iso_tuning tuning{64, 256, 64, 1, 0, 0, 0, 0, 1};   // the autotuner's choice on an 18M-vertex road graph
     UpwardGraph upg;                // packed upward graph
     std::vector<UpwardSearch> up;   // one workspace per host thread
     std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep

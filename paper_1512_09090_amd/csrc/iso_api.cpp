@@ -94,7 +94,7 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
             for (;;) {
                 uint32_t j = next.fetch_add(1);
                 if (j >= lanes) break;
-                uint32_t st = g->up[w].run(g->upg, P.pos[src[j]], U, TX);
+                uint32_t st = g->up[w].run(g->upg, P.pos[src[j]], U, TX, g->tuning.stall ? &P : nullptr);
                 if (settled) settled[j] = st;
                 auto &xp = A.xpos[j], &xv = A.xval[j], &sp = A.spos[j], &sv = A.sval[j];
                 sp.reserve(U.size());
@@ -961,6 +961,7 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (t->cell_block != 0 && t->cell_block != 256 && t->cell_block != 512)
         return fail(ISO_EINVAL, "cell_block must be 0, 256 or 512");
     if (t->table_max > isodev::TABLE_MAX) return fail(ISO_EINVAL, "table_max must be at most 16384");
+    if (t->stall > 1) return fail(ISO_EINVAL, "stall must be 0 or 1");
     if (t->core_mode != 0)
         return fail(ISO_EINVAL, "core_mode must be 0: the single-launch core sweep with a grid barrier "
                                 "is disabled");

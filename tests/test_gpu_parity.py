@@ -266,6 +266,34 @@ def _identical_across_tuning(road50k, combos):
         np.testing.assert_array_equal(ref[j], want)
 
 
+def test_stall_on_demand_changes_nothing(road50k):
+    """Stall-on-demand in the upward search drops vertices from the upward labels; edges, exact
+    distances and vertices in range stay the same in every mode, in batches and singly."""
+    g, orc, G = road50k
+    src, tau = synth.batch_queries(g.n, 70, seed=91, lo_min=1, hi_min=150)
+    out = {}
+    try:
+        for stall in (0, 1):
+            G.set_tuning(stall=stall)
+            for mode in (iso.MODE_PLAIN, iso.MODE_CELLS, iso.MODE_CD):
+                say(f"stall={stall} mode={mode}: batch of 70")
+                out[stall, mode] = G.query_batch(src, tau, mode)
+            out[stall, "dist"] = [G.distances(int(src[j]), int(tau[j]), iso.MODE_PLAIN)[0] for j in (0, 33)]
+            out[stall, "vert"] = G.query_vertices(int(src[5]), int(tau[5]), iso.MODE_CELLS)
+    finally:
+        G.set_tuning()
+    for mode in (iso.MODE_PLAIN, iso.MODE_CELLS, iso.MODE_CD):
+        for j in range(len(src)):
+            np.testing.assert_array_equal(out[1, mode][j], out[0, mode][j], err_msg=f"mode {mode} lane {j}")
+    for a, b, j in zip(out[1, "dist"], out[0, "dist"], (0, 33)):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, clamp_u32(orc.distances(int(src[j]))))
+    np.testing.assert_array_equal(out[1, "vert"], orc.in_range(int(src[5]), int(tau[5])))
+    for j in (0, 64, 69):
+        want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
+        np.testing.assert_array_equal(out[1, iso.MODE_CELLS][j], want)
+
+
 def test_results_identical_across_tuning(road50k):
     """Block size, LDS budget per cell workgroup and lanes per launch change only the schedule."""
     _identical_across_tuning(road50k, ((64, 16, 8, 0, 0), (1024, 160, 24, 0, 0), (256, 64, 3, 0, 1),
