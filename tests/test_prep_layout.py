@@ -327,6 +327,80 @@ def test_every_arc_flagged_on_exactly_one_entry(kind):
     np.testing.assert_array_equal(np.sort(flagged), want)
 
 
+def _core_search(L, s_pos, tau):
+    """The isoPHAST-CD reading, written out plainly on the layout: an upward search from s that does
+    not expand core vertices, then a tau-bounded Dijkstra over the core hierarchy (upward arcs and
+    finite downward entries turned around) from the core vertices it reached."""
+    import heapq
+    nc, INF = int(L["n_core"]), 0xFFFFFFFF
+    up_off, up_head, up_w = L["up_off"], L["up_head"], L["up_w"]
+    d, pq, done = {s_pos: 0}, [(0, s_pos)], set()
+    while pq:
+        du, u = heapq.heappop(pq)
+        if u in done or du != d[u]:
+            continue
+        done.add(u)
+        if u < nc:
+            continue
+        for e in range(int(up_off[u]), int(up_off[u + 1])):
+            x, nd = int(up_head[e]), min(INF, du + int(up_w[e]))
+            if nd < d.get(x, INF):
+                d[x] = nd
+                heapq.heappush(pq, (nd, x))
+    adj = {}
+    for x in range(nc):
+        for e in range(int(up_off[x]), int(up_off[x + 1])):
+            adj.setdefault(x, []).append((int(up_head[e]), int(up_w[e])))
+    off, arc = L["down_off"], L["down_arc"]
+    for v in range(nc):
+        for e in range(int(off[v]), int(off[v + 1])):
+            t, w = int(arc[e, 0]) & 0x3FFFFFFF, int(arc[e, 1])
+            if w != INF:
+                adj.setdefault(t, []).append((v, w))
+    lab = {u: du for u, du in d.items() if u < nc}
+    pq, settled = [(du, u) for u, du in lab.items()], {}
+    heapq.heapify(pq)
+    while pq and pq[0][0] <= tau:
+        du, u = heapq.heappop(pq)
+        if u in settled or du != lab[u]:
+            continue
+        settled[u] = du
+        for x, w in adj.get(u, ()):
+            nd = min(INF, du + w)
+            if nd < lab.get(x, INF):
+                lab[x] = nd
+                heapq.heappush(pq, (nd, x))
+    return settled
+
+
+@pytest.mark.parametrize("kind", ["grid", "random"])
+def test_core_hierarchy_search_settles_the_core_in_range(kind):
+    """isoPHAST-CD runs isoDijkstra on the core (Section 5); here the core is itself contracted, and a
+    search on its hierarchy must settle exactly the core vertices the oracle puts in range, with the
+    oracle's distances (the reading the GPU mode relies on)."""
+    from oracle import Oracle
+    if kind == "grid":
+        g = synth.config_graph("grid64")
+        G = iso.Graph.from_synth(g, num_cells=16, device=-1)
+        sources, taus = [0, 2080, 4095], [0, 150, 2000, 7000]
+    else:
+        g = synth.random_digraph(300, 900, seed=1701, wmax=40, zero_frac=0.1)
+        cells = np.random.default_rng(3).integers(0, 6, size=g.n).astype(np.uint32)
+        G = iso.Graph(g.n, g.tail, g.head, g.w, cell_of=cells, num_cells=6, device=-1)
+        sources, taus = [0, 77, 299], [0, 20, 60, 10_000]
+    L = G.layout()
+    perm = L["perm"]
+    pos = np.empty_like(perm)
+    pos[perm] = np.arange(len(perm), dtype=perm.dtype)
+    orc = Oracle.from_graph(g)
+    for s in sources:
+        full = orc.distances(s)
+        for tau in taus:
+            got = _core_search(L, int(pos[s]), tau)
+            want = {p: int(full[perm[p]]) for p in range(int(L["n_core"])) if full[perm[p]] <= tau}
+            assert got == want, (s, tau)
+
+
 def test_parallel_arcs_and_self_loops_are_merged():
     tail = np.array([0, 0, 0, 1, 1, 2], dtype=np.uint32)
     head = np.array([1, 1, 0, 2, 2, 0], dtype=np.uint32)
