@@ -866,15 +866,16 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
         }
     }
     if (tid == 0) s_ctl[0] = s_ctl[2] = s_ctl[3] = 0;
-    // labels: internal vertices start at INF (upward labels only in a source's cell) ...
-    for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
-        uint32_t val = INF;
-        if (has_up) {
+    // labels: internal vertices start at INF, or at their upward labels for a lane whose source
+    // lies in the cell.  An internal vertex's slot is first read at its own level (its tails lie on
+    // earlier levels or in the core), so only such lanes fill theirs here; the others take INF there.
+    if (has_up)
+        for (uint32_t i = tid >> lg; i < cnt; i += per_iter) {
+            uint32_t val = INF;
             uint32_t s = A.uslot[cb + i];
             if (s != NO_SLOT) val = A.uval[(s << lk) + jj];
+            s_lab[(i << lg) + j] = val;
         }
-        s_lab[(i << lg) + j] = val;
-    }
     // ... referenced core vertices take their final core labels (loads issued four at a time)
     for (uint32_t r0 = tid >> lg; r0 < nrefs; r0 += 4 * per_iter) {
         uint32_t rr[4], vv[4];
@@ -922,7 +923,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             const uint32_t i = s_lvl[l] + (tid >> lg);
             const bool act = i < s_lvl[l + 1];
             const uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
-            uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
+            uint32_t dv = act && has_up ? s_lab[(i << lg) + j] : INF;
             CellBits bits;
             relax_cell_vertex(e0, e1, dv, bits, tau, s_lab, lg, j, [&](uint32_t e) { return s_buf[e - eb0]; });
             if (act) {
@@ -969,7 +970,7 @@ __device__ __forceinline__ void cell_item_pipelined(const CellArgs &A, uint32_t 
             uint32_t i = base + (tid >> lg);
             bool act = i < bnd;
             uint32_t e0 = act ? s_off[i] : 0, e1 = act ? s_off[i + 1] : 0;
-            uint32_t dv = act ? s_lab[(i << lg) + j] : INF;
+            uint32_t dv = act && has_up ? s_lab[(i << lg) + j] : INF;
             CellBits bits;
             if (in_buf) {
                 // the level's entries are all in the LDS buffer: no global load here, so the
