@@ -171,7 +171,7 @@ struct DevGraph {
     std::vector<uint32_t> core_lvl_entries;   // down_off at each core level boundary
     uint32_t *d_down_off = nullptr;
     uint2 *d_down_arc = nullptr;
-    uint32_t *d_perm = nullptr, *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
+    uint32_t *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
     uint32_t *d_pos = nullptr;   // original id -> position (vertex output)
     // top-of-hierarchy table: X = core positions [0, TX) covering the first nlev_table levels;
     // d_table[y * TX + x] = shortest downward path y -> x inside X

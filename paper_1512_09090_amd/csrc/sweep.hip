@@ -1381,7 +1381,6 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_down_off, coff, bytes))) return r;
     if ((r = dev_alloc_copy((uint32_t **)&d_down_arc, P.down_arc.data(), 2 * size_t(P.down_off[n_core]), bytes)))
         return r;
-    if ((r = dev_alloc_copy(&d_perm, P.perm, bytes))) return r;
     if ((r = dev_alloc_copy(&d_pos, P.pos, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_cell, P.core_cell, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_ecc, P.core_ecc, bytes))) return r;
@@ -1582,7 +1581,7 @@ void DevGraph::release() {
     if (aux_ready) aux.release();
     aux_ready = false;
     hipSetDevice(device);
-    void *ptrs[] = {d_down_off, d_down_arc, d_perm, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
+    void *ptrs[] = {d_down_off, d_down_arc, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
                     d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair};
     for (void *p : ptrs) if (p) hipFree(p);
