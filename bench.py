@@ -104,7 +104,7 @@ class DeviceBatches:
             return self.G.query_batch_device(src, tau, mode, self.pairs, self.offsets[:k + 1])
 
 
-def serving(G, n, rates, duration, lanes, inflight):
+def serving(G, n, rates, duration, lanes, inflight, warm=1.0):
     """Poisson arrivals at each offered rate through the continuous-batching server
     (iso_server_*): submit at the trace's arrival times, collect every result, report the
     completed rate and the per-request latency (submit to result ready) p50/p99."""
@@ -114,7 +114,6 @@ def serving(G, n, rates, duration, lanes, inflight):
     import synth
 
     out = []
-    warm = 0.5
     for rate in rates:
         t, src, tau = synth.serving_trace(n, rate, duration + warm, seed=15)
         srv = iso.Server(G, max_lanes=lanes, max_inflight=inflight, mode=iso.MODE_CELLS)
@@ -136,21 +135,26 @@ def serving(G, n, rates, duration, lanes, inflight):
         th = threading.Thread(target=collect)
         th.start()
         t0 = time.perf_counter()
+        backlog = 0
         try:
             for i in range(len(t)):
                 dt = t0 + t[i] - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
                 q.put((srv.submit(int(src[i]), int(tau[i])), t[i] >= warm))
+            t_sub = time.perf_counter() - t0
+            backlog = srv.stats()["queue_depth"]   # requests still waiting for a sweep when the trace ends
         finally:
             q.put(None)
             th.join()
             stats = srv.stats()
             srv.close()
         span = max(done_at[0] - (t0 + warm), 1e-9)
-        r = {"offered_hz": rate, "requests": len(lat), "completed_qps": round(len(lat) / span, 1),
+        r = {"offered_hz": rate, "submitted_hz": round((len(t) - int(np.sum(t < warm))) / max(t_sub - warm, 1e-9), 1),
+             "requests": len(lat), "completed_qps": round(len(lat) / span, 1),
              "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
-             "mean_batch": round(float(np.mean(batch)), 2), "sweeps": stats["sweeps"]}
+             "mean_batch": round(float(np.mean(batch)), 2), "sweeps": stats["sweeps"],
+             "backlog_at_end": int(backlog)}
         log(f"serving {r}")
         out.append(r)
     return out
@@ -203,10 +207,83 @@ def measured_traffic(phase):
     return int(v) if v else None
 
 
+def host_cores():
+    """CPUs this process may run on: the affinity mask, capped by a cgroup CPU quota."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max" and int(period) > 0:
+            n = min(n, max(1, -(-int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The two kernels that take most of a step's device time, with HIP events around their launches
+# on the sweep's stream: the cell sweep (one launch per sweep; events around that launch alone)
+# and the core levels below the top table (one launch per level; events around the level
+# launches).  Bytes: the survey's algorithmic count (the graph stream at 8 bytes per entry plus
+# offsets, and per query every label written once and read back once, also those kept in LDS),
+# and the bytes that must come from or go to HBM (for the cell sweep: each swept cell's data
+# once, the referenced core labels once per query; the core levels keep every label in HBM, so
+# both counts agree there).
+KERNELS = {"cell_sweep": ("k_cell_chunks", "cell_ms", "cell_launches", "cell_bytes_survey", "cell_bytes"),
+           "core_levels": ("k_core_level64", "level_ms", "level_launches", "level_bytes", "level_bytes")}
+
+
+def roofline_of(prof, prof_iso, steps):
+    def entry(p, key):
+        name, t, n, b_survey, b_hbm = KERNELS[key]
+        ms, launches = p[t], max(1, p[n])
+        if ms <= 0:
+            return None
+        per = ms / launches
+        ach, ach_hbm = p[b_survey] / launches / 1e9 / (per / 1e3), p[b_hbm] / launches / 1e9 / (per / 1e3)
+        return {"kernel": name, "launches": p[n], "ms_total": round(ms, 3), "avg_launch_ms": round(per, 4),
+                "algorithmic_bytes_per_launch": int(p[b_survey] / launches), "achieved": round(ach, 1),
+                "frac": round(ach / HBM_PEAK_GBS, 4), "hbm_bytes_per_launch": int(p[b_hbm] / launches),
+                "achieved_hbm": round(ach_hbm, 1), "frac_hbm": round(ach_hbm / HBM_PEAK_GBS, 4)}
+
+    kernels = {k: entry(prof, k) for k in KERNELS}
+    kernels = {k: v for k, v in kernels.items() if v}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    d = kernels[dom]
+    traffic = measured_traffic(dom)
+    roof = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["frac"],
+            "traffic": traffic, "kernel": d["kernel"], "avg_launch_ms": d["avg_launch_ms"],
+            "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+            "achieved_hbm_resident": d["achieved_hbm"], "frac_hbm_resident": d["frac_hbm"],
+            "hbm_resident_bytes_per_launch": d["hbm_bytes_per_launch"],
+            "kernels": kernels,
+            "kernel_ms_per_step": {k: round(v["ms_total"] / steps, 4) for k, v in kernels.items()},
+            "note": "dominant kernel by summed HIP-event time over the timed region; consecutive sweeps "
+                    "overlap on two streams, so a launch's duration includes device time shared with the "
+                    "other sweep's kernels; achieved = the survey's algorithmic bytes (labels kept in LDS "
+                    "included), achieved_hbm_resident = the bytes that must cross HBM"}
+    if traffic:   # counter bytes per launch over the same launch time
+        roof["traffic_gbs"] = round(traffic / 1e9 / (d["avg_launch_ms"] / 1e3), 1)
+    iso_d = entry(prof_iso, dom) if prof_iso else None
+    if iso_d:
+        roof["isolated"] = dict(iso_d, note="same kernel, one sweep per call (host API run), no other sweep on "
+                                            "the GPU")
+    return roof
+
+
 def cpu_baseline(g, src, tau, seconds, threads):
     """The oracle on this host: throughput with one query per thread on `threads` threads (the
-    plain tau-bounded Dijkstra with the edge rule, and the paper's isoDijkstra), and the plain
-    oracle's single-thread latency; about `seconds` of wall time in total."""
+    plain tau-bounded Dijkstra with the edge rule, and the paper's isoDijkstra); every query runs
+    on one thread, so the per-query times of the throughput run are single-thread latencies
+    (taken while the other threads run queries of their own).  About `seconds` of wall time."""
     import oracle
 
     t0 = time.time()
@@ -238,14 +315,15 @@ def cpu_baseline(g, src, tau, seconds, threads):
             t.join()
         return len(done) / (time.perf_counter() - t1), done
 
-    lat_budget, iso_budget = 0.25 * seconds, 0.25 * seconds
-    _, lat = throughput("isochrone", lat_budget, 1, 0)
-    qps, _ = throughput("isochrone", seconds - lat_budget - iso_budget, threads, 0)
+    iso_budget = 0.25 * seconds
+    qps, lat = throughput("isochrone", seconds - iso_budget, threads, 0)
     iso_qps, _ = throughput("iso_dijkstra", iso_budget, threads, 0)
     return {"value": qps, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"the benchmark's query list (tau uniform 10-240 min) from its start, one query per thread; "
-                      f"{seconds:.0f}s in total",
-            "single_thread_latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "queries": len(lat)},
+            "sample": f"the benchmark's query list (tau uniform 10-240 min) from its start, one query per thread "
+                      f"on {threads} threads, about {seconds:.0f}s in total",
+            "host": {"nproc": os.cpu_count(), "usable_cores": host_cores(), "cpu_model": cpu_model()},
+            "single_thread_latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "queries": len(lat),
+                                         "note": "each query on one thread, measured in the all-core run"},
             "iso_dijkstra_qps": iso_qps}
 
 
@@ -296,7 +374,7 @@ def main():
     ap.add_argument("--workload", default="road18m")
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--latency-queries", type=int, default=100)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -305,9 +383,10 @@ def main():
     ap.add_argument("--save-tuning", default="", help="write the autotuner's result to this JSON file")
     ap.add_argument("--knobs", default="",
                     help="explicit tuning, e.g. lanes_per_launch=32,cell_lds_kb=24,cell_stage=0 (others default)")
-    ap.add_argument("--serve-rates", default="100,500,1000,2000,5000",
+    ap.add_argument("--serve-rates", default="100,500,1000,2000,5000,10000,20000,40000",
                     help="offered Poisson rates (queries/s) for the serving section; empty to skip")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--no-sweep", action="store_true", help="skip the queries-per-sweep comparison")
     ap.add_argument("--cd-minutes", default="5,15,45",
                     help="limits (minutes) of the isoPHAST-CD comparison; empty to skip")
@@ -423,16 +502,9 @@ def main():
     qps_plain = np_steps * lanes / (time.perf_counter() - t0)
     prof_plain = G.profile_read()
     G.profile_enable(False)
-    # the plain sweep (every cell for every query) with its own algorithmic bytes per launch
-    plain_phases = {}
-    for key in ("core", "cell"):
-        ms_, by_, la_ = prof_plain[f"{key}_ms"], prof_plain[f"{key}_bytes"], prof_plain[f"{key}_launches"]
-        if ms_ > 0:
-            gbs = (by_ / 1e9) / (ms_ / 1e3)
-            plain_phases[f"{key}_sweep"] = {"avg_launch_ms": round(ms_ / max(1, la_), 4),
-                                           "algorithmic_bytes_per_launch": int(by_ / max(1, la_)),
-                                           "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    log(f"plain batched (device output): {qps_plain:.1f} queries/s; phases {plain_phases}")
+    # the plain sweep (every cell for every query): the same two kernels with their own bytes
+    plain_phases = roofline_of(prof_plain, None, np_steps)["kernels"]
+    log(f"plain batched (device output): {qps_plain:.1f} queries/s; kernels {plain_phases}")
 
     # the other output of Section 3: vertices in range, as one bitmap row per query over the
     # original ids, left in HBM (one call per batch of `lanes` queries)
@@ -522,37 +594,15 @@ def main():
             core_search[f"{minutes}min"] = row
             log(f"isoPHAST-CD vs CP at {minutes} min: {row}")
 
-    # roofline of the dominant device phase in the timed region
-    phases = {"core_sweep": (prof["core_ms"], prof["core_bytes"], prof["core_launches"]),
-              "cell_sweep": (prof["cell_ms"], prof["cell_bytes"], prof["cell_launches"])}
-    dom = max(phases, key=lambda k: phases[k][0])
-    ms, byts, launches = phases[dom]
-    achieved = (byts / 1e9) / (ms / 1e3) if ms > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
-                "avg_launch_ms": round(ms / max(1, launches), 4),
-                "algorithmic_bytes_per_launch": int(byts / max(1, launches)),
-                "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
-                "note": "timed region: consecutive sweeps overlap on two streams, so a launch's duration "
-                        "includes device time shared with the other sweep's kernels"}
-    if roofline["traffic"]:   # counter bytes per launch over the same launch time
-        roofline["traffic_gbs"] = round(roofline["traffic"] / 1e9 / (roofline["avg_launch_ms"] / 1e3), 1)
-    key = {"core_sweep": "core", "cell_sweep": "cell"}[dom]
-    iso_ms, iso_launches = prof_iso[f"{key}_ms"], prof_iso[f"{key}_launches"]
-    if iso_ms > 0:
-        iso_gbs = (prof_iso[f"{key}_bytes"] / 1e9) / (iso_ms / 1e3)
-        roofline["isolated"] = {"avg_launch_ms": round(iso_ms / max(1, iso_launches), 4),
-                                "achieved": round(iso_gbs, 1), "frac": round(iso_gbs / HBM_PEAK_GBS, 4),
-                                "note": "same kernel, one sweep per call (host API run), no other sweep "
-                                        "on the GPU"}
+    roofline = roofline_of(prof, prof_iso, args.steps)
 
     serve = None
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serve = {"mode": "cells", "max_lanes": lanes, "max_inflight": 2,
-                 "trace": f"Poisson arrivals, {args.serve_seconds:g}s per rate after 0.5s warm-up, uniform "
-                          "sources, tau log-uniform 5-300 min; latency = submit to result ready",
-                 "rates": serving(G, info["n"], rates, args.serve_seconds, lanes, 2)}
+                 "trace": f"Poisson arrivals, {args.serve_seconds:g}s per rate after {args.serve_warmup:g}s "
+                          "warm-up, uniform sources, tau log-uniform 5-300 min; latency = submit to result ready",
+                 "rates": serving(G, info["n"], rates, args.serve_seconds, lanes, 2, args.serve_warmup)}
 
     sweep = None if args.no_sweep else lanes_sweep(G, src, tau)
     if sweep:
@@ -561,11 +611,11 @@ def main():
     if bw:
         log(f"attainable bandwidth (device copy): {bw:.0f} GB/s")
         roofline["attainable_gbs"] = round(bw, 1)
-        roofline["frac_of_attainable"] = round(achieved / bw, 4)
+        roofline["frac_of_attainable"] = round(roofline["achieved"] / bw, 4)
 
     cpu = None
     if not args.no_cpu:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = args.cpu_threads or host_cores()
         cpu = cpu_baseline(g, src, tau, args.cpu_seconds, threads)
         log(f"cpu baseline: {cpu}")
 
@@ -585,7 +635,7 @@ def main():
         "batched_plain_qps": round(qps_plain, 2),
         "plain_sweep_roofline": dict(plain_phases, unit="GB/s", peak=HBM_PEAK_GBS,
                                      note="plain mode (every cell swept for every query), two overlapping "
-                                          "streams, HIP events per launch"),
+                                          "streams, HIP events around the kernels' launches"),
         "host_api_qps": {"one_batch_per_call": round(qps_host, 2), "one_call": round(qps_host_pipe, 2),
                          "note": "iso_query_batch, edges copied to host memory (PCIe included)",
                          "call_ms_p50": round(1000 * percentile(times, 50), 3),

@@ -11,8 +11,8 @@
  *   an upward contraction-hierarchy search from s followed by a level-ordered
  *   downward sweep over the hierarchy - over every vertex (ISO_MODE_PLAIN) or
  *   over the core and the active cells of a single-level partition only
- *   (ISO_MODE_CELLS, the isoPHAST-CP query with the relaxed cell-flag rule of
- *   the parallel-query paragraph of Section 6) - with isochrone edges
+ *   (ISO_MODE_CELLS, the isoPHAST-CP query with the relaxed cell-flag rule
+ *   that Section 5 gives for parallel queries) - with isochrone edges
  *   extracted during the sweep.
  *
  * Arithmetic is exact uint32: weights are in [0, 2^32 - 2]; ISO_INF =
@@ -83,7 +83,8 @@ typedef struct {
  * their minimum weight (the answer is keyed on (tail, head), Section 3).
  */
 typedef struct {
-    uint32_t n;                 /* |V| (>= 1, < 2^29: edge keys pack two ids of ceil(log2 n) bits each) */
+    uint32_t n;                 /* |V| (>= 1, < 2^30: a downward entry holds its tail's sweep position in
+                                   30 bits beside two flag bits) */
     uint64_t m;                 /* |E| (number of entries in tail/head/weight) */
     const uint32_t *tail;       /* m tails, < n */
     const uint32_t *head;       /* m heads, < n */
@@ -240,9 +241,28 @@ int iso_query_distances(iso_graph *g, uint32_t source, uint32_t tau, int mode,
 int iso_last_query_stats(const iso_graph *g, iso_query_stats *stats);
 
 /*
- * Tuning knobs of the device sweep (chosen by the autotuner; when never set:
- * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 0,
- * cell_block 0, table_max 0).  lanes_per_launch: queries per sweep in
+ * Branch counters (test hook).  While enabled, the query calls on g count how often the rare
+ * paths of the device sweep run, summed until the next iso_debug_enable (which clears them;
+ * enabling also turns graph replay off for the core sweep):
+ *   counts[0] an isochrone edge of a cell found the workgroup's edge list full and was written
+ *             out on its own;
+ *   counts[1] a level of a cell held more vertices than a cell workgroup has threads (the level
+ *             was swept in several rounds);
+ *   counts[2] a core vertex with more than 32 entries per thread had its entries walked again
+ *             for a straddling entry;
+ *   counts[3] an isochrone edge of a core level found the workgroup's key list full;
+ *   counts[4] a sweep found more isochrone edges than the edge-key buffer held and was run again
+ *             with a larger buffer (direct query calls);
+ *   counts[5..7] reserved (0).
+ * iso_debug_read: counts must hold 8 words.
+ */
+int iso_debug_enable(iso_graph *g, int enable);
+int iso_debug_read(iso_graph *g, uint64_t counts[8]);
+
+/*
+ * Tuning knobs of the device sweep (the autotuner measures them; when never set:
+ * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 2,
+ * cell_block 0, table_max 0, stall 1, edge_cap 0).  lanes_per_launch: queries per sweep in
  * iso_query_batch (1..64); block: threads per workgroup of the core level
  * kernel (64..1024, multiple of 64); cell_lds_kb: LDS budget of one cell
  * workgroup in KiB (16..160), which sets how many queries' labels a cell
@@ -255,15 +275,22 @@ typedef struct {
     uint32_t cell_lds_kb;
     uint32_t use_graph;         /* 1 = capture the device sweep of a context once (per shape and buffers)
                                    into a hipGraph and replay it */
-    uint32_t core_mode;         /* must be 0 (one launch per core level); other values are reserved and
-                                   rejected with ISO_EINVAL */
-    uint32_t cell_stage;        /* 0 = a cell workgroup holds two levels' entries in LDS and loads the next
-                                   level while relaxing the current one; 1 = it copies the cell's whole
-                                   data into LDS first (needs the largest cell's data plus one lane's labels
-                                   to fit 160 KiB, else 0 is used); cell_lds_kb bounds the LDS either way,
-                                   raised to the minimum the variant needs */
-    uint32_t cell_block;        /* threads per cell workgroup: 256 or 512; 0 = 512 for sweeps of 32 or more
-                                   queries, else 256 */
+    uint32_t core_mode;         /* one launch per core level below the table; 0 = with 64 queries per sweep
+                                   one wavefront per core vertex (its entries read once for the 64
+                                   queries), else threads per (vertex, query, share of its entries);
+                                   2 = the latter at every width.  Other values give ISO_EINVAL */
+    uint32_t cell_stage;        /* 2 = one workgroup per active cell: the cell's data is copied into LDS
+                                   once and swept for all the queries that activate the cell, up to 16 at
+                                   a time, each thread holding one vertex's labels for those queries
+                                   (needs the largest cell's data and one query's labels to fit 160 KiB,
+                                   else 0 is used); 0 = work items of a cell and up to G queries, a
+                                   workgroup holds two levels' entries in LDS and loads the next level
+                                   while relaxing the current one; 1 = work items as in 0, the item's
+                                   whole cell data copied into LDS first (needs the largest cell's data
+                                   plus one lane's labels to fit 160 KiB, else 0 is used); cell_lds_kb
+                                   bounds the LDS in every variant, raised to the minimum it needs */
+    uint32_t cell_block;        /* threads per cell workgroup of variants 0 and 1: 256 or 512; 0 = 512 for
+                                   sweeps of 32 or more queries, else 256 (variant 2 uses 512) */
     uint32_t table_max;         /* level-merge threshold: the top core levels are merged into one (min,+)
                                    product with the distance table of their vertices while they hold at
                                    most this many vertices; the levels below get one launch each.  0 =
@@ -274,6 +301,13 @@ typedef struct {
                                    with a shorter path through a downward arc from a reached higher vertex
                                    is neither expanded nor handed to the sweep (default); 0 = off.  The
                                    answer is the same either way */
+    uint32_t edge_cap;          /* 0 = keep the edge-key buffer as it is; otherwise its capacity (in edges,
+                                   at least 16) is reset to this value by iso_set_tuning.  A sweep that finds
+                                   more isochrone edges than the buffer holds is run again with a larger
+                                   buffer (for the serving loop, within its device budget), so this only
+                                   moves memory against repeated sweeps; the answer is the same */
+    uint32_t overlap_cells;     /* resident cell workgroups per compute unit while two sweeps of one call
+                                   overlap on two streams (0 = 2; at most what fits, at most 16) */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);
@@ -330,6 +364,12 @@ typedef struct {
     uint64_t cell_vertices, cells_swept;                /* internal vertices and cells swept */
     uint64_t cell_lanes;        /* (cell, query) pairs swept: each cell counts its active lanes */
     uint64_t cell_items;        /* cell-sweep work items (a cell and up to G of its lanes) */
+    uint64_t cell_bytes_survey; /* the cell sweep's bytes counted as a plain PHAST sweep moves them: offsets
+                                   and 8-byte entries of the swept cells once, plus per (cell, query) every
+                                   internal label written once and read back once (also those that stay
+                                   in LDS) */
+    double level_ms;            /* the core level launches below the top table alone (k_core_level) */
+    uint64_t level_launches, level_bytes;   /* their launches and algorithmic bytes (as core_bytes) */
 } iso_profile;
 int iso_profile_enable(iso_graph *g, int enable);
 int iso_profile_read(const iso_graph *g, iso_profile *out);
@@ -363,7 +403,8 @@ typedef struct {
 typedef struct {
     uint64_t submitted, completed, sweeps, lanes_total;
     uint32_t contexts, lanes_cap, queue_depth, inflight;
-    uint64_t ctx_bytes;         /* device bytes reserved per context */
+    uint64_t ctx_bytes;         /* device bytes reserved per context (grows with the edge buffer) */
+    uint64_t regrown;           /* sweeps run again with a larger edge buffer after an overflow */
 } iso_server_stats;
 int iso_server_start(iso_graph *g, const iso_server_config *cfg, iso_server **out);
 /* Non-blocking; *ticket identifies the request.  ISO_ESTATE after iso_server_stop. */

@@ -52,7 +52,8 @@ class QueryStats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("lanes_per_launch", C.c_uint32), ("block", C.c_uint32), ("cell_lds_kb", C.c_uint32),
                 ("use_graph", C.c_uint32), ("core_mode", C.c_uint32), ("cell_stage", C.c_uint32),
-                ("cell_block", C.c_uint32), ("table_max", C.c_uint32), ("stall", C.c_uint32)]
+                ("cell_block", C.c_uint32), ("table_max", C.c_uint32), ("stall", C.c_uint32),
+                ("edge_cap", C.c_uint32), ("overlap_cells", C.c_uint32)]
 
 
 _U32P = C.POINTER(C.c_uint32)
@@ -71,7 +72,9 @@ class Profile(C.Structure):
                 ("sort_ms", C.c_double), ("core_launches", C.c_uint64), ("cell_launches", C.c_uint64),
                 ("calls", C.c_uint64), ("core_bytes", C.c_uint64), ("cell_bytes", C.c_uint64),
                 ("core_entries", C.c_uint64), ("cell_entries", C.c_uint64), ("cell_vertices", C.c_uint64),
-                ("cells_swept", C.c_uint64), ("cell_lanes", C.c_uint64), ("cell_items", C.c_uint64)]
+                ("cells_swept", C.c_uint64), ("cell_lanes", C.c_uint64), ("cell_items", C.c_uint64),
+                ("cell_bytes_survey", C.c_uint64), ("level_ms", C.c_double), ("level_launches", C.c_uint64),
+                ("level_bytes", C.c_uint64)]
 
 
 class Edge(C.Structure):
@@ -90,7 +93,8 @@ class RequestStats(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("sweeps", C.c_uint64),
                 ("lanes_total", C.c_uint64), ("contexts", C.c_uint32), ("lanes_cap", C.c_uint32),
-                ("queue_depth", C.c_uint32), ("inflight", C.c_uint32), ("ctx_bytes", C.c_uint64)]
+                ("queue_depth", C.c_uint32), ("inflight", C.c_uint32), ("ctx_bytes", C.c_uint64),
+                ("regrown", C.c_uint64)]
 
 
 _lib = None
@@ -142,6 +146,8 @@ def lib():
     L.iso_targets_free.restype = None
     L.iso_query_distances.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, _U32P, C.POINTER(C.c_uint8)]
     L.iso_last_query_stats.argtypes = [C.c_void_p, C.POINTER(QueryStats)]
+    L.iso_debug_enable.argtypes = [C.c_void_p, C.c_int]
+    L.iso_debug_read.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
     L.iso_set_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.iso_get_tuning.argtypes = [C.c_void_p, C.POINTER(Tuning)]
     L.iso_profile_enable.argtypes = [C.c_void_p, C.c_int]
@@ -354,15 +360,24 @@ class Graph:
                                          dist.ctypes.data_as(_U32P), swept.ctypes.data_as(C.POINTER(C.c_uint8))))
         return dist, swept.astype(bool)
 
+    def debug_enable(self, enable: bool = True):
+        _check(lib().iso_debug_enable(self._h, int(bool(enable))))
+
+    def debug_read(self) -> list[int]:
+        """Branch counters (iso_debug_read in include/iso.h)."""
+        out = (C.c_uint64 * 8)()
+        _check(lib().iso_debug_read(self._h, out))
+        return list(out)
+
     def last_stats(self) -> dict:
         s = QueryStats()
         _check(lib().iso_last_query_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in QueryStats._fields_}
 
-    def set_tuning(self, lanes_per_launch=64, block=256, cell_lds_kb=64, use_graph=1, core_mode=0, cell_stage=0,
-                   cell_block=0, table_max=0, stall=1):
+    def set_tuning(self, lanes_per_launch=64, block=256, cell_lds_kb=64, use_graph=1, core_mode=0, cell_stage=2,
+                   cell_block=0, table_max=0, stall=1, edge_cap=0, overlap_cells=0):
         t = Tuning(lanes_per_launch, block, cell_lds_kb, use_graph, core_mode, cell_stage, cell_block, table_max,
-                   stall)
+                   stall, edge_cap, overlap_cells)
         _check(lib().iso_set_tuning(self._h, C.byref(t)))
 
     def profile_enable(self, enable: bool = True):

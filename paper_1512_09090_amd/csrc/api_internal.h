@@ -321,12 +321,14 @@ struct iso_graph {
     int threads = 1;
     std::atomic<bool> busy{false};
     iso_query_stats last{};
-    iso_tuning tuning{64, 256, 64, 1, 0, 0, 0, 0, 1};   // the autotuner's choice on an 18M-vertex road graph
+    iso_tuning tuning{64, 256, 64, 1, 0, 2, 0, 0, 1, 0, 0};   // defaults (include/iso.h)
     UpwardGraph upg;                // packed upward graph
     std::vector<UpwardSearch> up;   // one workspace per host thread
     std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> up_out;   // one search result buffer per worker
     size_t out_cap = 1 << 20;
+    bool debug = false;              // count rare kernel branches (iso_debug_enable)
+    uint64_t resweeps = 0;           // sweeps run again with a larger edge buffer
     uint64_t *vbits_dev = nullptr;   // device bitmap of iso_query_vertices (ceil(n / 64) words)
     std::unique_ptr<CoreGraph> coreg;         // isoPHAST-CD: core graph (built on first use)
     std::vector<CoreDijkstra> cdj;            // one workspace per host thread

@@ -8,6 +8,7 @@
 #include <string>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "prep.h"
@@ -33,14 +34,17 @@ struct RunArgs {
     uint32_t lane_base = 0;
     uint32_t block = 256;            // threads per workgroup of the core level kernel
     uint32_t use_graph = 0;          // 1: replay the captured device sweep
-    uint32_t cell_stage = 0;         // 1: whole cell staged in LDS
-    uint32_t cell_block = 512;       // threads per cell workgroup
+    uint32_t cell_stage = 2;         // 0: level pipeline per work item, 1: a work item's cell staged in LDS,
+                                     // 2: one workgroup per cell for all its lanes (k_cell_chunks)
+    uint32_t cell_block = 512;       // threads per cell workgroup (cell_stage 0 and 1)
     size_t cell_lds_bytes = 40 * 1024;
     // resident cell workgroups per CU (0: as many as fit).  A sweep that overlaps another
     // sweep's kernels runs faster with fewer (measured: 2 of 3 on road18m), one alone with all.
     uint32_t cell_per_cu = 0;
     bool mode_plain = true;
     bool want_dist = false;
+    bool debug = false;          // count rare kernel branches (QueryBufs::d_dbg)
+    bool core64 = true;          // 64 queries per sweep: core levels one wavefront per vertex
     size_t out_cap = 0;          // capacity of the edge-key buffer
     uint32_t table_x = 0;        // top table used: core positions [0, table_x), the first table_levels levels
     uint32_t table_levels = 0;
@@ -112,11 +116,12 @@ struct QueryBufs {
     uint64_t *d_vmask = nullptr, *d_cin = nullptr;   // vertex output: lanes in range per position; per cell
     uint32_t *d_rlab = nullptr;                        // one-to-many: labels of a target set's rows
     uint64_t *d_prof = nullptr;                        // profile: cell-sweep sums (k_prof_cells)
+    unsigned long long *d_dbg = nullptr;               // branch counters of the sweep kernels (8 words)
     uint32_t *d_lane_off = nullptr;   // MAX_LANES + 1 lane starts of the decoded edges
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
     size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
            sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0,
-           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0, sz_rlab = 0, sz_prof = 0;
+           sz_lane_off = 0, sz_vmask = 0, sz_cin = 0, sz_rlab = 0, sz_prof = 0, sz_dbg = 0;
     void release();
 };
 
@@ -126,8 +131,9 @@ struct Profile {
     double core_ms = 0, active_ms = 0, cell_ms = 0, sort_ms = 0;
     uint64_t core_launches = 0, cell_launches = 0, calls = 0, core_bytes = 0, cell_bytes = 0;
     uint64_t core_entries = 0, cell_entries = 0, cell_vertices = 0, cells_swept = 0, cell_lanes = 0,
-             cell_items = 0;
-    hipEvent_t ev[6] = {};
+             cell_items = 0, cell_bytes_survey = 0, level_bytes = 0, level_launches = 0;
+    double level_ms = 0;
+    hipEvent_t ev[8] = {};   // phase marks: 0 core start, 1 core end, 2/3 cell sweep, 4/5 sort, 6/7 core levels
 };
 
 // Everything the captured sweep sequence depends on (kernel arguments and grid shapes).
@@ -150,9 +156,9 @@ struct SweepCtx {
     QueryBufs bufs;
     Profile prof;
     bool pending = false;
-    uint32_t K = 1, lk = 0, lg = 0, lanes = 0, lane_base = 0, nlev = 0, top = 0;
+    uint32_t K = 1, lk = 0, lg = 0, lanes = 0, lane_base = 0, nlev = 0, top = 0, cell_variant = 0;
     size_t cap = 0;
-    bool mode_plain = true, want_dist = false, vertex_mode = false, one_to_many = false;
+    bool mode_plain = true, want_dist = false, vertex_mode = false, one_to_many = false, levels_timed = false;
     uint32_t *h_counters = nullptr;   // pinned: keys produced, active cells
     int create(int device);
     void release();
@@ -193,13 +199,20 @@ struct DevGraph {
     // per-cell blobs for the cell sweep: [offsets][level bounds][core refs][entries]
     uint32_t *d_blob = nullptr;
     uint32_t *d_cblob = nullptr;   // word offset of each cell's blob
+    // per-cell data of the one-workgroup-per-cell sweep (k_cell_chunks): offsets, level starts,
+    // core refs, entries packed into one word each (packed2) or two
+    uint32_t *d_blob2 = nullptr, *d_cblob2 = nullptr;
+    uint32_t max_blob2_words = 0, max_rows2 = 0, lb2 = 16;
+    bool packed2 = false;
     uint4 *d_cmeta = nullptr;      // (internal count, levels, core refs, entries)
     uint32_t *d_cell_ebase = nullptr;   // index of each cell's first downward entry
     uint32_t max_blob_words = 0, max_cell_labels = 0, max_cell_cnt = 0, max_cell_levels = 0;
     int num_cus = 0;                                   // compute units of the device
     std::map<uint64_t, uint32_t> occ_cache;            // cell-sweep workgroups per CU by (variant, LDS)
-    int cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t &per_cu);
+    std::mutex occ_mu;                                 // the serving loop's threads launch concurrently
+    int cell_occupancy(uint32_t variant, uint32_t threads, size_t lds, uint32_t &per_cu);
     int upload_arc_ranks(const iso::Prep &P);
+    int upload_cell_blobs2(const iso::Prep &P, const std::vector<std::vector<uint32_t>> &refs_of);
     uint64_t bytes = 0;
     SweepCtx main;   // context of the direct query calls
     SweepCtx aux;    // second context of a batch call, so that consecutive sweeps overlap (made on first use)
@@ -222,7 +235,8 @@ struct DevGraph {
                        uint32_t table_levels, TargetSet &T);
     std::vector<uint32_t> sel_row;   // target selection scratch: position -> row
     int run(SweepCtx &C, const RunArgs &A, RunResult &R);
-    // device bytes a context needs for k lanes and an edge capacity (admission control)
+    // device bytes a context needs for k lanes and an edge capacity (admission control),
+    // including the radix sort's temporary storage for that capacity
     size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const;
     void release();
 };

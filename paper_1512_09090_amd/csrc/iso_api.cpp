@@ -58,6 +58,8 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     A.k_pow2 = pow2_at_least(lanes);
     A.mode_plain = plain;
     A.want_dist = want_dist;
+    A.debug = g->debug;
+    A.core64 = g->tuning.core_mode == 0;
     const uint32_t K = A.k_pow2;
     A.taus.assign(K, 0u);   // padding lanes: every label INF > 0, so they activate no cell and emit nothing
     A.src_cell.assign(K, iso::NO_CELL);
@@ -226,6 +228,7 @@ int run_lanes(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint32_t l
         if (r) return r;
         if (!R.overflow) break;
         g->out_cap = std::max<size_t>(g->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
+        g->resweeps++;
     }
     if (R.overflow) return fail(ISO_ENOMEM, "edge buffer overflow");
     double t2 = now_ms();
@@ -261,7 +264,7 @@ void iso_free(void *p) {
 int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
     if (!d || !out) return fail(ISO_EINVAL, "NULL argument");
     *out = nullptr;
-    if (d->n == 0 || d->n >= (1u << 29)) return fail(ISO_EINVAL, "n must be in [1, 2^29)");
+    if (d->n == 0 || d->n > iso::TAIL_MASK) return fail(ISO_EINVAL, "n must be in [1, 2^30)");
     if (d->m && (!d->tail || !d->head || !d->weight)) return fail(ISO_EINVAL, "arc arrays are NULL");
     uint32_t maxc = d->max_cell_size ? d->max_cell_size : 2048;
     if (maxc > 4096) return fail(ISO_EINVAL, "max_cell_size must be <= 4096");
@@ -480,6 +483,7 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         int r = D.finish(*W.C, R);
         for (int attempt = 0; !r && R.overflow && attempt < 8; ++attempt) {   // grow the edge buffer, sweep again
             g->out_cap = std::max<size_t>(g->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
+            g->resweeps++;
             W.A.out_cap = g->out_cap;
             r = D.launch(*W.C, W.A);
             if (!r) r = D.finish(*W.C, R);
@@ -524,7 +528,8 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         build_run_args(g, src + W->b, tau + W->b, W->lanes, mode == ISO_MODE_PLAIN, false, W->A, W->settled.data(),
                        mode == ISO_MODE_CD);
         W->A.out_cap = g->out_cap;
-        if (overlap) W->A.cell_per_cu = isodev::OVERLAP_CELL_PER_CU;   // the sweeps share the GPU
+        if (overlap)   // the sweeps share the GPU
+            W->A.cell_per_cu = g->tuning.overlap_cells ? g->tuning.overlap_cells : isodev::OVERLAP_CELL_PER_CU;
         g->last.t_upward_ms += now_ms() - tu;
         if (inflight.size() == nctx) {   // frees W's context
             int r = collect(*inflight.front());
@@ -913,10 +918,10 @@ int iso_profile_enable(iso_graph *g, int enable) {
     if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
     for (isodev::SweepCtx *C : {&g->D.main, &g->D.aux}) {   // aux: created with main's setting
         auto &P = C->prof;
-        hipEvent_t ev[6];
+        hipEvent_t ev[sizeof(P.ev) / sizeof(P.ev[0])];
         std::copy(std::begin(P.ev), std::end(P.ev), ev);
         P = isodev::Profile();
-        std::copy(ev, ev + 6, P.ev);
+        std::copy(std::begin(ev), std::end(ev), P.ev);
         P.on = enable != 0;
     }
     return ISO_OK;
@@ -928,12 +933,13 @@ int iso_profile_read(const iso_graph *g, iso_profile *o) {
     for (const isodev::SweepCtx *C : {&g->D.main, &g->D.aux}) {   // both sweep contexts of query calls
         const auto &P = C->prof;
         if (P.acc_ready && C->bufs.d_prof) {   // the cell-sweep sums kept on the device
-            uint64_t acc[5] = {0, 0, 0, 0, 0};
+            uint64_t acc[7] = {0, 0, 0, 0, 0, 0, 0};
             if (hipSetDevice(g->D.device) != hipSuccess ||
                 hipMemcpy(acc, C->bufs.d_prof, sizeof acc, hipMemcpyDeviceToHost) != hipSuccess)
                 return fail(ISO_EDEVICE, "reading the profile sums failed");
             o->cell_bytes += acc[0]; o->cells_swept += acc[1]; o->cell_lanes += acc[2];
             o->cell_vertices += acc[3]; o->cell_entries += acc[4];
+            o->cell_bytes_survey += acc[5]; o->cell_items += acc[6];
         }
         o->core_ms += P.core_ms; o->active_ms += P.active_ms; o->cell_ms += P.cell_ms; o->sort_ms += P.sort_ms;
         o->core_launches += P.core_launches; o->cell_launches += P.cell_launches; o->calls += P.calls;
@@ -941,7 +947,37 @@ int iso_profile_read(const iso_graph *g, iso_profile *o) {
         o->core_entries += P.core_entries; o->cell_entries += P.cell_entries;
         o->cell_vertices += P.cell_vertices; o->cells_swept += P.cells_swept;
         o->cell_lanes += P.cell_lanes; o->cell_items += P.cell_items;
+        o->level_ms += P.level_ms; o->level_launches += P.level_launches; o->level_bytes += P.level_bytes;
     }
+    return ISO_OK;
+}
+
+int iso_debug_enable(iso_graph *g, int enable) {
+    if (!g) return fail(ISO_EINVAL, "NULL argument");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    g->debug = enable != 0;
+    g->resweeps = 0;
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    for (isodev::SweepCtx *C : {&g->D.main, &g->D.aux})
+        if (C->bufs.d_dbg && hipMemset(C->bufs.d_dbg, 0, 8 * sizeof(uint64_t)) != hipSuccess)
+            return fail(ISO_EDEVICE, "clearing the branch counters failed");
+    return ISO_OK;
+}
+
+int iso_debug_read(iso_graph *g, uint64_t counts[8]) {
+    if (!g || !counts) return fail(ISO_EINVAL, "NULL argument");
+    std::fill(counts, counts + 8, uint64_t(0));
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    for (isodev::SweepCtx *C : {&g->D.main, &g->D.aux}) {
+        if (!C->bufs.d_dbg) continue;
+        uint64_t v[8];
+        if (hipMemcpy(v, C->bufs.d_dbg, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(ISO_EDEVICE, "reading the branch counters failed");
+        for (int k = 0; k < 8; ++k) counts[k] += v[k];
+    }
+    counts[4] += g->resweeps;
     return ISO_OK;
 }
 
@@ -957,15 +993,17 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (t->block < 64 || t->block > 1024 || t->block % 64) return fail(ISO_EINVAL, "block must be a multiple of 64 in [64, 1024]");
     if (t->cell_lds_kb < 16 || t->cell_lds_kb > 160) return fail(ISO_EINVAL, "cell_lds_kb must be in [16, 160]");
     if (t->use_graph > 1) return fail(ISO_EINVAL, "use_graph must be 0 or 1");
-    if (t->cell_stage > 1) return fail(ISO_EINVAL, "cell_stage must be 0 or 1");
+    if (t->cell_stage > 2) return fail(ISO_EINVAL, "cell_stage must be 0, 1 or 2");
     if (t->cell_block != 0 && t->cell_block != 256 && t->cell_block != 512)
         return fail(ISO_EINVAL, "cell_block must be 0, 256 or 512");
     if (t->table_max > isodev::TABLE_MAX) return fail(ISO_EINVAL, "table_max must be at most 16384");
     if (t->stall > 1) return fail(ISO_EINVAL, "stall must be 0 or 1");
-    if (t->core_mode != 0)
-        return fail(ISO_EINVAL, "core_mode must be 0: the single-launch core sweep with a grid barrier "
-                                "is disabled");
+    if (t->overlap_cells > 16) return fail(ISO_EINVAL, "overlap_cells must be at most 16");
+    if (t->core_mode != 0 && t->core_mode != 2)
+        return fail(ISO_EINVAL, "core_mode must be 0 or 2 (1, a single-launch core sweep with a grid "
+                                "barrier, was removed)");
     g->tuning = *t;
+    if (t->edge_cap) g->out_cap = std::max<size_t>(16, t->edge_cap);
     return ISO_OK;
 }
 

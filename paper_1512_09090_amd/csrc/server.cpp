@@ -50,8 +50,8 @@ struct iso_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::thread launcher, completer;
-    uint64_t next_ticket = 1, submitted = 0, completed = 0, sweeps = 0, lanes_total = 0;
-    size_t out_cap = 1 << 20;
+    uint64_t next_ticket = 1, submitted = 0, completed = 0, sweeps = 0, lanes_total = 0, regrown = 0;
+    size_t out_cap = 1 << 20;   // edge-key capacity of a sweep; guarded by mu (grown by the completer)
     bool accepting = false, stopping = false, launcher_done = false, stopped = false;
 };
 
@@ -78,6 +78,7 @@ void launcher_loop(iso_server *s) {
         std::vector<uint64_t> tickets;
         std::vector<uint32_t> src, tau;
         isodev::SweepCtx *ctx = nullptr;
+        size_t cap = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return (s->stopping && s->queue.empty()) || (!s->queue.empty() && !s->free_ctx.empty()); });
@@ -95,13 +96,14 @@ void launcher_loop(iso_server *s) {
                 tau.push_back(r.tau);
             }
             for (uint64_t tk : tickets) s->reqs[tk].batch_lanes = uint32_t(tickets.size());
+            cap = s->out_cap;   // written by the completer when a sweep overflows
         }
         InFlight f;
         f.ctx = ctx;
         f.tickets = tickets;
         build_run_args(g, src.data(), tau.data(), uint32_t(src.size()), s->cfg.mode == ISO_MODE_PLAIN, false,
                        f.args, nullptr, s->cfg.mode == ISO_MODE_CD);
-        f.args.out_cap = s->out_cap;
+        f.args.out_cap = cap;
         int r = g->D.launch(*ctx, f.args);
         if (r) {
             fail_batch(s, tickets, r);
@@ -144,8 +146,23 @@ void completer_loop(iso_server *s) {
         };
         int r = g->D.finish(*f.ctx, R);
         for (int attempt = 0; !r && R.overflow && attempt < 8; ++attempt) {
-            s->out_cap = std::max<size_t>(s->out_cap * 2, size_t(R.count) + (size_t(R.count) >> 3));
-            f.args.out_cap = s->out_cap;
+            // grow the edge buffer and sweep again, as long as every context still fits the
+            // device budget with the larger buffer (otherwise the batch fails with ISO_ENOMEM)
+            size_t cap = 0;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                cap = std::max<size_t>(std::max(s->out_cap, f.args.out_cap * 2),
+                                       size_t(R.count) + (size_t(R.count) >> 3));
+                const size_t need = g->D.ctx_bytes(s->lanes_cap, cap, size_t(s->lanes_cap) * 4096);
+                if (s->cfg.device_budget && need * s->ctxs.size() > s->cfg.device_budget) {
+                    r = api_fail(ISO_ENOMEM, "the edge buffer this sweep needs exceeds the device budget");
+                    break;
+                }
+                s->out_cap = cap;
+                s->ctx_bytes = std::max(s->ctx_bytes, need);
+                s->regrown++;
+            }
+            f.args.out_cap = cap;
             r = g->D.launch(*f.ctx, f.args);
             if (!r) r = g->D.finish(*f.ctx, R);
         }
@@ -298,6 +315,7 @@ int iso_server_get_stats(iso_server *s, iso_server_stats *o) {
     o->queue_depth = uint32_t(s->queue.size());
     o->inflight = uint32_t(s->inflight.size());
     o->ctx_bytes = s->ctx_bytes;
+    o->regrown = s->regrown;
     return ISO_OK;
 }
 

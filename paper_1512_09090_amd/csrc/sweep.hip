@@ -6,8 +6,8 @@
 //      top, each vertex taking min(upward label, tail label + length) over its
 //      incoming downward arcs (Section 2, PHAST scanning phase; Section 5,
 //      isoPHAST-CP second phase).  Every core vertex also sets its cell's flags
-//      i (label <= tau) and o (label + ecc > tau) - the relaxed rule of the
-//      parallel-query paragraph of Section 6 - and tests the flagged original
+//      i (label <= tau) and o (label + ecc > tau) - the relaxed rule that
+//      Section 5 gives for parallel queries - and tests the flagged original
 //      arcs at it for isochrone edges (Section 5, output during the sweep).
 //      The top levels, where the hierarchy narrows to a near-clique chain, are
 //      answered from a precomputed table of downward distances (one (min,+)
@@ -26,8 +26,9 @@
 // k lanes (one per query) times S sub-lanes that split the vertex's arc list,
 // combined by a shuffle-xor minimum.  Isochrone edges are collected per
 // workgroup in LDS and appended with one output reservation per workgroup as
-// 64-bit keys lane << 2b | tail << b | head (b = bits of a vertex id), then
-// radix-sorted over their 2b + log2 k bits (query, tail, head).
+// 64-bit keys lane << r | rank, where rank is the arc's index among all arcs
+// ordered by (tail, head) over original ids and r = ceil(log2 m); a radix sort
+// over their r + log2 k bits orders them by (query, tail, head).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -54,14 +55,14 @@ constexpr uint32_t LOCAL_MASK = 0xFFFFu;   // cell-local tail index inside a blo
 constexpr uint32_t NO_SLOT = 0xFFFFFFFFu;
 constexpr uint32_t NO_CELL = 0xFFFFFFFFu;
 
-__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
-    uint32_t s = a + b;
-    return s < a ? INF : s;
-}
+// a + b saturated at INF (one v_add_u32 with the clamp bit)
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
-// Output key of an isochrone edge: the lane above the arc's rank in (tail, head) order.
-__device__ __forceinline__ uint64_t edge_key(uint32_t lane, uint32_t rank, uint32_t rb) {
-    return (uint64_t(lane) << rb) | uint64_t(rank);
+// Output key of an isochrone edge as the sweep kernels write it: the lane, the downward entry
+// and the direction (0: the entry's forward arc tail -> head, 1: its reverse arc).  Before the
+// sort, k_rank_keys turns it into lane << rb | the arc's rank in (tail, head) order.
+__device__ __forceinline__ uint64_t entry_key(uint32_t lane, uint32_t entry, uint32_t rev) {
+    return (uint64_t(lane) << 33) | (uint64_t(entry) << 1) | rev;
 }
 
 // Sorted keys -> (tail, head) pairs (the rank's entry of arc_pair), and the first position of
@@ -83,24 +84,33 @@ __global__ void k_decode(const uint64_t *__restrict__ keys, uint32_t n, uint2 *_
 // per active cell its lanes, internal vertices and entries, and its algorithmic bytes (the
 // cell's data streamed once, each active lane reading each referenced core label once), added
 // into acc[0..4] = bytes, cells, lanes, vertices, entries.  Every thread reaches the reduction.
+// Also acc[5]: the survey's algorithmic bytes of the swept cells (the graph stream at 8 bytes
+// per entry plus the offsets, and per (cell, lane) each internal label written once and read
+// back once), and acc[6]: chunks of 2^lg lanes (the one-workgroup-per-cell sweep).  words_mode:
+// 0 per-item cell data, 1 / 2 per-cell data with wide / packed entries.
 __host__ __device__ __forceinline__ uint32_t blob_words(uint32_t cnt, uint32_t nl, uint32_t nrefs, uint32_t ne);
+__host__ __device__ __forceinline__ uint32_t c2_words(uint32_t cnt, uint32_t nl, uint32_t nrefs, uint32_t ne,
+                                                      bool packed);
 __global__ void k_prof_cells(const uint32_t *__restrict__ clist, const uint32_t *__restrict__ counters,
                              const uint64_t *__restrict__ cmask, const uint4 *__restrict__ cmeta,
-                             unsigned long long *__restrict__ acc) {
+                             unsigned long long *__restrict__ acc, uint32_t words_mode, uint32_t lg) {
     const uint32_t n = counters[1];
-    unsigned long long v[5] = {0, 0, 0, 0, 0};
+    unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t c = clist[i];
         const uint4 m = cmeta[c];
         const unsigned long long l = (unsigned long long)__popcll(cmask[c]);
-        v[0] += 4ull * blob_words(m.x, m.y, m.z, m.w) + l * 4ull * m.z;
+        const uint32_t words = words_mode ? c2_words(m.x, m.y, m.z, m.w, words_mode == 2) : blob_words(m.x, m.y, m.z, m.w);
+        v[0] += 4ull * words + l * 4ull * m.z;
         v[1] += 1;
         v[2] += l;
         v[3] += m.x;
         v[4] += m.w;
+        v[5] += 4ull * (m.x + 1) + 8ull * m.w + 8ull * m.x * l;
+        v[6] += (l + (1ull << lg) - 1) >> lg;
     }
 #pragma unroll
-    for (uint32_t k = 0; k < 5; ++k) {
+    for (uint32_t k = 0; k < 7; ++k) {
         for (uint32_t o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], (int)o);
         if (__lane_id() == 0 && v[k]) atomicAdd(&acc[k], v[k]);
     }
@@ -168,11 +178,11 @@ struct CoreArgs {
     const uint2 *down_arc;
     uint32_t *dcore;
     const uint32_t *uslot, *uval, *core_cell, *core_ecc, *taus;
-    const uint2 *arc_rank;   // per downward entry: ranks of its forward and reverse arcs
     uint64_t *vin, *vout;    // per core vertex: lanes with d <= tau, lanes with d + ecc > tau
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk, rb;
+    uint32_t out_cap, lane_base, lk;
+    unsigned long long *dbg;   // branch counters (nullptr: none)
 };
 
 // Per (vertex, lane, sub-lane): bit k of `in` / `flag` tells whether the sub-lane's k-th entry
@@ -237,6 +247,7 @@ __device__ __forceinline__ void push_key(bool pred, uint64_t key, uint64_t *s_ke
         if (k < CORE_KEYS) {
             s_keys[k] = key;
         } else {
+            if (A.dbg) atomicAdd(&A.dbg[3], 1ull);
             const uint32_t idx = atomicAdd(A.out_count, 1u);
             if (idx < A.out_cap) A.out_keys[idx] = key;
         }
@@ -259,18 +270,19 @@ __device__ __forceinline__ void extract_group(ARC arc, LAB lab, const CoreArgs &
         const bool have = st != 0;
         const uint32_t k = have ? uint32_t(__ffs(st) - 1) : 0u;
         st &= st - 1u;
-        const uint2 rk = have ? A.arc_rank[beg + sub + k * S] : make_uint2(INF, INF);
-        push_key(rk.x != INF, edge_key(lane, rk.x, A.rb), s_keys, s_n, A);
-        push_key(rk.y != INF, edge_key(lane, rk.y, A.rb), s_keys, s_n, A);
+        const uint32_t e = beg + sub + k * S;
+        const uint32_t x = have ? arc(e).x : 0u;
+        push_key(x & FLAG_FWD, entry_key(lane, e, 0u), s_keys, s_n, A);
+        push_key(x & FLAG_REV, entry_key(lane, e, 1u), s_keys, s_n, A);
     }
     uint32_t e = walk ? beg + sub : 0, stop = walk ? end : 0;
     while (__any(e < stop)) {
         const bool have = e < stop;
         const uint2 a = have ? arc(e) : make_uint2(0u, 0u);
         const bool str = have && (a.x & FLAGS) && ((lab(a.x & TAIL_MASK) <= tau) != vin);
-        const uint2 rk = str ? A.arc_rank[e] : make_uint2(INF, INF);
-        push_key(rk.x != INF, edge_key(lane, rk.x, A.rb), s_keys, s_n, A);
-        push_key(rk.y != INF, edge_key(lane, rk.y, A.rb), s_keys, s_n, A);
+        if (A.dbg && str) atomicAdd(&A.dbg[2], 1ull);
+        push_key(str && (a.x & FLAG_FWD), entry_key(lane, e, 0u), s_keys, s_n, A);
+        push_key(str && (a.x & FLAG_REV), entry_key(lane, e, 1u), s_keys, s_n, A);
         e += S;
     }
 }
@@ -411,6 +423,81 @@ k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
     keys_begin(&s_n);
     const uint32_t b = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
     core_item(A, b * blockDim.x + threadIdx.x, ls, vbeg, vend, s_keys, &s_n);
+    keys_end(s_keys, &s_n, &s_base, A);
+}
+
+// A core level for 64 queries per sweep: one wavefront per vertex, lane j = query j.  The
+// vertex's offsets and entries are the same for the whole wavefront (scalar loads), and each
+// entry costs one coalesced 256-byte load of its tail's label row.  The first 32 entries'
+// "tail in range" bits give the straddling entries once the label is final (a vertex with
+// more entries walks them again).  Block b of the grid takes the (b mod 8)-th eighth of the
+// level, as in k_core_level.
+__global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, uint32_t vbeg, uint32_t vend) {
+    __shared__ uint64_t s_keys[CORE_KEYS];
+    __shared__ uint32_t s_n, s_base;
+    keys_begin(&s_n);
+    const uint32_t b = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t v = vbeg + b * (blockDim.x >> 6) + wv;   // uniform over the wavefront
+    const uint32_t j = __lane_id();
+    if (v < vend) {
+        const uint32_t tau = A.taus[j];
+        const uint32_t beg = A.down_off[v], end = A.down_off[v + 1];
+        const uint32_t sl = A.uslot[v];
+        uint32_t dv = sl != NO_SLOT ? A.uval[(sl << 6) + j] : INF;
+        uint32_t in = 0, flag = 0;   // per entry k < 32: tail in range (this lane), entry flagged
+        const uint2 *__restrict__ darc = A.down_arc;
+        const uint32_t *__restrict__ dc = A.dcore;
+        for (uint32_t e = beg; e < end; e += 8) {
+            uint2 a[8];
+            uint32_t l[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) a[u] = e + u < end ? darc[e + u] : make_uint2(0u, INF);
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) l[u] = e + u < end ? dc[((a[u].x & TAIL_MASK) << 6) + j] : INF;
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) {
+                dv = min(dv, sat_add(l[u], a[u].y));
+                const uint32_t k = e - beg + u;
+                if (k < 32 && e + u < end) {
+                    flag |= ((a[u].x & FLAGS) ? 1u : 0u) << k;
+                    in |= uint32_t(l[u] <= tau) << k;
+                }
+            }
+        }
+        A.dcore[(v << 6) + j] = dv;
+        const uint32_t cell = A.core_cell[v];
+        if (cell != NO_CELL) {
+            const uint32_t ecc = A.core_ecc[v];
+            const uint64_t bin = __ballot(dv <= tau), bout = __ballot(sat_add(dv, ecc) > tau);
+            if (j == 0) {
+                A.vin[v] = bin;
+                A.vout[v] = bout;
+            }
+        }
+        // straddling flagged entries: the recorded bits, or a walk over every entry beyond 32
+        const bool vin = dv <= tau;
+        const uint32_t lane = A.lane_base + j;
+        if (end - beg <= 32) {
+            uint32_t st = flag & (vin ? ~in : in);
+            while (__any(st != 0)) {
+                const bool have = st != 0;
+                const uint32_t k = have ? uint32_t(__ffs(st) - 1) : 0u;
+                st &= st - 1u;
+                const uint32_t x = have ? darc[beg + k].x : 0u;
+                push_key(x & FLAG_FWD, entry_key(lane, beg + k, 0u), s_keys, &s_n, A);
+                push_key(x & FLAG_REV, entry_key(lane, beg + k, 1u), s_keys, &s_n, A);
+            }
+        } else {
+            for (uint32_t e = beg; e < end; ++e) {   // uniform loop
+                const uint2 a = darc[e];
+                const bool str = (a.x & FLAGS) && ((dc[((a.x & TAIL_MASK) << 6) + j] <= tau) != vin);
+                if (A.dbg && str) atomicAdd(&A.dbg[2], 1ull);
+                push_key(str && (a.x & FLAG_FWD), entry_key(lane, e, 0u), s_keys, &s_n, A);
+                push_key(str && (a.x & FLAG_REV), entry_key(lane, e, 1u), s_keys, &s_n, A);
+            }
+        }
+    }
     keys_end(s_keys, &s_n, &s_base, A);
 }
 
@@ -609,12 +696,11 @@ struct CellArgs {
         *src_cell;
     const uint64_t *cmask;
     const uint4 *cmeta;
-    const uint2 *arc_rank;   // per downward entry: ranks of its forward and reverse arcs
     uint32_t *dist_out;
     uint64_t *vmask;   // vertex output: lane masks by position (nullptr: edges only)
     uint64_t *out_keys;
     uint32_t *out_count;
-    uint32_t out_cap, lane_base, lk, lg, num_cells, rb;
+    uint32_t out_cap, lane_base, lk, lg, num_cells;
 };
 
 // Cell workgroups have 256 or 512 threads (the cell_block knob); the item code reads blockDim.x.
@@ -697,9 +783,8 @@ __host__ __device__ __forceinline__ uint32_t cell_lds_words(uint32_t cnt, uint32
 __device__ __forceinline__ uint64_t cand_key(const CellArgs &A, uint32_t word, const uint32_t *s_off, uint32_t eb,
                                              uint64_t lanes, uint32_t q) {
     const uint32_t i = word & 0xFFFu, k = (word >> 12) & (CAND_K_MAX - 1u), j = (word >> 25) & 63u;
-    const uint2 rk = A.arc_rank[eb + s_off[i] + k];
     const uint32_t lane = A.lane_base + nth_set_bit(lanes, q + j);
-    return edge_key(lane, (word >> 31) ? rk.y : rk.x, A.rb);
+    return entry_key(lane, eb + s_off[i] + k, word >> 31);
 }
 
 // Wavefront-aggregated append of a candidate to the LDS list (count in ctl[0]); every lane of
@@ -1167,6 +1252,286 @@ k_cell_sweep(CellArgs A) {
     }
 }
 
+// ------------------------------------------------------------ cell sweep, one workgroup per cell
+//
+// One workgroup takes a whole active cell: it copies the cell's data into LDS once and sweeps
+// it for all the queries that activate the cell, up to G of them at a time (a lane chunk), so
+// a cell's data crosses HBM once per sweep and the level loop reads LDS only.  Within a chunk
+// of W lanes, thread t serves lane slot t mod W of vertex slot t / W of the current level; the
+// W slots of a vertex read the same entries and one LDS row of W labels per tail.  The levels
+// that fit the vertex slots of one wavefront (the top of the cell's hierarchy) are swept by
+// wavefront 0 alone, with wavefront-scope fences instead of workgroup barriers.  Vertices of
+// the cell's last level are tails of no entry (every entry goes from an earlier level to a
+// later one), so only the earlier levels' labels are stored.
+//
+// Cell data (one blob per cell, 16-byte aligned, a multiple of 4 words):
+//   off[cnt + 1]   entry offsets of the internal vertices (relative to the cell's first entry)
+//   lvl[nl + 1]    level starts, top level first; lvl[nl] = cnt
+//   refs[nrefs]    the core positions the cell's entries read
+//   (padding to an even word), then the entries, one word each in the packed form:
+//     bits [0, LB) tail's row (internal vertex i < stored: i; core ref r: stored + r),
+//     bit LB the forward original arc, bit LB + 1 the reverse one, bits [LB + 2, 32) the length
+//     (all ones: the dummy entry's infinite length),
+//   or two words each in the wide form (row | FWD bit 31 | REV bit 30, length), used when a
+//   length or a row index does not fit the packed word.
+// stored = lvl[nl - 1]: the rows of every level but the last.
+
+constexpr uint32_t C2_CAND = 1024;   // candidate words in LDS
+constexpr uint32_t C2_CTL = 4;       // control words: candidate count, output base
+constexpr uint32_t C2_THREADS = 512;
+
+struct Cell2Args {
+    const uint32_t *clist, *counters, *blob, *cblob, *cell_off, *cell_ebase, *dcore, *uslot, *uval, *taus,
+        *src_cell;
+    const uint64_t *cmask;
+    const uint4 *cmeta;   // (cnt, nl, nrefs, ne)
+    uint32_t *dist_out;
+    uint64_t *vmask;
+    uint64_t *out_keys;
+    uint32_t *out_count;
+    uint32_t out_cap, lane_base, lk, lgmax, lb;   // lb: row bits of a packed entry
+    unsigned long long *dbg;                      // branch counters (nullptr: none)
+};
+
+__host__ __device__ __forceinline__ uint32_t c2_head_words(uint32_t cnt, uint32_t nl, uint32_t nrefs) {
+    return ((cnt + 1) + (nl + 1) + nrefs + 1u) & ~1u;
+}
+__host__ __device__ __forceinline__ uint32_t c2_words(uint32_t cnt, uint32_t nl, uint32_t nrefs, uint32_t ne,
+                                                      bool packed) {
+    return (c2_head_words(cnt, nl, nrefs) + (packed ? ne : 2 * ne) + 3u) & ~3u;
+}
+// LDS words of a cell workgroup: the largest blob, label rows of W lanes, candidates, control.
+__host__ __device__ __forceinline__ uint32_t c2_lds_words(uint32_t blob_words, uint32_t rows, uint32_t w) {
+    return ((blob_words + 3u) & ~3u) + ((rows * w + 3u) & ~3u) + C2_CAND + C2_CTL;
+}
+
+
+// An entry decoded: tail row, length (INF for a dummy entry), forward / reverse original arc.
+struct C2Ent {
+    uint32_t row, w;
+    bool fwd, rev;
+};
+template <bool PACKED>
+__device__ __forceinline__ C2Ent c2_entry(const uint32_t *s_ent, uint32_t e, uint32_t lb) {
+    C2Ent r;
+    if (PACKED) {
+        const uint32_t x = s_ent[e];
+        r.row = x & ((1u << lb) - 1u);
+        r.fwd = (x >> lb) & 1u;
+        r.rev = (x >> (lb + 1)) & 1u;
+        const uint32_t wc = x >> (lb + 2), wmax = 0xFFFFFFFFu >> (lb + 2);
+        r.w = wc == wmax ? INF : wc;
+    } else {
+        const uint2 x = reinterpret_cast<const uint2 *>(s_ent)[e];
+        r.row = x.x & LOCAL_MASK;
+        r.fwd = (x.x & FLAG_FWD) != 0;
+        r.rev = (x.x & FLAG_REV) != 0;
+        r.w = x.y;
+    }
+    return r;
+}
+
+// Appends a candidate (the cell-local entry e, the lane's rank among the cell's active lanes,
+// the direction) to the LDS list, or writes it out at once when the list is full.
+__device__ __forceinline__ void c2_push(const Cell2Args &A, uint32_t *s_cand, uint32_t *s_ctl, uint32_t e,
+                                        uint32_t rank, uint32_t rev, uint32_t lane, uint32_t ebase) {
+    const uint32_t k = atomicAdd(&s_ctl[0], 1u);
+    if (k < C2_CAND) {
+        s_cand[k] = e | (rank << 25) | (rev << 31);
+    } else {
+        if (A.dbg) atomicAdd(&A.dbg[0], 1ull);
+        const uint32_t idx = atomicAdd(A.out_count, 1u);
+        if (idx < A.out_cap) A.out_keys[idx] = entry_key(lane, ebase + e, rev);
+    }
+}
+
+// Writes the listed candidates with one output reservation and empties the list.  Every thread
+// calls it with the same n (read between two barriers); it ends with a barrier.
+__device__ __forceinline__ void c2_flush(const Cell2Args &A, uint32_t n, uint32_t *s_cand, uint32_t *s_ctl,
+                                         uint64_t lanes, uint32_t ebase) {
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_ctl[1] = atomicAdd(A.out_count, n);
+    __syncthreads();
+    const uint32_t base = s_ctl[1];
+    for (uint32_t k = tid; k < n; k += blockDim.x) {
+        const uint32_t w = s_cand[k];
+        const uint32_t lane = A.lane_base + nth_set_bit(lanes, (w >> 25) & 63u);
+        if (base + k < A.out_cap) A.out_keys[base + k] = entry_key(lane, ebase + (w & 0x1FFFFFFu), w >> 31);
+    }
+    __syncthreads();
+    if (tid == 0) s_ctl[0] = 0;
+    __syncthreads();
+}
+
+// One vertex i of the current level for one lane slot j of the chunk (a thread's work; the W
+// slots of a vertex are consecutive threads, which read the same entries and the tail's row of
+// W labels).  tau, live (a real lane), up (its source lies in the cell: the upward labels
+// start the vertex's label), lane (the batch lane).
+template <bool PACKED>
+__device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t i, uint32_t j, uint32_t W,
+                                          const uint32_t *s_off, const uint32_t *s_ent, uint32_t *s_lab,
+                                          uint32_t stored, uint32_t tau, bool live, bool up, uint32_t lane,
+                                          uint32_t cb, uint32_t rank, uint32_t *s_cand, uint32_t *s_ctl,
+                                          uint32_t ebase, uint32_t lb) {
+    uint32_t dv = INF, e0 = 0, e1 = 0;
+    if (act) {
+        if (up) {   // a source in the cell: its upward label (host search) starts the label
+            const uint32_t sl = A.uslot[cb + i];
+            if (sl != NO_SLOT) dv = A.uval[(sl << A.lk) + lane];
+        }
+        e0 = s_off[i];
+        e1 = s_off[i + 1];
+    }
+    bool fin = false, fout = false;   // a flagged entry's tail in / out of range
+    for (uint32_t e = e0; e < e1; e += 2) {
+        const bool two = e + 1 < e1;
+        const C2Ent x0 = c2_entry<PACKED>(s_ent, e, lb);
+        const C2Ent x1 = c2_entry<PACKED>(s_ent, two ? e + 1 : e, lb);
+        const uint32_t t0 = s_lab[x0.row * W + j], t1 = s_lab[x1.row * W + j];
+        dv = min(dv, min(sat_add(t0, x0.w), sat_add(t1, two ? x1.w : INF)));
+        const bool f0 = x0.fwd || x0.rev, f1 = two && (x1.fwd || x1.rev);
+        fin |= (f0 && t0 <= tau) || (f1 && t1 <= tau);
+        fout |= (f0 && t0 > tau) || (f1 && t1 > tau);
+    }
+    const bool vin = dv <= tau;
+    if (act) {
+        if (i < stored) s_lab[i * W + j] = dv;
+        if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << A.lk) + lane] = dv;
+    }
+    if (A.vmask) {   // lanes in range, ORed over the vertex's W slots (consecutive threads)
+        uint64_t m = act && live && vin ? (1ull << lane) : 0ull;
+        for (uint32_t o = 1; o < W; o <<= 1) m |= (uint64_t)__shfl_xor((unsigned long long)m, (int)o);
+        if (act && j == 0 && m) atomicOr((unsigned long long *)&A.vmask[cb + i], (unsigned long long)m);
+    }
+    // isochrone edges at i: in range, the flagged entries with tails out of range; out of range,
+    // those with tails in range (a second walk, only where one exists)
+    if (!(act && live && (vin ? fout : fin))) return;
+    for (uint32_t e = e0; e < e1; ++e) {
+        const C2Ent x = c2_entry<PACKED>(s_ent, e, lb);
+        if (!(x.fwd || x.rev) || ((s_lab[x.row * W + j] <= tau) == vin)) continue;
+        if (x.fwd) c2_push(A, s_cand, s_ctl, e, rank, 0u, A.lane_base + lane, ebase);
+        if (x.rev) c2_push(A, s_cand, s_ctl, e, rank, 1u, A.lane_base + lane, ebase);
+    }
+}
+
+// Sweep of one lane chunk: ranks [q0, q0 + W) of the cell's active lanes (W a power of two).
+// Thread t serves lane slot t mod W of vertex slot t / W.  The leading levels that fit
+// wavefront 0 (64 / W vertices) are swept by it alone, with wavefront-scope fences between
+// them; the other wavefronts join at the first wider level.
+template <bool PACKED>
+__device__ __forceinline__ void c2_chunk(const Cell2Args &A, uint32_t *smem, uint32_t c, uint32_t q0, uint32_t W,
+                                         uint64_t lanes, uint32_t L, uint32_t cnt, uint32_t nl, uint32_t nrefs,
+                                         uint32_t words, uint32_t stored, uint32_t cb, uint32_t ebase) {
+    const uint32_t tid = threadIdx.x, T = blockDim.x;
+    const uint32_t lw = __builtin_ctz(W);
+    const uint32_t *s_off = smem, *s_lvl = smem + cnt + 1, *s_refs = s_lvl + nl + 1;
+    const uint32_t *s_ent = smem + c2_head_words(cnt, nl, nrefs);
+    uint32_t *s_lab = smem + ((words + 3u) & ~3u);
+    uint32_t *s_cand = s_lab + ((size_t(stored + nrefs) * (1u << A.lgmax) + 3u) & ~3u);
+    uint32_t *s_ctl = s_cand + C2_CAND;
+    const uint32_t j = tid & (W - 1);
+    const uint32_t rank = q0 + j;
+    const bool live = rank < L;
+    const uint32_t lane = nth_set_bit(lanes, live ? rank : q0);
+    const uint32_t tau = A.taus[lane];
+    const bool up = live && A.src_cell[lane] == c;
+    // the referenced core vertices' final labels, one (ref, slot) pair per thread
+    for (uint32_t r = tid >> lw; r < nrefs; r += T >> lw)
+        s_lab[(stored + r) * W + j] = A.dcore[(s_refs[r] << A.lk) + lane];
+    __syncthreads();
+    const uint32_t wslots = 64u >> lw;   // vertex slots of one wavefront
+    uint32_t l0 = 0;
+    while (l0 < nl && s_lvl[l0 + 1] - s_lvl[l0] <= wslots) ++l0;
+    const uint32_t per = T >> lw, wfirst = (tid & ~63u) >> lw;
+    for (uint32_t l = tid < 64 ? 0u : l0; l < nl; ++l) {
+        if (l == l0) __syncthreads();   // wavefront 0 done with the leading levels, the others waiting
+        const uint32_t a = s_lvl[l], b = s_lvl[l + 1];
+        if (A.dbg && tid == 0 && b - a > per) atomicAdd(&A.dbg[1], 1ull);
+        for (uint32_t base = a; base < b; base += per) {
+            if (base + wfirst >= b) break;   // whole wavefronts past the level's end
+            const uint32_t i = base + (tid >> lw);
+            c2_vertex<PACKED>(A, i < b, i, j, W, s_off, s_ent, s_lab, stored, tau, live, up, lane, cb, rank, s_cand,
+                              s_ctl, ebase, A.lb);
+        }
+        if (l < l0) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            __syncthreads();
+        }
+    }
+    if (l0 == nl) __syncthreads();
+}
+
+template <bool PACKED>
+__device__ __forceinline__ void c2_cell(const Cell2Args &A, uint32_t *smem, uint32_t c) {
+    const uint32_t tid = threadIdx.x, T = blockDim.x;
+    const uint4 meta = A.cmeta[c];
+    const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z, ne = meta.w;
+    const uint64_t lanes = A.cmask[c];
+    const uint32_t L = uint32_t(__popcll(lanes));
+    const uint32_t words = c2_words(cnt, nl, nrefs, ne, PACKED);
+    const uint32_t cb = A.cell_off[c], ebase = A.cell_ebase[c];
+    // copy the cell's data into LDS: every 16-byte load of a round is issued before its stores
+    {
+        const uint4 *g4 = reinterpret_cast<const uint4 *>(A.blob + A.cblob[c]);
+        uint4 *s4 = reinterpret_cast<uint4 *>(smem);
+        const uint32_t n4 = words >> 2, last = n4 - 1;   // a blob holds its offsets: n4 >= 1
+        for (uint32_t i = tid; i < n4; i += 4 * T) {
+            const uint4 v0 = g4[i], v1 = g4[min(i + T, last)], v2 = g4[min(i + 2 * T, last)];
+            const uint4 v3 = g4[min(i + 3 * T, last)];
+            s4[i] = v0;
+            if (i + T < n4) s4[i + T] = v1;
+            if (i + 2 * T < n4) s4[i + 2 * T] = v2;
+            if (i + 3 * T < n4) s4[i + 3 * T] = v3;
+        }
+    }
+    __syncthreads();
+    const uint32_t stored = nl ? smem[cnt + 1 + nl - 1] : 0u;
+    uint32_t *s_lab = smem + ((words + 3u) & ~3u);
+    uint32_t *s_cand = s_lab + ((size_t(stored + nrefs) * (1u << A.lgmax) + 3u) & ~3u);
+    uint32_t *ctl = s_cand + C2_CAND;
+    if (tid == 0) ctl[0] = 0;
+    // lane chunks of up to 2^lgmax lanes; the last one as narrow as its lanes allow
+    const uint32_t G = 1u << A.lgmax;
+    for (uint32_t q0 = 0; q0 < L; q0 += G) {
+        const uint32_t rest = min(G, L - q0);
+        uint32_t W = 1;
+        while (W < rest) W <<= 1;   // the narrowest power of two that holds the chunk's lanes
+        c2_chunk<PACKED>(A, smem, c, q0, W, lanes, L, cnt, nl, nrefs, words, stored, cb, ebase);
+        // every thread passed the chunk's last barrier: the count is stable
+        const uint32_t n = ctl[0];
+        if (n > C2_CAND / 2 || (q0 + G >= L && n > 0)) c2_flush(A, min(n, C2_CAND), s_cand, ctl, lanes, ebase);
+    }
+}
+
+// The cell sweep over the active cells: XCD x (block index mod 8) takes the x-th eighth of the
+// active-cell list (neighbouring cells share core rows in that XCD's L2) and its workgroups
+// stride through it.  No workgroup waits for another.
+template <bool PACKED>
+__global__ void __launch_bounds__(C2_THREADS) k_cell_chunks(Cell2Args A) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t total = A.counters[1];
+    const uint32_t rows = (total + 7u) >> 3;
+    const uint32_t x = blockIdx.x & 7u, stride = gridDim.x >> 3;
+    const uint32_t end = min(total, (x + 1u) * rows);
+    for (uint32_t it = x * rows + (blockIdx.x >> 3); it < end; it += stride) {
+        c2_cell<PACKED>(A, smem, A.clist[it]);
+        __syncthreads();   // the next cell overwrites the LDS
+    }
+}
+
+// Entry keys -> output keys: lane << rb | the rank of the entry's forward or reverse arc.
+__global__ void k_rank_keys(uint64_t *__restrict__ keys, const uint32_t *__restrict__ count, uint32_t cap,
+                            const uint2 *__restrict__ arc_rank, uint32_t rb) {
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        const uint2 r = arc_rank[uint32_t(k >> 1)];
+        keys[i] = (uint64_t(uint32_t(k >> 33)) << rb) | ((k & 1u) ? r.y : r.x);
+    }
+}
+
 // ----------------------------------------------------------------- host side
 
 #define HIPCHK(x)                                                                   \
@@ -1296,16 +1661,21 @@ int DevGraph::select_targets(const iso::Prep &P, const uint32_t *targets, uint32
 
 // Workgroups of a cell-sweep variant that fit one compute unit with `lds` bytes of LDS each
 // (cached per variant and size).
-int DevGraph::cell_occupancy(bool staged, uint32_t threads, size_t lds, uint32_t &per_cu) {
-    const uint64_t key = (uint64_t(staged) << 40) | (uint64_t(threads) << 24) | lds;
+int DevGraph::cell_occupancy(uint32_t variant, uint32_t threads, size_t lds, uint32_t &per_cu) {
+    const uint64_t key = (uint64_t(variant) << 40) | (uint64_t(threads) << 24) | lds;
+    std::lock_guard<std::mutex> lock(occ_mu);
     auto f = occ_cache.find(key);
     if (f != occ_cache.end()) {
         per_cu = f->second;
         return 0;
     }
+    // variants: 0 level pipeline, 1 staged work item, 2 / 3 one workgroup per cell (wide / packed)
+    const void *fn = variant == 0   ? (const void *)k_cell_sweep<false>
+                     : variant == 1 ? (const void *)k_cell_sweep<true>
+                     : variant == 2 ? (const void *)k_cell_chunks<false>
+                                    : (const void *)k_cell_chunks<true>;
     int nb = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, staged ? (const void *)k_cell_sweep<true> : (const void *)k_cell_sweep<false>, int(threads), lds));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, int(threads), lds));
     per_cu = uint32_t(std::max(1, nb));
     occ_cache[key] = per_cu;
     return 0;
@@ -1362,6 +1732,93 @@ int DevGraph::upload_arc_ranks(const iso::Prep &P) {
     if ((r = dev_alloc_copy(&d_arc_rank, rank, bytes))) return r;
     if ((r = dev_alloc_copy(&d_arc_pair, pair, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cell_ebase, ebase, bytes))) return r;
+    return 0;
+}
+
+// Cell data of k_cell_chunks (layout at c2_head_words): per cell its entry offsets, level
+// starts, core refs and entries.  An entry's tail becomes a row index: internal vertex i ->
+// i, core ref r -> stored + r, where stored is the first vertex of the cell's last level (no
+// entry has its tail there: every entry goes from an earlier level to a later one).  The
+// entries are packed into one word (row bits lb2, two flags, length) when every cell's rows
+// and every finite length fit, else kept as two words.
+int DevGraph::upload_cell_blobs2(const iso::Prep &P, const std::vector<std::vector<uint32_t>> &refs_of) {
+    std::vector<uint32_t> stored(num_cells, 0);
+    max_rows2 = 1;
+    uint32_t wmax_seen = 0;
+    for (uint32_t c = 0; c < num_cells; ++c) {
+        const uint32_t b = P.cell_off[c], e = P.cell_off[c + 1];
+        const uint32_t nl = P.cell_lvl_ptr[c + 1] - P.cell_lvl_ptr[c];
+        stored[c] = nl ? P.cell_lvl[P.cell_lvl_ptr[c + 1] - 1] - b : 0u;
+        max_rows2 = std::max(max_rows2, stored[c] + uint32_t(refs_of[c].size()));
+        if (P.down_off[e] - P.down_off[b] >= (1u << 25)) {
+            set_error("a cell has 2^25 or more downward entries");
+            return -1;
+        }
+        for (uint64_t k = P.down_off[b]; k < P.down_off[e]; ++k) {
+            const uint32_t t = P.down_arc[2 * k] & TAIL_MASK, w = P.down_arc[2 * k + 1];
+            if (t >= b && t - b >= stored[c]) {
+                set_error("a cell's last level holds the tail of a downward entry");
+                return -1;
+            }
+            if (w != INF) wmax_seen = std::max(wmax_seen, w);
+        }
+    }
+    lb2 = std::max<uint32_t>(1, ilog2(max_rows2));
+    packed2 = lb2 <= 16 && uint64_t(wmax_seen) < (uint64_t(1) << (30 - lb2)) - 1;
+    std::vector<uint32_t> cblob2(std::max<uint32_t>(1, num_cells), 0);
+    uint64_t total = 0;
+    max_blob2_words = 0;
+    for (uint32_t c = 0; c < num_cells; ++c) {
+        const uint32_t cnt = P.cell_off[c + 1] - P.cell_off[c], nl = P.cell_lvl_ptr[c + 1] - P.cell_lvl_ptr[c];
+        const uint32_t ne = P.down_off[P.cell_off[c + 1]] - P.down_off[P.cell_off[c]];
+        const uint32_t w = c2_words(cnt, nl, uint32_t(refs_of[c].size()), ne, packed2);
+        cblob2[c] = uint32_t(total);
+        total += w;
+        max_blob2_words = std::max(max_blob2_words, w);
+        if (total >= (uint64_t(1) << 32)) {
+            set_error("cell data exceed 2^32 words");
+            return -1;
+        }
+    }
+    std::vector<uint32_t> blob(std::max<uint64_t>(4, total), 0);
+    std::vector<uint32_t> ref_index(std::max<uint32_t>(1, n_core), 0);
+    const uint32_t wcode_inf = packed2 ? (0xFFFFFFFFu >> (lb2 + 2)) : 0u;
+    for (uint32_t c = 0; c < num_cells; ++c) {
+        const uint32_t b = P.cell_off[c], e = P.cell_off[c + 1], cnt = e - b;
+        const uint32_t nl = P.cell_lvl_ptr[c + 1] - P.cell_lvl_ptr[c];
+        const auto &refs = refs_of[c];
+        const uint32_t nr = uint32_t(refs.size());
+        for (uint32_t r2 = 0; r2 < nr; ++r2) ref_index[refs[r2]] = r2;
+        uint32_t *w = blob.data() + cblob2[c];
+        const uint32_t base_e = P.down_off[b];
+        for (uint32_t i = 0; i <= cnt; ++i) w[i] = P.down_off[b + i] - base_e;
+        uint32_t *lv = w + cnt + 1;
+        for (uint32_t l = 0; l < nl; ++l) lv[l] = P.cell_lvl[P.cell_lvl_ptr[c] + l] - b;
+        lv[nl] = cnt;
+        uint32_t *rf = lv + nl + 1;
+        for (uint32_t r2 = 0; r2 < nr; ++r2) rf[r2] = refs[r2];
+        uint32_t *en = w + c2_head_words(cnt, nl, nr);
+        for (uint32_t k = 0; k < P.down_off[e] - base_e; ++k) {
+            const uint32_t x = P.down_arc[2 * uint64_t(base_e + k)], t = x & TAIL_MASK;
+            const uint32_t len = P.down_arc[2 * uint64_t(base_e + k) + 1];
+            const uint32_t row = t >= b ? t - b : stored[c] + ref_index[t];
+            if (packed2) {
+                const uint32_t code = len == INF ? wcode_inf : len;
+                en[k] = row | (((x & FLAG_FWD) ? 1u : 0u) << lb2) | (((x & FLAG_REV) ? 1u : 0u) << (lb2 + 1)) |
+                        (code << (lb2 + 2));
+            } else {
+                en[2 * k] = row | (x & FLAGS);
+                en[2 * k + 1] = len;
+            }
+        }
+    }
+    int r;
+    if ((r = dev_alloc_copy(&d_blob2, blob, bytes))) return r;
+    if ((r = dev_alloc_copy(&d_cblob2, cblob2, bytes))) return r;
+    HIPCHK(hipFuncSetAttribute((const void *)k_cell_chunks<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(LDS_MAX)));
+    HIPCHK(hipFuncSetAttribute((const void *)k_cell_chunks<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(LDS_MAX)));
     return 0;
 }
 
@@ -1539,6 +1996,9 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     if ((r = dev_alloc_copy(&d_blob, blob, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cblob, cblob, bytes))) return r;
     if ((r = dev_alloc_copy(&d_cmeta, cmeta, bytes))) return r;
+    blob.clear();
+    blob.shrink_to_fit();
+    if ((r = upload_cell_blobs2(P, refs_of))) return r;
     if ((r = upload_arc_ranks(P))) return r;
     max_cell_levels = 0;
     for (uint32_t c = 0; c < num_cells; ++c) max_cell_levels = std::max(max_cell_levels, uint32_t(cmeta[c].y));
@@ -1583,7 +2043,7 @@ void DevGraph::release() {
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
-                    d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair};
+                    d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair, d_blob2, d_cblob2};
     for (void *p : ptrs) if (p) hipFree(p);
     (void)hipGetLastError();   // a failed free must not surface in another handle's next check
     device = -1;
@@ -1591,7 +2051,8 @@ void DevGraph::release() {
 
 void QueryBufs::release() {
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
-                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin, d_rlab, d_prof};
+                    d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin, d_rlab, d_prof,
+                    d_dbg};
     for (void *p : ptrs) if (p) hipFree(p);
     if (h_pinned) hipHostFree(h_pinned);
     *this = QueryBufs();
@@ -1615,8 +2076,13 @@ static int ensure(void **p, size_t &have, size_t need) {
 size_t DevGraph::ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const {
     uint32_t K = 1;
     while (K < k) K <<= 1;
+    // temporary storage of the radix sort over cap keys (the size query allocates nothing)
+    size_t sort_tmp = 0;
+    if (hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                          int(std::min<size_t>(cap, size_t(INT32_MAX))), 0, 64) != hipSuccess)
+        sort_tmp = cap * 8 + (1 << 20);
     return size_t(n_core) * K * 4 + size_t(n) * 4 + upward_entries * (K + 3) * 4 + size_t(n_core) * 16 +
-           size_t(num_cells) * (3 + MAX_LANES) * 4 + 2 * cap * 8 + (1 << 20);
+           size_t(num_cells) * (3 + MAX_LANES) * 4 + 2 * cap * 8 + sort_tmp + (1 << 20);
 }
 
 int DevGraph::run(SweepCtx &C, const RunArgs &A, RunResult &R) {
@@ -1647,7 +2113,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
     int r;
-    if (!B.d_uslot) {
+    if (!B.d_uslot) {   // the slot table is all NO_SLOT between sweeps
         if ((r = ensure((void **)&B.d_uslot, B.sz_uslot, size_t(n) * 4))) return r;
         k_fill<<<dim3(2048), dim3(256), 0, s>>>(B.d_uslot, NO_SLOT, uint64_t(n));
     }
@@ -1772,15 +2238,17 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     uint64_t *d_cmask = reinterpret_cast<uint64_t *>(B.d_list);
     uint32_t *d_clist = B.d_list + 2 * size_t(num_cells), *d_items = d_clist + num_cells;
     CoreArgs CA{d_down_off, d_down_arc, B.d_dcore, B.d_uslot, B.d_uval, d_core_cell, d_core_ecc, d_taus,
-                d_arc_rank, vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, rank_bits};
+                vin, vout, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, nullptr};
     const bool prof_on = C.prof.on;
     // the core sweep (table and core levels, one launch per level) has only per-context kernel
     // arguments; with use_graph it is captured once per signature and replayed.  The cell
     // flags, the active cells and the cell sweep (three launches) follow it eagerly, so the
     // phase events of the profile sit between whole launches in both cases.
     const bool cd = A.core_dijkstra;
-    const bool use_graph = A.use_graph && !cd;   // isoPHAST-CD's core part is two launches: no graph
-    GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block, uint32_t(A.cell_lds_bytes), xcap,
+    // isoPHAST-CD's core part is two launches: no graph; the branch counters are not captured
+    const bool use_graph = A.use_graph && !cd && !A.debug;
+    GraphSig sig{K, A.mode_plain ? 1u : 0u, A.want_dist ? 1u : 0u, A.block | (A.core64 ? 1u << 31 : 0u),
+                 uint32_t(A.cell_lds_bytes), xcap,
                  A.cell_stage, A.cell_block, A.table_x, A.table_levels, uint64_t(cap), {uint64_t(uintptr_t(B.d_dcore)), uint64_t(uintptr_t(B.d_uslot)),
                                  uint64_t(uintptr_t(B.d_uval)), uint64_t(uintptr_t(B.d_xin)),
                                  uint64_t(uintptr_t(B.d_keys)), uint64_t(uintptr_t(B.d_flags)),
@@ -1789,11 +2257,18 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                                  uint64_t(uintptr_t(B.d_taus))}};
     // cell sweep plan: variant, lanes per work item (as many as fit the LDS budget), LDS per
     // workgroup and a grid of resident workgroups (no more than there can be items), a multiple of 8
-    bool staged = A.cell_stage == 1 && size_t(staged_lds_words(max_blob_words, max_cell_labels, 0)) * 4 <= LDS_MAX;
+    // one workgroup per cell (cell_stage 2) when a cell's data and one lane's rows fit the LDS,
+    // else the per-item variants
+    const bool chunks = A.cell_stage == 2 && size_t(c2_lds_words(max_blob2_words, max_rows2, 1)) * 4 <= LDS_MAX;
+    bool staged = !chunks && A.cell_stage == 1 &&
+                  size_t(staged_lds_words(max_blob_words, max_cell_labels, 0)) * 4 <= LDS_MAX;
+    const uint32_t variant = chunks ? (packed2 ? 3u : 2u) : staged ? 1u : 0u;
+    const uint32_t cell_threads = chunks ? C2_THREADS : A.cell_block;
     uint32_t cell_lg = 0, cell_grid = 8;
     size_t lds = 0;
     if (num_cells > 0) {
         auto lds_of = [&](uint32_t g) {
+            if (chunks) return size_t(c2_lds_words(max_blob2_words, max_rows2, 1u << g)) * 4;
             return size_t(staged ? staged_lds_words(max_blob_words, max_cell_labels, g)
                                  : cell_lds_words(max_cell_cnt, max_cell_levels, max_cell_labels, g)) * 4;
         };
@@ -1805,20 +2280,25 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             return -2;
         }
         uint32_t per_cu = 0;
-        if ((r = cell_occupancy(staged, A.cell_block, lds, per_cu))) return r;
+        if ((r = cell_occupancy(variant, cell_threads, lds, per_cu))) return r;
         if (A.cell_per_cu) per_cu = std::min(per_cu, A.cell_per_cu);
-        uint64_t most = uint64_t(num_cells) << (lk - cell_lg);
+        uint64_t most = chunks ? uint64_t(num_cells) : uint64_t(num_cells) << (lk - cell_lg);
         uint64_t want = std::min<uint64_t>(uint64_t(per_cu) * uint64_t(std::max(1, num_cus)), most);
         cell_grid = uint32_t(std::max<uint64_t>(8, (want + 7) / 8 * 8));
     }
+    unsigned long long *dbg = nullptr;
+    if (A.debug) {   // summed over calls; cleared when first allocated and by iso_debug_enable
+        if (!B.d_dbg) {
+            if ((r = ensure((void **)&B.d_dbg, B.sz_dbg, 8 * sizeof(uint64_t)))) return r;
+            k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_dbg), 0u, 16);
+        }
+        dbg = B.d_dbg;
+    }
+    CA.dbg = dbg;
     bool replay = use_graph && C.graph_exec && std::memcmp(&sig, &C.sig, sizeof sig) == 0;
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[0], s));
-    if (use_graph && !replay) {
-        if (C.graph_exec) hipGraphExecDestroy(C.graph_exec);
-        C.graph_exec = nullptr;
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    }
-    // core sweep: the table levels as one (min,+) product, then one launch per level
+    // core sweep: the table levels as one (min,+) product, then one launch per level (captured
+    // once per signature and replayed with use_graph)
     size_t nlev = core_lvl.size() - 1;
     const uint32_t tx = A.table_x;
     size_t top = A.table_levels;
@@ -1837,8 +2317,6 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             k_top_finish<<<dim3(uint32_t(((uint64_t(n_core) << (lk + ls)) + 255) / 256)), dim3(256), 0, s>>>(
                 CA, n_core, ls);
         }
-    } else if (replay) {
-        HIPCHK(hipGraphLaunch(C.graph_exec, s));
     } else {
         if (tx > 0) {
             k_fill<<<dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (tx * K + 255) / 256))), dim3(256), 0, s>>>(
@@ -1856,28 +2334,44 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                 k_top_finish<<<dim3(uint32_t(((uint64_t(tx) << (lk + ls)) + 255) / 256)), dim3(256), 0, s>>>(CA, tx, ls);
             }
         }
-        const uint32_t blk = A.block;
-        for (size_t l = top; l < nlev; ++l) {
-            uint32_t vb = core_lvl[l], ve = core_lvl[l + 1];
-            uint32_t ls = level_ls(ve - vb, core_lvl_entries[l + 1] - core_lvl_entries[l], K);
-            uint64_t threads = uint64_t(ve - vb) << (lk + ls);
-            uint32_t grid = uint32_t((threads + blk - 1) / blk);
-            grid = (grid + 7u) & ~7u;   // a multiple of 8 (the block mapping assumes it)
-            k_core_level<<<dim3(grid), dim3(blk), 0, s>>>(CA, ls, vb, ve);
+        if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[6], s));
+        if (replay) {
+            HIPCHK(hipGraphLaunch(C.graph_exec, s));
+        } else {
+            if (use_graph) {
+                if (C.graph_exec) hipGraphExecDestroy(C.graph_exec);
+                C.graph_exec = nullptr;
+                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            }
+            const uint32_t blk = A.block;
+            for (size_t l = top; l < nlev; ++l) {
+                uint32_t vb = core_lvl[l], ve = core_lvl[l + 1];
+                if (K == 64 && A.core64) {   // one wavefront per vertex, 4 per workgroup
+                    uint32_t grid = ((ve - vb + 3) / 4 + 7u) & ~7u;
+                    k_core_level64<<<dim3(grid), dim3(256), 0, s>>>(CA, vb, ve);
+                    continue;
+                }
+                uint32_t ls = level_ls(ve - vb, core_lvl_entries[l + 1] - core_lvl_entries[l], K);
+                uint64_t threads = uint64_t(ve - vb) << (lk + ls);
+                uint32_t grid = uint32_t((threads + blk - 1) / blk);
+                grid = (grid + 7u) & ~7u;   // a multiple of 8 (the block mapping assumes it)
+                k_core_level<<<dim3(grid), dim3(blk), 0, s>>>(CA, ls, vb, ve);
+            }
+            if (use_graph) {
+                hipGraph_t graph = nullptr;
+                HIPCHK(hipStreamEndCapture(s, &graph));
+                hipError_t ie = hipGraphInstantiate(&C.graph_exec, graph, nullptr, nullptr, 0);
+                hipGraphDestroy(graph);
+                if (ie != hipSuccess) {
+                    C.graph_exec = nullptr;
+                    set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+                    return -3;
+                }
+                C.sig = sig;
+                HIPCHK(hipGraphLaunch(C.graph_exec, s));
+            }
         }
-    }
-    if (use_graph && !replay) {
-        hipGraph_t graph = nullptr;
-        HIPCHK(hipStreamEndCapture(s, &graph));
-        hipError_t ie = hipGraphInstantiate(&C.graph_exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (ie != hipSuccess) {
-            C.graph_exec = nullptr;
-            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-            return -3;
-        }
-        C.sig = sig;
-        HIPCHK(hipGraphLaunch(C.graph_exec, s));
+        if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[7], s));
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[1], s));
     if (vmode && n_core > 0)   // vertex output: lane masks of the core positions
@@ -1893,15 +2387,26 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         if (vmode)   // internal positions: the cells left out because they lie wholly in range
             k_vmask_cells<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(B.d_cin, d_cmask, d_cell_off, num_cells,
                                                                            B.d_vmask);
-        CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot, B.d_uval,
-                    d_taus, d_src, d_cmask, d_cmeta, d_arc_rank, A.want_dist ? B.d_dist : nullptr,
-                    vmode ? B.d_vmask : nullptr, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg, num_cells,
-                    rank_bits};
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
-        if (staged)
-            k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
-        else
-            k_cell_sweep<false><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
+        if (chunks) {
+            Cell2Args LA{d_clist, B.d_counters, d_blob2, d_cblob2, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot,
+                         B.d_uval, d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr,
+                         vmode ? B.d_vmask : nullptr, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg,
+                         lb2, dbg};
+            if (packed2)
+                k_cell_chunks<true><<<dim3(cell_grid), dim3(C2_THREADS), lds, s>>>(LA);
+            else
+                k_cell_chunks<false><<<dim3(cell_grid), dim3(C2_THREADS), lds, s>>>(LA);
+        } else {
+            CellArgs LA{d_items, n_items, d_cblob, d_blob, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot, B.d_uval,
+                        d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr,
+                        vmode ? B.d_vmask : nullptr, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg,
+                        num_cells};
+            if (staged)
+                k_cell_sweep<true><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
+            else
+                k_cell_sweep<false><<<dim3(cell_grid), dim3(A.cell_block), lds, s>>>(LA);
+        }
     } else if (prof_on) {
         HIPCHK(hipEventRecord(C.prof.ev[2], s));
     }
@@ -1909,16 +2414,20 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     if (prof_on && num_cells > 0) {   // after the last phase event: not part of any phase's time
         if ((r = ensure((void **)&B.d_prof, B.sz_prof, 8 * sizeof(uint64_t)))) return r;
         if (!C.prof.acc_ready) {
-            k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_prof), 0u, 16);
+            k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_prof), 0u, 16);   // 8 sums
             C.prof.acc_ready = true;
         }
         k_prof_cells<<<dim3(64), dim3(256), 0, s>>>(d_clist, B.d_counters, d_cmask, d_cmeta,
-                                                   reinterpret_cast<unsigned long long *>(B.d_prof));
+                                                   reinterpret_cast<unsigned long long *>(B.d_prof),
+                                                   chunks ? (packed2 ? 2u : 1u) : 0u, cell_lg);
     }
     if (vmode) {   // lane masks by position -> one bitmap row per lane over the original ids
         const uint32_t W = (n + 63) / 64;
         k_vmask_out<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(B.d_vmask, d_pos, n, W, A.lanes, A.vbits);
     }
+    if (!vmode && cap > 0)   // entry keys -> (lane, arc rank) keys for the sort
+        k_rank_keys<<<dim3(uint32_t(std::min<size_t>(1024, (cap + 255) / 256))), dim3(256), 0, s>>>(
+            B.d_keys, out_count, uint32_t(cap), d_arc_rank, rank_bits);
     HIPCHK(hipGetLastError());
     if (nu) k_uset_clear<<<dim3((nu + 255) / 256), dim3(256), 0, s>>>(B.d_uslot, d_upos, nu);
     HIPCHK(hipMemcpyAsync(C.h_counters, B.d_counters, 16, hipMemcpyDeviceToHost, s));
@@ -1927,6 +2436,8 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     C.K = K;
     C.lk = lk;
     C.lg = lg;
+    C.cell_variant = variant;
+    C.levels_timed = !cd && n_core > 0;
     C.lanes = A.lanes;
     C.lane_base = A.lane_base;
     C.cap = cap;
@@ -1996,14 +2507,20 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
         prof.core_entries += core_entries;
         // offsets + entries + cell ids and eccentricities + k labels written and read back once
         prof.core_bytes += 4ull * (n_core + 1) + 8ull * core_entries + 8ull * n_core + uint64_t(K) * 8ull * n_core;
+        if (C.levels_timed) {   // the level launches below the table (k_core_level)
+            HIPCHK(hipEventElapsedTime(&ms, prof.ev[6], prof.ev[7]));
+            prof.level_ms += ms;
+            prof.level_launches += C.nlev - C.top;
+            const uint64_t nv = n_core - core_lvl[C.top], ne = core_entries - core_lvl_entries[C.top];
+            prof.level_bytes += 4ull * (nv + 1) + 8ull * ne + 8ull * nv + uint64_t(K) * 8ull * nv;
+        }
         if (num_cells > 0) {
             HIPCHK(hipEventElapsedTime(&ms, prof.ev[1], prof.ev[2]));
             prof.active_ms += ms;
             HIPCHK(hipEventElapsedTime(&ms, prof.ev[2], prof.ev[3]));
             prof.cell_ms += ms;
             prof.cell_launches++;
-            prof.cell_items += C.h_counters[2];
-            // the per-cell counts and bytes are summed on the device (k_prof_cells)
+            // the per-cell counts, work items and bytes are summed on the device (k_prof_cells)
         }
     }
     if (C.vertex_mode) {   // the vertex bitmaps are written; the edge keys are not used

@@ -295,16 +295,18 @@ def test_stall_on_demand_changes_nothing(road50k):
 
 
 def test_results_identical_across_tuning(road50k):
-    """Block size, LDS budget per cell workgroup and lanes per launch change only the schedule."""
+    """Block size, LDS budget per cell workgroup, lanes per launch, the cell-sweep variant and
+    the core-level kernel change only the schedule."""
     _identical_across_tuning(road50k, ((64, 16, 8, 0, 0), (1024, 160, 24, 0, 0), (256, 64, 3, 0, 1),
                                        (512, 24, 16, 0, 0), (256, 40, 64, 0, 1), (128, 160, 64, 0, 1),
-                                       (256, 16, 5, 0, 1)))
+                                       (256, 16, 5, 0, 1), (256, 64, 64, 2, 2), (256, 16, 64, 0, 2),
+                                       (512, 160, 64, 0, 2), (256, 32, 12, 2, 2), (128, 96, 33, 0, 2)))
 
 
 @pytest.mark.skip(reason="core_mode=1 (all core levels in one cooperative launch with a grid barrier "
                          "per level) hung on the device at its first launch (road50k, 32 lanes, grid of "
-                         "8 blocks x 256 CUs); no cause in the kernel was found, so the mode is switched "
-                         "off and iso_set_tuning rejects it")
+                         "8 blocks x 256 CUs); no cause in the kernel was found, so the variant was removed "
+                         "and iso_set_tuning rejects core_mode=1")
 def test_results_identical_cooperative_core(road50k):
     _identical_across_tuning(road50k, ((1024, 160, 24, 1, 0), (256, 64, 3, 1, 0), (256, 40, 64, 1, 0)))
 

@@ -291,7 +291,8 @@ def test_abi_error_paths():
     with pytest.raises(iso.IsoError) as e:
         G.set_tuning(lanes_per_launch=65)
     assert e.value.code == iso.ISO_EINVAL
-    for bad in (dict(block=96), dict(cell_lds_kb=8), dict(use_graph=2), dict(core_mode=1), dict(cell_stage=2),
+    for bad in (dict(block=96), dict(cell_lds_kb=8), dict(use_graph=2), dict(core_mode=1), dict(core_mode=3),
+                dict(cell_stage=3),
                 dict(cell_block=128), dict(table_max=16385), dict(stall=2)):
         with pytest.raises(iso.IsoError) as e:
             G.set_tuning(**bad)
