@@ -174,6 +174,25 @@ int iso_query_batch_device(iso_graph *g, size_t k, const uint32_t *sources, cons
                            uint64_t *total, void *stream);
 
 /*
+ * iso_query_batch_device for callers that cannot allocate memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments, checks, results
+ * and errors, but the call makes no device or pinned-host allocation (no hipMalloc,
+ * hipHostMalloc, hipFree, and no allocating library routine).  Its device buffers are carved
+ * from a static scratch array of 64 MiB that every GPU the library runs on holds until the
+ * process ends (the stream, events and a 4 MiB pinned staging block of this path are made when
+ * the graph is loaded); host-side bookkeeping still uses the C++ heap.  The queries run one
+ * sweep of up to lanes_per_launch (iso_tuning) at a time.  A sweep whose buffers (for k lanes
+ * about n * 4 + n_core * k * 4 + n_core * 16 + num_cells * 268 bytes) or isochrone edges (16
+ * bytes each plus the sort's temporary storage) do not fit the scratch fails with ISO_ENOMEM
+ * and a message; use fewer queries per sweep.  Calls that overlap on one GPU share its scratch
+ * and race: the caller must not run two of them at once on the same device, even on different
+ * graphs.
+ */
+int iso_query_batch_device_noalloc(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus,
+                                   int mode, uint32_t *pairs, uint64_t cap, uint32_t *offsets,
+                                   uint64_t *total, void *stream);
+
+/*
  * The other output that Section 3 says every approach can serve: the set of
  * vertices in range, d(s, v) <= tau, instead of the isochrone edges.  In
  * ISO_MODE_CELLS the internal vertices of a cell that is not swept for a

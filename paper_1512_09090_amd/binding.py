@@ -133,6 +133,7 @@ def lib():
                                   C.POINTER(C.c_size_t)]
     L.iso_query_batch_device.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.c_void_p, C.c_uint64,
                                          C.c_void_p, C.POINTER(C.c_uint64), C.c_void_p]
+    L.iso_query_batch_device_noalloc.argtypes = L.iso_query_batch_device.argtypes
     L.iso_query_batch_vertices_device.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.c_void_p,
                                                   C.c_void_p]
     L.iso_query_vertices.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.POINTER(_U32P),
@@ -293,7 +294,11 @@ class Graph:
         flat = _edges_to_numpy(ptr, total)
         return [flat[offsets[j]:offsets[j + 1]] for j in range(k)]
 
-    def query_batch_device(self, sources, taus, mode, pairs, offsets, stream=None) -> int:
+    def query_batch_device_noalloc(self, sources, taus, mode, pairs, offsets, stream=None) -> int:
+        """query_batch_device through iso_query_batch_device_noalloc (no allocation in the call)."""
+        return self.query_batch_device(sources, taus, mode, pairs, offsets, stream, noalloc=True)
+
+    def query_batch_device(self, sources, taus, mode, pairs, offsets, stream=None, noalloc=False) -> int:
         """Edges of k queries written to device memory: `pairs` (cap x 2, 32-bit integers) and
         `offsets` (k + 1, 32-bit integers) are contiguous torch tensors on the graph's device;
         `stream` (default: torch's current stream) is waited for before they are written.
@@ -311,9 +316,9 @@ class Graph:
             if need is not None and x.numel() < need:
                 raise IsoError(ISO_EINVAL, f"{name} needs {need} entries")
         total = C.c_uint64()
-        st = lib().iso_query_batch_device(self._h, k, sp, tp, int(mode), C.c_void_p(pairs.data_ptr()),
-                                          pairs.numel() // 2, C.c_void_p(offsets.data_ptr()), C.byref(total),
-                                          C.c_void_p(stream))
+        fn = lib().iso_query_batch_device_noalloc if noalloc else lib().iso_query_batch_device
+        st = fn(self._h, k, sp, tp, int(mode), C.c_void_p(pairs.data_ptr()), pairs.numel() // 2,
+                C.c_void_p(offsets.data_ptr()), C.byref(total), C.c_void_p(stream))
         if st == ISO_ESPACE:
             e = IsoError(st, lib().iso_last_error().decode(errors="replace"))
             e.total = total.value

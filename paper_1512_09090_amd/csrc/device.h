@@ -22,6 +22,9 @@ constexpr uint32_t TABLE_MAX = 16384;           // vertices of the top-of-hierar
 constexpr uint32_t TABLE_DEFAULT = TABLE_MAX;   // vertices of the levels merged into it by default
 constexpr uint32_t MAX_LANES = 64;
 constexpr uint32_t MAX_CELLS = 1u << 24;   // cell ids share a 32-bit work item with a width shift and a lane chunk
+// static device scratch of the no-allocation entry point (per GPU) and its pinned staging block
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+constexpr size_t FIXED_STAGE_BYTES = size_t(4) << 20;
 
 struct TargetSet;
 
@@ -45,6 +48,7 @@ struct RunArgs {
     bool want_dist = false;
     bool debug = false;          // count rare kernel branches (QueryBufs::d_dbg)
     bool core64 = true;          // 64 queries per sweep: core levels one wavefront per vertex
+    bool fill_uslot = false;     // refill the slot table first (its memory is shared with other calls)
     size_t out_cap = 0;          // capacity of the edge-key buffer
     uint32_t table_x = 0;        // top table used: core positions [0, table_x), the first table_levels levels
     uint32_t table_levels = 0;
@@ -119,6 +123,7 @@ struct QueryBufs {
     unsigned long long *d_dbg = nullptr;               // branch counters of the sweep kernels (8 words)
     uint32_t *d_lane_off = nullptr;   // MAX_LANES + 1 lane starts of the decoded edges
     void *d_sort_tmp = nullptr, *h_pinned = nullptr;
+    bool fixed = false;   // carved from the static scratch (iso_query_batch_device_noalloc): never freed or grown
     size_t sz_dcore = 0, sz_uval = 0, sz_uin = 0, sz_taus = 0, sz_src_cell = 0, sz_flags = 0, sz_list = 0,
            sz_counters = 0, sz_keys = 0, sz_keys_sorted = 0, sz_sort_tmp = 0, sz_dist = 0, sz_pinned = 0,
            sz_lane_off = 0, sz_vmask = 0, sz_cin = 0, sz_rlab = 0, sz_prof = 0, sz_dbg = 0;
@@ -215,6 +220,11 @@ struct DevGraph {
     int upload_cell_blobs2(const iso::Prep &P, const std::vector<std::vector<uint32_t>> &refs_of);
     uint64_t bytes = 0;
     SweepCtx main;   // context of the direct query calls
+    SweepCtx fixed;  // context of the no-allocation entry point (buffers in the static scratch)
+    void *scratch_ptr = nullptr;      // device address of this GPU's static scratch
+    hipEvent_t fixed_wait = nullptr;  // for waiting on the caller's stream without creating an event
+    int setup_fixed();
+    int carve_fixed(uint32_t K, uint32_t nu, uint32_t nx, size_t min_cap, size_t &cap);
     SweepCtx aux;    // second context of a batch call, so that consecutive sweeps overlap (made on first use)
     bool aux_ready = false;
     // per-cell sizes for the byte accounting

@@ -660,6 +660,100 @@ int iso_query_batch_device(iso_graph *g, size_t k, const uint32_t *sources, cons
     return r;
 }
 
+// iso_query_batch_device without any allocation: one sweep at a time on the graph's fixed
+// context, whose device buffers are carved from the static scratch for each sweep.
+int iso_query_batch_device_noalloc(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus, int mode,
+                                   uint32_t *pairs, uint64_t cap, uint32_t *offsets, uint64_t *total, void *stream) {
+    if (total) *total = 0;
+    if (!offsets || !total || (k && (!sources || !taus)) || (cap && !pairs))
+        return fail(ISO_EINVAL, "NULL argument");
+    if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    for (size_t j = 0; j < k; ++j) {
+        int r = check_query(g, sources[j], taus[j], mode);
+        if (r) return r;
+    }
+    if (k >= iso::INF) return fail(ISO_EINVAL, "too many queries in one call");
+    if (cap > (uint64_t(1) << 60)) return fail(ISO_EINVAL, "capacity out of range");
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    if (!device_range_ok(offsets, (k + 1) * sizeof(uint32_t), g->D.device))
+        return fail(ISO_EINVAL, "offsets is not k + 1 words of device memory on the graph's device");
+    if (cap && !device_range_ok(pairs, cap * 2 * sizeof(uint32_t), g->D.device))
+        return fail(ISO_EINVAL, "pairs is not cap pairs of device memory on the graph's device");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    isodev::DevGraph &D = g->D;
+    isodev::SweepCtx &C = D.fixed;
+    if (hipEventRecord(D.fixed_wait, (hipStream_t)stream) != hipSuccess ||
+        hipStreamWaitEvent(C.stream, D.fixed_wait, 0) != hipSuccess)
+        return fail(ISO_EDEVICE, "waiting for the caller's stream failed");
+    g->last = iso_query_stats{};
+    const double t0 = now_ms();
+    if (k == 0) {
+        const uint32_t zero = 0;
+        if (hipMemcpyAsync(offsets, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, C.stream) != hipSuccess ||
+            hipStreamSynchronize(C.stream) != hipSuccess)
+            return fail(ISO_EDEVICE, "writing the offsets failed");
+        return ISO_OK;
+    }
+    const uint32_t per = std::max<uint32_t>(1, std::min<uint32_t>(g->tuning.lanes_per_launch, isodev::MAX_LANES));
+    uint64_t done = 0;
+    bool over = false;
+    for (size_t b = 0; b < k; b += per) {
+        const uint32_t lanes = uint32_t(std::min<size_t>(per, k - b));
+        isodev::RunArgs A;
+        const double tu = now_ms();
+        build_run_args(g, sources + b, taus + b, lanes, mode == ISO_MODE_PLAIN, false, A, nullptr,
+                       mode == ISO_MODE_CD);
+        g->last.t_upward_ms += now_ms() - tu;
+        A.use_graph = 0;
+        A.debug = false;
+        A.fill_uslot = b == 0;   // the scratch may hold another call's data
+        uint32_t nu = 0, nx = 0;
+        for (uint32_t j = 0; j < lanes; ++j) {
+            nu += uint32_t(A.spos[j].size());
+            nx += uint32_t(A.xpos[j].size());
+        }
+        size_t kcap = 0;
+        int r = D.carve_fixed(A.k_pow2, nu, nx, 1, kcap);
+        if (r) return r == -2 ? ISO_ENOMEM : r;
+        A.out_cap = kcap;
+        const double tw = now_ms();
+        if ((r = D.launch(C, A))) {
+            if (C.pending) {
+                isodev::RunResult R0;
+                D.finish(C, R0);
+            }
+            return r == -2 ? ISO_ENOMEM : r;
+        }
+        isodev::RunResult R;
+        R.dev_dst = true;
+        R.dev_pairs = pairs;
+        R.dev_overflow = over;
+        R.dev_off = offsets + b;
+        R.dev_cap = cap;
+        R.dev_base = uint32_t(done);
+        R.dev_lanes = lanes;
+        if ((r = D.finish(C, R))) return r == -2 ? ISO_ENOMEM : r;
+        if (R.overflow)
+            return fail(ISO_ENOMEM, "the isochrone edges of one sweep exceed the static scratch; use fewer "
+                                    "queries per sweep");
+        over = R.dev_overflow;
+        done += R.count;
+        if (done >= iso::INF) return fail(ISO_ESPACE, "more than 2^32 - 2 edges in one call");
+        g->last.lanes += lanes;
+        g->last.active_cells += R.active_cells;
+        g->last.t_device_ms += now_ms() - tw - R.t_result_ms;
+        g->last.t_sort_ms += R.t_result_ms;
+    }
+    *total = done;
+    g->last.edges = done;
+    g->last.t_total_ms = now_ms() - t0;
+    return over ? fail(ISO_ESPACE, "device edge buffer holds " + std::to_string(cap) + " pairs, the call found " +
+                                       std::to_string(done))
+                : ISO_OK;
+}
+
 // One sweep of k <= 64 queries whose output is the vertices in range: bitmap rows of
 // ceil(n / 64) words per query at `bits` (device).  With `caller` set, its queued work is
 // waited for first.

@@ -2007,7 +2007,8 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     HIPCHK(hipFuncSetAttribute((const void *)k_cell_sweep<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                int(LDS_MAX)));
     HIPCHK(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, device));
-    return main.create(device);
+    if ((r = main.create(device))) return r;
+    return setup_fixed();
 }
 
 int SweepCtx::create(int device_) {
@@ -2040,6 +2041,9 @@ void DevGraph::release() {
     main.release();
     if (aux_ready) aux.release();
     aux_ready = false;
+    fixed.release();
+    if (fixed_wait) hipEventDestroy(fixed_wait);
+    fixed_wait = nullptr;
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
@@ -2050,6 +2054,11 @@ void DevGraph::release() {
 }
 
 void QueryBufs::release() {
+    if (fixed) {   // carved from the static scratch: nothing to free but the staging block
+        if (h_pinned) hipHostFree(h_pinned);
+        *this = QueryBufs();
+        return;
+    }
     void *ptrs[] = {d_dcore, d_uval, d_uin, d_taus, d_src_cell, d_flags, d_list, d_counters, d_keys,
                     d_keys_sorted, d_sort_tmp, d_dist, d_xin, d_uslot, d_lane_off, d_vmask, d_cin, d_rlab, d_prof,
                     d_dbg};
@@ -2058,9 +2067,114 @@ void QueryBufs::release() {
     *this = QueryBufs();
 }
 
+// Scratch memory of iso_query_batch_device_noalloc: a static device array, so that the entry
+// point needs no allocation.  Each GPU the library runs on holds its own copy until the process
+// ends.  Host code must not take the array's address directly (that is a host-side stand-in):
+// scratch_setup asks the runtime for the device address of this GPU's copy, once per device,
+// and every use goes through that address.
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+static std::mutex scratch_mu;
+static void *scratch_addr[256];
+
+// Device address of the scratch array on `device` (which must be current).
+static int scratch_setup(int device, void **addr) {
+    if (device < 0 || device >= 256) {
+        set_error("device ordinal out of range for the static scratch");
+        return -1;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[device]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_error("hipGetSymbolAddress gave no address for the static scratch");
+            return -3;
+        }
+        scratch_addr[device] = ptr;
+    }
+    *addr = scratch_addr[device];
+    return 0;
+}
+
+// The sweep context of iso_query_batch_device_noalloc: its stream, events and a pinned staging
+// block, made at load; its device buffers are carved from the static scratch per sweep.
+int DevGraph::setup_fixed() {
+    int r;
+    if ((r = scratch_setup(device, &scratch_ptr))) return r;
+    if ((r = fixed.create(device))) return r;
+    fixed.bufs.fixed = true;
+    HIPCHK(hipHostMalloc(&fixed.bufs.h_pinned, FIXED_STAGE_BYTES, hipHostMallocDefault));
+    fixed.bufs.sz_pinned = FIXED_STAGE_BYTES;
+    HIPCHK(hipEventCreateWithFlags(&fixed_wait, hipEventDisableTiming));
+    return 0;
+}
+
+// Lays out the buffers of one sweep of K lanes with nu upward entries below the table and nx
+// inside it in the static scratch, the edge keys taking what is left: *cap edges (at least
+// min_cap, else ISO_ENOMEM).  Nothing is allocated.
+int DevGraph::carve_fixed(uint32_t K, uint32_t nu, uint32_t nx, size_t min_cap, size_t &cap) {
+    QueryBufs &B = fixed.bufs;
+    uint8_t *base = static_cast<uint8_t *>(scratch_ptr);
+    size_t off = 0;
+    auto take = [&](void **p, size_t &sz, size_t bytes) {
+        bytes = (std::max<size_t>(bytes, 256) + 255) & ~size_t(255);
+        *p = off + bytes <= SCRATCH_BYTES ? base + off : nullptr;
+        sz = bytes;
+        off += bytes;
+    };
+    take((void **)&B.d_uslot, B.sz_uslot, size_t(n) * 4);
+    take((void **)&B.d_dcore, B.sz_dcore, std::max<size_t>(1, size_t(n_core) * K) * 4);
+    take((void **)&B.d_uval, B.sz_uval, size_t(std::max(8192u, nu)) * K * 4);
+    take((void **)&B.d_uin, B.sz_uin, size_t(std::max(1u, nu)) * 3 * 4);
+    fixed.xcap = std::max(1u, nx);
+    take((void **)&B.d_xin, B.sz_xin, (size_t(K) + 1 + 2 * size_t(fixed.xcap)) * 4);
+    take((void **)&B.d_taus, B.sz_taus, 2 * K * 4);
+    take((void **)&B.d_flags, B.sz_flags, size_t(std::max(1u, n_core)) * 16);
+    take((void **)&B.d_list, B.sz_list, size_t(std::max(1u, num_cells)) * (3 + MAX_LANES) * 4);
+    take((void **)&B.d_counters, B.sz_counters, 64);
+    take((void **)&B.d_lane_off, B.sz_lane_off, (MAX_LANES + 1) * 4);
+    if (off > SCRATCH_BYTES) {
+        set_error("a sweep of " + std::to_string(K) + " queries on this graph needs " + std::to_string(off >> 20) +
+                  " MiB of buffers, more than the " + std::to_string(SCRATCH_BYTES >> 20) +
+                  " MiB of static scratch (use fewer queries per sweep)");
+        return -2;
+    }
+    // the rest: two key arrays and the radix sort's temporary storage for `cap` keys
+    const size_t rest = SCRATCH_BYTES - off;
+    size_t lo = 0, hi = rest / 16;
+    auto need = [&](size_t c) {
+        size_t tmp = 0;
+        if (hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                              int(std::min<size_t>(c, size_t(INT32_MAX))), 0, 64) != hipSuccess)
+            tmp = c * 8 + (1 << 20);
+        return 2 * ((c * 8 + 255) & ~size_t(255)) + ((tmp + 255) & ~size_t(255));
+    };
+    while (lo < hi) {   // the largest capacity that fits
+        const size_t mid = (lo + hi + 1) / 2;
+        if (need(mid) <= rest) lo = mid;
+        else hi = mid - 1;
+    }
+    cap = std::min<size_t>(lo, INF - 1);
+    if (cap < std::max<size_t>(1, min_cap)) {
+        set_error("the isochrone edges of one sweep exceed the static scratch (" +
+                  std::to_string(SCRATCH_BYTES >> 20) + " MiB)");
+        return -2;
+    }
+    take((void **)&B.d_keys, B.sz_keys, cap * 8);
+    take((void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8);
+    B.sz_sort_tmp = SCRATCH_BYTES - off;
+    B.d_sort_tmp = base + off;
+    return 0;
+}
+
 // grow-only allocation helper
-static int ensure(void **p, size_t &have, size_t need) {
+static int ensure(bool fixed, void **p, size_t &have, size_t need) {
     if (need <= have && *p) return 0;
+    if (fixed) {   // a buffer carved from the static scratch never grows
+        set_error("the call needs more than the " + std::to_string(SCRATCH_BYTES >> 20) +
+                  " MiB of static scratch memory");
+        return -2;
+    }
     if (*p) hipFree(*p);
     *p = nullptr;
     have = 0;
@@ -2113,40 +2227,44 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     QueryBufs &B = C.bufs;
     hipStream_t s = C.stream;
     int r;
-    if (!B.d_uslot) {   // the slot table is all NO_SLOT between sweeps
-        if ((r = ensure((void **)&B.d_uslot, B.sz_uslot, size_t(n) * 4))) return r;
+    if (!B.d_uslot || A.fill_uslot) {   // the slot table is all NO_SLOT between sweeps
+        if ((r = ensure(B.fixed, (void **)&B.d_uslot, B.sz_uslot, size_t(n) * 4))) return r;
         k_fill<<<dim3(2048), dim3(256), 0, s>>>(B.d_uslot, NO_SLOT, uint64_t(n));
     }
     size_t core_words = std::max<size_t>(1, size_t(n_core) * K);
-    if ((r = ensure((void **)&B.d_dcore, B.sz_dcore, core_words * 4))) return r;
-    if ((r = ensure((void **)&B.d_uval, B.sz_uval, size_t(std::max(8192u, nu)) * K * 4))) return r;
-    if ((r = ensure((void **)&B.d_uin, B.sz_uin, size_t(std::max(1u, nu)) * 3 * 4))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_dcore, B.sz_dcore, core_words * 4))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_uval, B.sz_uval, size_t(std::max(8192u, nu)) * K * 4))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_uin, B.sz_uin, size_t(std::max(1u, nu)) * 3 * 4))) return r;
     // table lists: ptr (K + 1) | positions (xcap) | labels (xcap), capacity kept across calls so
     // that the pointers in a captured graph stay valid
     if (C.xcap < nx || B.sz_xin < (size_t(K) + 1 + 2 * size_t(C.xcap)) * 4) {
         C.xcap = std::max<uint32_t>(std::max<uint32_t>(nx + nx / 2, 1024u * K), C.xcap);
-        if ((r = ensure((void **)&B.d_xin, B.sz_xin, (size_t(K) + 1 + 2 * size_t(C.xcap)) * 4))) return r;
+        if ((r = ensure(B.fixed, (void **)&B.d_xin, B.sz_xin, (size_t(K) + 1 + 2 * size_t(C.xcap)) * 4))) return r;
     }
     const uint32_t xcap = C.xcap;
-    if ((r = ensure((void **)&B.d_taus, B.sz_taus, 2 * K * 4))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_taus, B.sz_taus, 2 * K * 4))) return r;
     // per core vertex: lanes in range, lanes whose range may leave the vertex's cell
-    if ((r = ensure((void **)&B.d_flags, B.sz_flags, size_t(std::max(1u, n_core)) * 16))) return r;
-    if ((r = ensure((void **)&B.d_list, B.sz_list, size_t(std::max(1u, num_cells)) * (3 + MAX_LANES) * 4)))
+    if ((r = ensure(B.fixed, (void **)&B.d_flags, B.sz_flags, size_t(std::max(1u, n_core)) * 16))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_list, B.sz_list, size_t(std::max(1u, num_cells)) * (3 + MAX_LANES) * 4)))
         return r;
-    if ((r = ensure((void **)&B.d_counters, B.sz_counters, 64))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_counters, B.sz_counters, 64))) return r;
     size_t cap = A.out_cap;
-    if ((r = ensure((void **)&B.d_keys, B.sz_keys, cap * 8))) return r;
-    if ((r = ensure((void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8))) return r;
-    if ((r = ensure((void **)&B.d_lane_off, B.sz_lane_off, (MAX_LANES + 1) * 4))) return r;
-    if (A.want_dist && (r = ensure((void **)&B.d_dist, B.sz_dist, size_t(n) * K * 4))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_keys, B.sz_keys, cap * 8))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_lane_off, B.sz_lane_off, (MAX_LANES + 1) * 4))) return r;
+    if (A.want_dist && (r = ensure(B.fixed, (void **)&B.d_dist, B.sz_dist, size_t(n) * K * 4))) return r;
     const bool vmode = A.vbits != nullptr;
     if (vmode) {
-        if ((r = ensure((void **)&B.d_vmask, B.sz_vmask, size_t(n) * 8))) return r;
-        if ((r = ensure((void **)&B.d_cin, B.sz_cin, size_t(std::max(1u, num_cells)) * 8))) return r;
+        if ((r = ensure(B.fixed, (void **)&B.d_vmask, B.sz_vmask, size_t(n) * 8))) return r;
+        if ((r = ensure(B.fixed, (void **)&B.d_cin, B.sz_cin, size_t(std::max(1u, num_cells)) * 8))) return r;
     }
     // per-call host inputs staged in one pinned buffer: counters back, taus, source cells,
     // upward entries
     size_t stage = (16 + 2 * size_t(K) + 3 * size_t(nu) + (K + 1) + 2 * size_t(nx)) * 4;
+    if (stage > B.sz_pinned && B.fixed) {
+        set_error("the queries' upward labels exceed the staging block of the no-allocation entry point");
+        return -2;
+    }
     if (stage > B.sz_pinned) {
         HIPCHK(hipStreamSynchronize(s));
         if (B.h_pinned) hipHostFree(B.h_pinned);
@@ -2191,7 +2309,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     if (A.tg) {   // one-to-many: the table product, then the target set's level groups
         const TargetSet &T = *A.tg;
         const uint64_t rows = uint64_t(T.tx) + T.nr;
-        if ((r = ensure((void **)&B.d_rlab, B.sz_rlab, std::max<uint64_t>(1, rows) * K * 4))) return r;
+        if ((r = ensure(B.fixed, (void **)&B.d_rlab, B.sz_rlab, std::max<uint64_t>(1, rows) * K * 4))) return r;
         if (T.tx > 0) {
             k_fill<<<dim3(std::max<uint32_t>(1, std::min<uint32_t>(1024, (T.tx * K + 255) / 256))), dim3(256), 0,
                      s>>>(B.d_rlab, INF, uint64_t(T.tx) * K);
@@ -2289,7 +2407,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     unsigned long long *dbg = nullptr;
     if (A.debug) {   // summed over calls; cleared when first allocated and by iso_debug_enable
         if (!B.d_dbg) {
-            if ((r = ensure((void **)&B.d_dbg, B.sz_dbg, 8 * sizeof(uint64_t)))) return r;
+            if ((r = ensure(B.fixed, (void **)&B.d_dbg, B.sz_dbg, 8 * sizeof(uint64_t)))) return r;
             k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_dbg), 0u, 16);
         }
         dbg = B.d_dbg;
@@ -2412,7 +2530,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[3], s));
     if (prof_on && num_cells > 0) {   // after the last phase event: not part of any phase's time
-        if ((r = ensure((void **)&B.d_prof, B.sz_prof, 8 * sizeof(uint64_t)))) return r;
+        if ((r = ensure(B.fixed, (void **)&B.d_prof, B.sz_prof, 8 * sizeof(uint64_t)))) return r;
         if (!C.prof.acc_ready) {
             k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_prof), 0u, 16);   // 8 sums
             C.prof.acc_ready = true;
@@ -2461,7 +2579,7 @@ int DevGraph::sort_keys(SweepCtx &C, uint32_t cnt_all) {
     int r;
     HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
                                              int(cnt_all), 0, end_bit, s));
-    if ((r = ensure((void **)&B.d_sort_tmp, B.sz_sort_tmp, tmp))) return r;
+    if ((r = ensure(B.fixed, (void **)&B.d_sort_tmp, B.sz_sort_tmp, tmp))) return r;
     if (C.prof.on) HIPCHK(hipEventRecord(C.prof.ev[4], s));
     HIPCHK(hipcub::DeviceRadixSort::SortKeys(B.d_sort_tmp, tmp, (const uint64_t *)B.d_keys, B.d_keys_sorted,
                                              int(cnt_all), 0, end_bit, s));
