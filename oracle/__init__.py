@@ -24,7 +24,7 @@ def build(force: bool = False, src: str = SRC_PATH, out: str = LIB_PATH) -> str:
     """Compile oracle.c with gcc into a shared library (plain -O2, no vectorisation tricks)."""
     if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
         tmp = out + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, src])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
         os.replace(tmp, out)
     return out
 
@@ -51,6 +51,9 @@ def _load(path: str):
     lib.orc_iso_dijkstra.argtypes = [_P, _P, C.c_uint32, C.c_uint64, C.POINTER(_U64P), _U64P]
     lib.orc_in_range.restype = C.c_uint64
     lib.orc_in_range.argtypes = [_P, _P, C.c_uint32, C.c_uint64, C.POINTER(_U32P)]
+    lib.orc_polygon.restype = C.c_uint64
+    lib.orc_polygon.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint8), C.POINTER(_U64P),
+                                C.POINTER(_U64P), _U64P]
     lib.orc_free.argtypes = [_P]
     return lib
 
@@ -147,6 +150,28 @@ class Oracle:
             return np.ctypeslib.as_array(ptr, shape=(cnt,)).copy() if cnt else np.zeros(0, dtype=np.uint32)
         finally:
             self._L.orc_free(ptr)
+
+    def polygon(self, xy, in_range):
+        """The isochrone polygon of a vertex set in range (Section 7, face traversal on the planar
+        embedding xy): a list of cycles, each an (k, 2) uint32 array of boundary darts (u in range,
+        v not), each cycle from its smallest dart, the cycles ordered by it."""
+        xyc = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1)
+        inr = np.zeros(self.n, dtype=np.uint8)
+        inr[np.asarray(in_range, dtype=np.int64)] = 1
+        dp, cp, nc = _U64P(), _U64P(), C.c_uint64()
+        nd = self._L.orc_polygon(self._g, xyc.ctypes.data_as(C.POINTER(C.c_double)),
+                                 inr.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(dp), C.byref(cp), C.byref(nc))
+        if nd == 0xFFFFFFFFFFFFFFFF:
+            raise ValueError("a face walk did not close: the embedding is not planar")
+        try:
+            d = np.ctypeslib.as_array(dp, shape=(nd,)).copy() if nd else np.zeros(0, dtype=np.uint64)
+            c = np.ctypeslib.as_array(cp, shape=(nc.value + 1,)).copy()
+        finally:
+            self._L.orc_free(dp)
+            self._L.orc_free(cp)
+        pairs = np.stack([(d >> np.uint64(32)).astype(np.uint32), (d & np.uint64(0xFFFFFFFF)).astype(np.uint32)],
+                         axis=1)
+        return [pairs[c[i]:c[i + 1]] for i in range(int(nc.value))]
 
     def iso_dijkstra(self, s: int, tau: int):
         """The paper's isoDijkstra: (edges, settled count).  Requires tau < 2^64-1."""

@@ -389,4 +389,142 @@ uint64_t orc_iso_dijkstra(const orc_graph *g, orc_ws *ws, uint32_t s, uint64_t t
     return ws->order_len;
 }
 
+/* ---------------------------------------------------------------- polygon */
+/*
+ * The isochrone polygon (Section 7: traverse the faces of a planar embedding
+ * along the border of the region in range, switching to the twin face at every
+ * isochrone edge), written out plainly:
+ *   - the graph is taken undirected (u and v are neighbours if either arc
+ *     exists), each vertex's neighbours ordered counterclockwise by the angle
+ *     atan2(dy, dx) of the straight segment to them (ties, which a planar
+ *     embedding does not have, by id);
+ *   - a boundary dart is an ordered pair (u, v) of neighbours with u in range
+ *     and v not;
+ *   - from a boundary dart, walk the face on its left (from dart (a, b) the walk
+ *     goes on to (b, c), c the neighbour of b next clockwise from a) until a
+ *     dart (p, q) leads from out of range into range; the next boundary dart is
+ *     its twin (q, p), and the walk goes on in the twin's face;
+ *   - these successors form cycles; each cycle is listed from its smallest dart
+ *     (by (u, v)), the cycles in the order of their smallest darts.
+ * in_range: n bytes, nonzero for vertices in range.  Output: *darts_out holds
+ * the darts as (u << 32 | v) in cycle order, *cyc_out the start of every cycle
+ * plus the end (ncycles + 1 words); returns the number of darts.  Returns
+ * UINT64_MAX if a face walk exceeds every dart of the graph (not planar).
+ */
+#include <math.h>
+
+typedef struct { uint32_t v; double a; } orc_nb;
+
+static int cmp_nb(const void *x, const void *y)
+{
+    const orc_nb *p = x, *q = y;
+    if (p->a < q->a) return -1;
+    if (p->a > q->a) return 1;
+    return p->v < q->v ? -1 : (p->v > q->v);
+}
+
+/* index of w in the neighbour list of v (present by construction) */
+static uint64_t nb_index(const uint64_t *off, const orc_nb *nb, uint32_t v, uint32_t w)
+{
+    for (uint64_t k = off[v]; k < off[v + 1]; ++k)
+        if (nb[k].v == w) return k;
+    return UINT64_MAX;
+}
+
+uint64_t orc_polygon(const orc_graph *g, const double *xy, const uint8_t *in_range,
+                     uint64_t **darts_out, uint64_t **cyc_out, uint64_t *ncyc_out)
+{
+    uint32_t n = g->n;
+    /* undirected neighbour lists: both directions of every arc, self-loops dropped */
+    uint64_t *off = calloc((size_t)n + 1, sizeof(uint64_t));
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint64_t e = g->out_off[u]; e < g->out_off[u + 1]; ++e)
+            if (g->out_head[e] != u) { off[u + 1]++; off[g->out_head[e] + 1]++; }
+    for (uint32_t v = 0; v < n; ++v) off[v + 1] += off[v];
+    orc_nb *nb = malloc((off[n] ? off[n] : 1) * sizeof(orc_nb));
+    uint64_t *fill = malloc(((size_t)n + 1) * sizeof(uint64_t));
+    memcpy(fill, off, ((size_t)n + 1) * sizeof(uint64_t));
+    for (uint32_t u = 0; u < n; ++u)
+        for (uint64_t e = g->out_off[u]; e < g->out_off[u + 1]; ++e) {
+            uint32_t v = g->out_head[e];
+            if (v == u) continue;
+            nb[fill[u]++].v = v;
+            nb[fill[v]++].v = u;
+        }
+    /* sort by id, drop duplicates, then sort counterclockwise */
+    uint64_t *noff = calloc((size_t)n + 1, sizeof(uint64_t));
+    uint64_t w = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+        uint64_t b = off[u], e = off[u + 1];
+        for (uint64_t k = b; k < e; ++k) nb[k].a = (double)nb[k].v;
+        qsort(nb + b, e - b, sizeof(orc_nb), cmp_nb);
+        uint64_t start = w;
+        for (uint64_t k = b; k < e; ++k)
+            if (k == b || nb[k].v != nb[k - 1].v) nb[w++] = nb[k];
+        for (uint64_t k = start; k < w; ++k) {
+            uint32_t v = nb[k].v;
+            nb[k].a = atan2(xy[2 * (size_t)v + 1] - xy[2 * (size_t)u + 1], xy[2 * (size_t)v] - xy[2 * (size_t)u]);
+        }
+        qsort(nb + start, w - start, sizeof(orc_nb), cmp_nb);
+        noff[u + 1] = w;
+    }
+    free(off);
+    off = noff;
+    /* boundary darts, sorted by (u, v) */
+    uint64_t nd = 0;
+    for (uint32_t u = 0; u < n; ++u)
+        if (in_range[u])
+            for (uint64_t k = off[u]; k < off[u + 1]; ++k)
+                if (!in_range[nb[k].v]) nd++;
+    uint64_t *darts = malloc((nd ? nd : 1) * sizeof(uint64_t));
+    uint64_t *next = malloc((nd ? nd : 1) * sizeof(uint64_t));
+    uint8_t *seen = calloc(nd ? nd : 1, 1);
+    nd = 0;
+    for (uint32_t u = 0; u < n; ++u)
+        if (in_range[u])
+            for (uint64_t k = off[u]; k < off[u + 1]; ++k)
+                if (!in_range[nb[k].v]) darts[nd++] = ((uint64_t)u << 32) | nb[k].v;
+    qsort(darts, nd, sizeof(uint64_t), cmp_u64);
+    uint64_t limit = 2 * off[n] + 2, bad = 0;
+    for (uint64_t i = 0; i < nd && !bad; ++i) {
+        uint32_t a = (uint32_t)(darts[i] >> 32), b = (uint32_t)darts[i];
+        uint64_t steps = 0;
+        for (;;) {
+            /* from (a, b): c is the neighbour of b next clockwise from a */
+            uint64_t ka = nb_index(off, nb, b, a);
+            uint64_t kc = ka == off[b] ? off[b + 1] - 1 : ka - 1;
+            uint32_t c = nb[kc].v;
+            a = b;
+            b = c;
+            if (!in_range[a] && in_range[b]) break;   /* (a, b) enters the region: its twin leaves it */
+            if (++steps > limit) { bad = 1; break; }
+        }
+        uint64_t key = ((uint64_t)b << 32) | a, lo = 0, hi = nd;   /* twin (b, a) */
+        while (lo < hi) {
+            uint64_t mid = (lo + hi) / 2;
+            if (darts[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        if (lo == nd || darts[lo] != key) { bad = 1; break; }   /* not a boundary dart: no planar embedding */
+        next[i] = lo;
+    }
+    uint64_t *outd = malloc((nd ? nd : 1) * sizeof(uint64_t));
+    uint64_t *cyc = malloc((nd + 1) * sizeof(uint64_t));
+    uint64_t no = 0, nc = 0;
+    for (uint64_t i = 0; i < nd && !bad; ++i) {
+        if (seen[i]) continue;
+        cyc[nc++] = no;
+        for (uint64_t j = i; !seen[j]; j = next[j]) {   /* i is the smallest dart of its cycle */
+            seen[j] = 1;
+            outd[no++] = darts[j];
+        }
+    }
+    cyc[nc] = no;
+    free(off); free(nb); free(fill); free(darts); free(next); free(seen);
+    if (bad) { free(outd); free(cyc); return UINT64_MAX; }
+    *darts_out = outd;
+    *cyc_out = cyc;
+    *ncyc_out = nc;
+    return no;
+}
+
 void orc_free(void *p) { free(p); }

@@ -14,7 +14,7 @@ import pytest
 import synth
 from oracle import INF, SRC_PATH, Oracle
 from tests import golden_io
-from tests.test_oracle_pins import as_u64, bellman_ford, definition_edges
+from tests.test_oracle_pins import as_u64, bellman_ford, definition_edges, polygon_pins_pass
 
 MUTANTS = {
     "strict_stop": ("if (ws->heap[0].key > tau) break;", "if (ws->heap[0].key >= tau) break;"),
@@ -38,6 +38,11 @@ MUTANTS = {
                            "for (uint64_t i = 0; i < settled; ++i) buf[i] = ws->order[i];\n"
                            "    qsort(buf, settled, sizeof(uint32_t), cmp_u32);\n    *verts_out = buf;\n"
                            "    return settled ? settled - 1 : 0;"),
+    "polygon_ccw_walk": ("uint64_t kc = ka == off[b] ? off[b + 1] - 1 : ka - 1;",
+                         "uint64_t kc = ka + 1 == off[b + 1] ? off[b] : ka + 1;"),
+    "polygon_no_twin": ("uint64_t key = ((uint64_t)b << 32) | a, lo = 0, hi = nd;",
+                        "uint64_t key = ((uint64_t)a << 32) | b, lo = 0, hi = nd;"),
+    "polygon_exit_test": ("if (!in_range[a] && in_range[b]) break;", "if (in_range[a] && !in_range[b]) break;"),
     "relax_wrong_weight": ("uint64_t nd = it.key + g->out_w[e];\n            if (nd < get_dist(ws, v)) {\n"
                            "                set_dist(ws, v, nd);\n                heap_push(ws, nd, v);\n            }\n        }\n    }\n    return",
                            "uint64_t nd = it.key + g->out_w[e] / 2;\n            if (nd < get_dist(ws, v)) {\n"
@@ -80,12 +85,15 @@ def _pins_pass(libpath) -> bool:
             return False
         if not np.array_equal(orc.distances(f["source"]), f["dist"]):
             return False
-    return True
+    try:
+        return polygon_pins_pass(libpath)
+    except ValueError:   # a face walk that never closes
+        return False
 
 
 def test_unmodified_oracle_passes(tmp_path):
     out = str(tmp_path / "liboracle_ref.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", out, SRC_PATH])
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", out, SRC_PATH, "-lm"])
     assert _pins_pass(out)
 
 
@@ -98,6 +106,6 @@ def test_mutant_is_caught(name, tmp_path):
     mpath = tmp_path / f"oracle_{name}.c"
     mpath.write_text(src.replace(old, new))
     out = str(tmp_path / f"liboracle_{name}.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", out, str(mpath)])
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", out, str(mpath), "-lm"])
     assert not _pins_pass(out), f"mutant {name} survived every pin"
     os.remove(out)

@@ -244,3 +244,89 @@ def test_invariants(name, nq):
         # I7: monotone in tau
         _, d_lo, _ = orc.isochrone(s, tau // 2, want_dist=True)
         assert np.all(inr[d_lo != INF])
+
+
+# ------------------------------------------------------------------ isochrone polygon (Section 7)
+
+def signed_area(g, cycle):
+    """Shoelace area of the polygon through the midpoints of a cycle's boundary edges."""
+    p = 0.5 * (g.xy[cycle[:, 0]] + g.xy[cycle[:, 1]])
+    x, y = p[:, 0], p[:, 1]
+    return 0.5 * float(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+
+
+def grid_with_slow_block(W, c, block):
+    """Uniform W x W grid (weight c) whose arcs touching the `block` vertices weigh c * 10^6."""
+    g = synth.uniform_grid(W, c)
+    slow = np.zeros(g.n, dtype=bool)
+    slow[block] = True
+    w = g.w.astype(np.uint64)
+    w[slow[g.tail] | slow[g.head]] *= 1_000_000
+    return synth.Graph(g.n, g.tail, g.head, w.astype(np.uint32), g.xy)
+
+
+def polygon_pins_pass(libpath=None) -> bool:
+    """Closed forms of the polygon on a uniform grid: the in-range set of a source far from the
+    border is an L1 ball of radius r, bounded by one cycle of 4(2r+1) darts; a block of slow
+    vertices strictly inside the ball and off both axes through the source (so that no other
+    distance changes: an L-shaped path avoids it) adds a second cycle of 2(k + l) darts around a
+    k x l block.  The walk keeps the region on its left, so the outer cycle runs counterclockwise
+    (positive area in x-right, y-up coordinates) and a hole's cycle clockwise."""
+    W, c = 25, 10
+    s = 12 * W + 12
+    g = synth.uniform_grid(W, c)
+    orc = Oracle.from_graph(g, libpath)
+    for r in range(0, 9):
+        cyc = orc.polygon(g.xy, orc.in_range(s, c * r))
+        if len(cyc) != 1 or len(cyc[0]) != 4 * (2 * r + 1):
+            return False
+        if r > 0 and signed_area(g, cyc[0]) <= 0:
+            return False
+    bx, by = np.meshgrid(np.arange(14, 16), np.arange(15, 18))   # a 2 x 3 block at offsets (2..3, 3..5)
+    block = (by * W + bx).ravel()
+    gb = grid_with_slow_block(W, c, block)
+    ob = Oracle.from_graph(gb, libpath)
+    r = 9
+    inr = ob.in_range(s, c * r)
+    if not np.array_equal(np.sort(inr), np.sort(np.setdiff1d(orc.in_range(s, c * r), block))):
+        return False
+    cyc = ob.polygon(gb.xy, inr)
+    if sorted(len(x) for x in cyc) != [2 * (2 + 3), 4 * (2 * r + 1)]:
+        return False
+    outer, hole = sorted(cyc, key=len, reverse=True)
+    return signed_area(gb, outer) > 0 > signed_area(gb, hole)
+
+
+def test_polygon_closed_forms():
+    assert polygon_pins_pass()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_polygon_partitions_the_boundary(seed):
+    """On the jittered planar grid: the cycles hold every dart (u in range, v not, u and v
+    neighbours in either direction) exactly once, so the polygon covers the isochrone edges."""
+    g = synth.config_graph("grid64")
+    orc = Oracle.from_graph(g)
+    rng = np.random.default_rng(seed)
+    for s, tau in zip(rng.integers(0, g.n, size=5), rng.integers(0, 9000, size=5)):
+        inr = orc.in_range(int(s), int(tau))
+        cyc = orc.polygon(g.xy, inr)
+        got = np.concatenate(cyc) if cyc else np.zeros((0, 2), np.uint32)
+        key = got[:, 0].astype(np.int64) << 32 | got[:, 1].astype(np.int64)
+        assert len(np.unique(key)) == len(key)
+        mark = np.zeros(g.n, dtype=bool)
+        mark[inr] = True
+        u = np.concatenate([g.tail, g.head]).astype(np.int64)
+        v = np.concatenate([g.head, g.tail]).astype(np.int64)
+        want = np.unique((u << 32 | v)[mark[u] & ~mark[v]])
+        np.testing.assert_array_equal(np.sort(key), want)
+        for cy in cyc:   # each cycle starts at its smallest dart; cycles ordered by it
+            k = cy[:, 0].astype(np.int64) << 32 | cy[:, 1].astype(np.int64)
+            assert k[0] == k.min()
+        firsts = [int(cy[0, 0]) << 32 | int(cy[0, 1]) for cy in cyc]
+        assert firsts == sorted(firsts)
+        # the isochrone edges are exactly the arcs of these darts, in either direction
+        edges, _, _ = orc.isochrone(int(s), int(tau))
+        ek = edges[:, 0].astype(np.int64) << 32 | edges[:, 1].astype(np.int64)
+        und = np.unique(np.concatenate([key, (key & 0xFFFFFFFF) << 32 | key >> 32]))
+        assert np.isin(ek, und).all()
