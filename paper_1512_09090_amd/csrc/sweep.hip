@@ -1271,7 +1271,8 @@ k_cell_sweep(CellArgs A) {
 //   (padding to an even word), then the entries, one word each in the packed form:
 //     bits [0, LB) tail's row (internal vertex i < stored: i; core ref r: stored + r),
 //     bit LB the forward original arc, bit LB + 1 the reverse one, bits [LB + 2, 32) the length
-//     (all ones: the dummy entry's infinite length),
+//     (below 2^(29 - LB); all ones for the dummy entry's infinite length, so that an arithmetic
+//     shift decodes it to INF),
 //   or two words each in the wide form (row | FWD bit 31 | REV bit 30, length), used when a
 //   length or a row index does not fit the packed word.
 // stored = lvl[nl - 1]: the rows of every level but the last.
@@ -1319,8 +1320,7 @@ __device__ __forceinline__ C2Ent c2_entry(const uint32_t *s_ent, uint32_t e, uin
         r.row = x & ((1u << lb) - 1u);
         r.fwd = (x >> lb) & 1u;
         r.rev = (x >> (lb + 1)) & 1u;
-        const uint32_t wc = x >> (lb + 2), wmax = 0xFFFFFFFFu >> (lb + 2);
-        r.w = wc == wmax ? INF : wc;
+        r.w = uint32_t(int32_t(x) >> (lb + 2));   // all ones (the dummy entry) -> INF
     } else {
         const uint2 x = reinterpret_cast<const uint2 *>(s_ent)[e];
         r.row = x.x & LOCAL_MASK;
@@ -1368,7 +1368,7 @@ __device__ __forceinline__ void c2_flush(const Cell2Args &A, uint32_t n, uint32_
 // W labels).  tau, live (a real lane), up (its source lies in the cell: the upward labels
 // start the vertex's label), lane (the batch lane).
 template <bool PACKED>
-__device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t i, uint32_t j, uint32_t W,
+__device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t i, uint32_t j, uint32_t W, uint32_t lw,
                                           const uint32_t *s_off, const uint32_t *s_ent, uint32_t *s_lab,
                                           uint32_t stored, uint32_t tau, bool live, bool up, uint32_t lane,
                                           uint32_t cb, uint32_t rank, uint32_t *s_cand, uint32_t *s_ctl,
@@ -1383,19 +1383,31 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
         e1 = s_off[i + 1];
     }
     bool fin = false, fout = false;   // a flagged entry's tail in / out of range
-    for (uint32_t e = e0; e < e1; e += 2) {
-        const bool two = e + 1 < e1;
-        const C2Ent x0 = c2_entry<PACKED>(s_ent, e, lb);
-        const C2Ent x1 = c2_entry<PACKED>(s_ent, two ? e + 1 : e, lb);
-        const uint32_t t0 = s_lab[x0.row * W + j], t1 = s_lab[x1.row * W + j];
-        dv = min(dv, min(sat_add(t0, x0.w), sat_add(t1, two ? x1.w : INF)));
-        const bool f0 = x0.fwd || x0.rev, f1 = two && (x1.fwd || x1.rev);
-        fin |= (f0 && t0 <= tau) || (f1 && t1 <= tau);
-        fout |= (f0 && t0 > tau) || (f1 && t1 > tau);
+    // four entries at a time: their words (read whether or not they belong to i: the reads stay
+    // inside the workgroup's LDS), then the four tails' labels, then the minimum
+    for (uint32_t e = e0; e < e1; e += 4) {
+        uint32_t row[4], w[4], t[4];
+        bool fl[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const C2Ent x = c2_entry<PACKED>(s_ent, e + k, lb);
+            const bool valid = e + k < e1;
+            row[k] = valid ? x.row : 0u;
+            w[k] = valid ? x.w : INF;
+            fl[k] = valid && (x.fwd || x.rev);
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) t[k] = s_lab[(row[k] << lw) + j];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            dv = min(dv, sat_add(t[k], w[k]));
+            fin |= fl[k] && t[k] <= tau;
+            fout |= fl[k] && t[k] > tau;
+        }
     }
     const bool vin = dv <= tau;
     if (act) {
-        if (i < stored) s_lab[i * W + j] = dv;
+        if (i < stored) s_lab[(i << lw) + j] = dv;
         if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << A.lk) + lane] = dv;
     }
     if (A.vmask) {   // lanes in range, ORed over the vertex's W slots (consecutive threads)
@@ -1408,7 +1420,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
     if (!(act && live && (vin ? fout : fin))) return;
     for (uint32_t e = e0; e < e1; ++e) {
         const C2Ent x = c2_entry<PACKED>(s_ent, e, lb);
-        if (!(x.fwd || x.rev) || ((s_lab[x.row * W + j] <= tau) == vin)) continue;
+        if (!(x.fwd || x.rev) || ((s_lab[(x.row << lw) + j] <= tau) == vin)) continue;
         if (x.fwd) c2_push(A, s_cand, s_ctl, e, rank, 0u, A.lane_base + lane, ebase);
         if (x.rev) c2_push(A, s_cand, s_ctl, e, rank, 1u, A.lane_base + lane, ebase);
     }
@@ -1437,7 +1449,7 @@ __device__ __forceinline__ void c2_chunk(const Cell2Args &A, uint32_t *smem, uin
     const bool up = live && A.src_cell[lane] == c;
     // the referenced core vertices' final labels, one (ref, slot) pair per thread
     for (uint32_t r = tid >> lw; r < nrefs; r += T >> lw)
-        s_lab[(stored + r) * W + j] = A.dcore[(s_refs[r] << A.lk) + lane];
+        s_lab[((stored + r) << lw) + j] = A.dcore[(s_refs[r] << A.lk) + lane];
     __syncthreads();
     const uint32_t wslots = 64u >> lw;   // vertex slots of one wavefront
     uint32_t l0 = 0;
@@ -1450,7 +1462,7 @@ __device__ __forceinline__ void c2_chunk(const Cell2Args &A, uint32_t *smem, uin
         for (uint32_t base = a; base < b; base += per) {
             if (base + wfirst >= b) break;   // whole wavefronts past the level's end
             const uint32_t i = base + (tid >> lw);
-            c2_vertex<PACKED>(A, i < b, i, j, W, s_off, s_ent, s_lab, stored, tau, live, up, lane, cb, rank, s_cand,
+            c2_vertex<PACKED>(A, i < b, i, j, W, lw, s_off, s_ent, s_lab, stored, tau, live, up, lane, cb, rank, s_cand,
                               s_ctl, ebase, A.lb);
         }
         if (l < l0) {
@@ -1764,7 +1776,7 @@ int DevGraph::upload_cell_blobs2(const iso::Prep &P, const std::vector<std::vect
         }
     }
     lb2 = std::max<uint32_t>(1, ilog2(max_rows2));
-    packed2 = lb2 <= 16 && uint64_t(wmax_seen) < (uint64_t(1) << (30 - lb2)) - 1;
+    packed2 = lb2 <= 16 && uint64_t(wmax_seen) < (uint64_t(1) << (29 - lb2));
     std::vector<uint32_t> cblob2(std::max<uint32_t>(1, num_cells), 0);
     uint64_t total = 0;
     max_blob2_words = 0;
