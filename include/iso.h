@@ -217,6 +217,39 @@ int iso_query_vertices(iso_graph *g, uint32_t source, uint32_t tau, int mode,
                        uint32_t **vertices, size_t *count);
 
 /*
+ * Isochrone polygons (Section 7: the region in range outlined by traversing the faces of a
+ * planar embedding, starting from the isochrone edges).  The embedding comes from the vertex
+ * coordinates given at load (desc.xy; ISO_ESTATE without them): every pair of vertices
+ * joined by an arc, in either direction, is one straight segment, and the neighbours of a
+ * vertex are ordered counterclockwise by the angle atan2(dy, dx) of their segments (equal
+ * angles by neighbour id).  A boundary dart is an ordered neighbour pair (u, v) with u in
+ * range and v not (one per undirected isochrone edge).  From a boundary dart the face on its
+ * left is walked - from (a, b) on to (b, c), c the neighbour of b next clockwise from a - up
+ * to the first pair (p, q) with p out of range and q in range; the successor of the dart is
+ * (q, p), again a boundary dart.  The successors form the polygon's cycles: on a plane
+ * embedding one per component of the region's border, outer borders counterclockwise and
+ * holes clockwise.  Each cycle is listed from its smallest dart by (tail, head), the cycles
+ * in the order of those.  Where segments cross, the same rule still defines cycles (the
+ * faces of the rotation system) and they are returned as such.
+ *
+ * iso_query_polygon_batch: k (1..64) queries in one sweep, modes as iso_query.  *darts
+ * (library-allocated, iso_free) receives every lane's boundary darts in cycle order, lane j's
+ * at [dart_off[j], dart_off[j + 1]) (dart_off: k + 1 entries, caller memory).  *cycles
+ * (library-allocated, iso_free) receives the start of every cycle as an index into *darts,
+ * then one more entry, the total dart count; lane j's cycles are c in
+ * [cycle_off[j], cycle_off[j + 1]) (cycle_off: k + 1, caller memory), cycle c spanning darts
+ * [cycles[c], cycles[c + 1]).  The first call on a graph builds the embedding on the host and
+ * makes it resident (five words per dart, two darts per neighbour pair); ISO_EINVAL if a
+ * coordinate is not finite.
+ * iso_query_polygon: one query; *count darts and *ncycles cycles (*cycles has ncycles + 1
+ * entries).
+ */
+int iso_query_polygon_batch(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus, int mode,
+                            iso_edge **darts, size_t *dart_off, uint64_t **cycles, size_t *cycle_off);
+int iso_query_polygon(iso_graph *g, uint32_t source, uint32_t tau, int mode, iso_edge **darts, size_t *count,
+                      uint64_t **cycles, size_t *ncycles);
+
+/*
  * One-to-many distances on the same hierarchy: RPHAST (Section 2), the
  * restricted PHAST the paper times in Table 1.  iso_targets_select runs the
  * target selection once: a search from the targets against the direction of

@@ -57,6 +57,7 @@ class Tuning(C.Structure):
 
 
 _U32P = C.POINTER(C.c_uint32)
+_U64P = C.POINTER(C.c_uint64)
 
 
 class Layout(C.Structure):
@@ -138,6 +139,10 @@ def lib():
                                                   C.c_void_p]
     L.iso_query_vertices.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.POINTER(_U32P),
                                      C.POINTER(C.c_size_t)]
+    L.iso_query_polygon_batch.argtypes = [C.c_void_p, C.c_size_t, _U32P, _U32P, C.c_int, C.POINTER(C.POINTER(Edge)),
+                                          C.POINTER(C.c_size_t), C.POINTER(_U64P), C.POINTER(C.c_size_t)]
+    L.iso_query_polygon.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.POINTER(C.POINTER(Edge)),
+                                    C.POINTER(C.c_size_t), C.POINTER(_U64P), C.POINTER(C.c_size_t)]
     L.iso_targets_select.argtypes = [C.c_void_p, _U32P, C.c_size_t, C.POINTER(C.c_void_p)]
     L.iso_targets_query.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, _U32P, _U32P]
     L.iso_targets_query_device.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, _U32P, C.c_void_p, C.c_void_p]
@@ -352,6 +357,40 @@ class Graph:
             raise IsoError(ISO_EINVAL, f"bits must be a contiguous 64-bit device tensor of {k} x {W} words")
         _check(lib().iso_query_batch_vertices_device(self._h, k, sp, tp, int(mode), C.c_void_p(bits.data_ptr()),
                                                      C.c_void_p(stream)))
+
+    def polygon_batch(self, sources, taus, mode: int = MODE_PLAIN) -> list[list[np.ndarray]]:
+        """Isochrone polygons of k <= 64 queries (iso_query_polygon_batch): per query a list of
+        cycles, each an (len, 2) uint32 array of boundary darts (tail in range, head not) in
+        cycle order from its smallest dart, the cycles ordered by that dart."""
+        s, sp = _u32(sources)
+        t, tp = _u32(taus)
+        k = s.size
+        doff = (C.c_size_t * (k + 1))()
+        coff = (C.c_size_t * (k + 1))()
+        dp = C.POINTER(Edge)()
+        cp = _U64P()
+        _check(lib().iso_query_polygon_batch(self._h, k, sp, tp, int(mode), C.byref(dp), doff, C.byref(cp), coff))
+        try:
+            nd, nc = doff[k], coff[k]
+            cyc = np.ctypeslib.as_array(cp, shape=(nc + 1,)).copy()
+        finally:
+            lib().iso_free(cp)
+        flat = _edges_to_numpy(dp, nd)
+        return [[flat[int(cyc[c]):int(cyc[c + 1])] for c in range(coff[j], coff[j + 1])] for j in range(k)]
+
+    def polygon(self, source: int, tau: int, mode: int = MODE_PLAIN) -> list[np.ndarray]:
+        """The isochrone polygon of one query (iso_query_polygon), as polygon_batch's lists."""
+        dp = C.POINTER(Edge)()
+        cp = _U64P()
+        cnt, nc = C.c_size_t(), C.c_size_t()
+        _check(lib().iso_query_polygon(self._h, int(source), int(tau), int(mode), C.byref(dp), C.byref(cnt),
+                                       C.byref(cp), C.byref(nc)))
+        try:
+            cyc = np.ctypeslib.as_array(cp, shape=(nc.value + 1,)).copy()
+        finally:
+            lib().iso_free(cp)
+        flat = _edges_to_numpy(dp, cnt.value)
+        return [flat[int(cyc[c]):int(cyc[c + 1])] for c in range(nc.value)]
 
     def select_targets(self, targets) -> "Targets":
         """RPHAST target selection for a one-to-many target set (original ids)."""

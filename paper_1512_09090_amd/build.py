@@ -17,7 +17,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{os.p
 # device code: gfx950 only; packed FP32 instructions disabled
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-SOURCES = ["prep.cpp", "iso_api.cpp", "server.cpp", "sweep.hip"]
+SOURCES = ["prep.cpp", "iso_api.cpp", "server.cpp", "sweep.hip", "polygon.hip"]
 
 
 def _compile(src: str, obj_dir: str) -> str:

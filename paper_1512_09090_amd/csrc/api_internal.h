@@ -330,6 +330,7 @@ struct iso_graph {
     bool debug = false;              // count rare kernel branches (iso_debug_enable)
     uint64_t resweeps = 0;           // sweeps run again with a larger edge buffer
     uint64_t *vbits_dev = nullptr;   // device bitmap of iso_query_vertices (ceil(n / 64) words)
+    std::vector<double> xy;          // vertex coordinates given at load (the polygon output's embedding)
     std::unique_ptr<CoreGraph> coreg;         // isoPHAST-CD: core graph (built on first use)
     std::vector<CoreDijkstra> cdj;            // one workspace per host thread
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> cd_out;   // per worker: settled core labels

@@ -58,6 +58,7 @@ struct RunArgs {
     // vertices in range instead of edges (vbits set): per lane j < lanes, row j of ceil(n / 64)
     // words of vbits gets bit v % 64 of word v / 64 for every original id v in range; no edges
     uint64_t *vbits = nullptr;
+    bool vmask_only = false;     // vertex output kept as lane masks by position only (polygons)
     // one-to-many instead (tg set): distances from each lane's source to the target set's
     // targets, row j of tg_out (tg->count words) for lane j < lanes; no cells, no edges
     const TargetSet *tg = nullptr;
@@ -106,6 +107,40 @@ struct TargetSet {
     uint32_t *d_row = nullptr;           // count: row of each target
     uint64_t bytes = 0;
     void release();
+};
+
+// Rotation system of the input graph for the polygon output (polygon.hip): darts are the
+// ordered neighbour pairs (u, v) of the undirected input, numbered in (u, v) order over
+// original ids (CSR d_off over u, n + 1 words).
+struct Rotation {
+    bool ready = false;
+    uint64_t darts = 0, bytes = 0;
+    uint32_t *d_off = nullptr;     // n + 1: first dart of each original id
+    uint32_t *d_hpos = nullptr;    // per dart: sweep position of the head
+    uint32_t *d_hid = nullptr;     // per dart: original id of the head
+    uint32_t *d_twin = nullptr;    // per dart: the dart (v, u)
+    uint32_t *d_fnext = nullptr;   // per dart (a, b): the next dart (b, c) of the face on its left
+    void release();
+};
+
+// Work buffers of the polygon kernels (grown on demand, kept between calls).
+struct PolyBufs {
+    size_t cap = size_t(1) << 16;   // boundary-dart capacity of the enumeration
+    uint64_t *d_keys = nullptr, *d_keys2 = nullptr, *d_scan = nullptr, *d_scx = nullptr;
+    uint32_t *d_nxt = nullptr, *d_mn = nullptr, *d_rk = nullptr, *d_w = nullptr, *d_cyc = nullptr,
+             *d_small = nullptr;
+    uint2 *d_out = nullptr;
+    void *d_sort_tmp = nullptr, *d_scan_tmp = nullptr;
+    size_t sz_keys = 0, sz_keys2 = 0, sz_scan = 0, sz_scx = 0, sz_nxt = 0, sz_mn = 0, sz_rk = 0, sz_w = 0,
+           sz_cyc = 0, sz_small = 0, sz_out = 0, sz_sort_tmp = 0, sz_scan_tmp = 0;
+    void release();
+};
+
+// Polygons of one sweep's lanes: darts as (tail, head) pairs in cycle order, lane j's darts
+// [loff[j], loff[j + 1]); cycle starts (indices into the darts), lane j's cycles
+// [lcyc[j], lcyc[j + 1]).
+struct PolyResult {
+    std::vector<uint32_t> darts, cyc, loff, lcyc;
 };
 
 struct QueryBufs {
@@ -231,6 +266,13 @@ struct DevGraph {
     std::vector<uint32_t> cell_cnt, cell_words, cell_core_refs;
     std::vector<uint64_t> cell_entries;
     uint64_t core_entries = 0;
+
+    // polygon output (polygon.hip): the rotation system built from the coordinates on first
+    // use, and the polygon kernels after a vertex-mask sweep on C
+    Rotation rot;
+    PolyBufs poly;
+    int upload_rotation(const iso::Prep &P, const double *xy, int threads);
+    int polygons(SweepCtx &C, uint32_t lanes, PolyResult &out);
 
     int upload(const iso::Prep &P, int device);
     // launch: copies the inputs and enqueues the whole sweep on C.stream (asynchronous);

@@ -351,6 +351,7 @@ int iso_load_graph(const iso_graph_desc *d, iso_graph **out) {
             g->up_out.resize(W);
             g->pool = std::make_unique<WorkerPool>(W);
         }
+        if (d->xy) g->xy.assign(d->xy, d->xy + 2 * size_t(d->n));
         g->out_cap = std::max<size_t>(1 << 16, std::min<size_t>(g->P.m / 4 + 1024, size_t(1) << 24));
         if (d->device >= 0) {
             int r = g->D.upload(g->P, d->device);
@@ -755,8 +756,9 @@ int iso_query_batch_device_noalloc(iso_graph *g, size_t k, const uint32_t *sourc
 }
 
 // One sweep of k <= 64 queries whose output is the vertices in range: bitmap rows of
-// ceil(n / 64) words per query at `bits` (device).  With `caller` set, its queued work is
-// waited for first.
+// ceil(n / 64) words per query at `bits` (device), or with bits NULL only the lane masks by
+// position in the sweep context (the polygon output).  With `wait` set, the caller's queued
+// work is waited for first.
 static int vertices_sweep(iso_graph *g, size_t k, const uint32_t *src, const uint32_t *tau, int mode,
                           uint64_t *bits, bool wait, hipStream_t caller) {
     const double t0 = now_ms();
@@ -766,6 +768,7 @@ static int vertices_sweep(iso_graph *g, size_t k, const uint32_t *src, const uin
     build_run_args(g, src, tau, uint32_t(k), mode == ISO_MODE_PLAIN, false, A, settled.data(), mode == ISO_MODE_CD);
     A.out_cap = g->out_cap;
     A.vbits = bits;
+    A.vmask_only = bits == nullptr;
     const double t1 = now_ms();
     if (wait) {
         int r = wait_for_caller(g->D, caller, false);
@@ -829,6 +832,74 @@ int iso_query_vertices(iso_graph *g, uint32_t source, uint32_t tau, int mode, ui
         for (uint64_t w = h[i]; w; w &= w - 1) out[k++] = uint32_t(i * 64 + size_t(__builtin_ctzll(w)));
     *vertices = out;
     *count = cnt;
+    return ISO_OK;
+}
+
+int iso_query_polygon_batch(iso_graph *g, size_t k, const uint32_t *sources, const uint32_t *taus, int mode,
+                            iso_edge **darts, size_t *dart_off, uint64_t **cycles, size_t *cycle_off) {
+    if (darts) *darts = nullptr;
+    if (cycles) *cycles = nullptr;
+    if (!darts || !dart_off || !cycles || !cycle_off || !sources || !taus) return fail(ISO_EINVAL, "NULL argument");
+    if (!g) return fail(ISO_EINVAL, "graph handle is NULL");
+    if (!g->on_device) return fail(ISO_EDEVICE, "graph was loaded without a device");
+    if (k < 1 || k > isodev::MAX_LANES) return fail(ISO_EINVAL, "k must be in [1, 64]");
+    for (size_t j = 0; j < k; ++j) {
+        int r = check_query(g, sources[j], taus[j], mode);
+        if (r) return r;
+    }
+    if (g->xy.empty()) return fail(ISO_ESTATE, "polygons need the vertex coordinates (desc.xy at load)");
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(ISO_EBUSY, "graph handle in use");
+    if (hipSetDevice(g->D.device) != hipSuccess) return fail(ISO_EDEVICE, "hipSetDevice failed");
+    int r;
+    if (!g->D.rot.ready) {
+        try {
+            if ((r = g->D.upload_rotation(g->P, g->xy.data(), g->threads))) return fail(r, iso_last_error());
+        } catch (const std::bad_alloc &) {
+            return fail(ISO_ENOMEM, "out of host memory building the rotation system");
+        }
+    }
+    if ((r = vertices_sweep(g, k, sources, taus, mode, nullptr, false, nullptr))) return r;
+    const double t0 = now_ms();
+    isodev::PolyResult PR;
+    try {
+        if ((r = g->D.polygons(g->D.main, uint32_t(k), PR))) return fail(r, iso_last_error());
+    } catch (const std::bad_alloc &) {
+        return fail(ISO_ENOMEM, "out of host memory for the polygons");
+    }
+    const size_t nd = PR.loff[k], nc = PR.lcyc[k];
+    iso_edge *d = (iso_edge *)std::malloc(std::max<size_t>(1, nd) * sizeof(iso_edge));
+    uint64_t *c = (uint64_t *)std::malloc((nc + 1) * sizeof(uint64_t));
+    if (!d || !c) {
+        std::free(d);
+        std::free(c);
+        return fail(ISO_ENOMEM, "out of host memory for the result");
+    }
+    if (nd) std::memcpy(d, PR.darts.data(), nd * sizeof(iso_edge));
+    for (size_t i = 0; i < nc; ++i) c[i] = PR.cyc[i];
+    c[nc] = nd;
+    for (size_t j = 0; j <= k; ++j) {
+        dart_off[j] = PR.loff[j];
+        cycle_off[j] = PR.lcyc[j];
+    }
+    *darts = d;
+    *cycles = c;
+    g->last.edges = nd;
+    g->last.t_sort_ms = now_ms() - t0;
+    g->last.t_total_ms += g->last.t_sort_ms;
+    return ISO_OK;
+}
+
+int iso_query_polygon(iso_graph *g, uint32_t source, uint32_t tau, int mode, iso_edge **darts, size_t *count,
+                      uint64_t **cycles, size_t *ncycles) {
+    if (darts) *darts = nullptr;
+    if (cycles) *cycles = nullptr;
+    if (!count || !ncycles) return fail(ISO_EINVAL, "NULL output pointer");
+    size_t doff[2], coff[2];
+    int r = iso_query_polygon_batch(g, 1, &source, &tau, mode, darts, doff, cycles, coff);
+    if (r) return r;
+    *count = doff[1];
+    *ncycles = coff[1];
     return ISO_OK;
 }
 

@@ -2054,6 +2054,9 @@ void DevGraph::release() {
     if (aux_ready) aux.release();
     aux_ready = false;
     fixed.release();
+    hipSetDevice(device);
+    rot.release();
+    poly.release();
     if (fixed_wait) hipEventDestroy(fixed_wait);
     fixed_wait = nullptr;
     hipSetDevice(device);
@@ -2265,7 +2268,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     if ((r = ensure(B.fixed, (void **)&B.d_keys_sorted, B.sz_keys_sorted, cap * 8))) return r;
     if ((r = ensure(B.fixed, (void **)&B.d_lane_off, B.sz_lane_off, (MAX_LANES + 1) * 4))) return r;
     if (A.want_dist && (r = ensure(B.fixed, (void **)&B.d_dist, B.sz_dist, size_t(n) * K * 4))) return r;
-    const bool vmode = A.vbits != nullptr;
+    const bool vmode = A.vbits != nullptr || A.vmask_only;
     if (vmode) {
         if ((r = ensure(B.fixed, (void **)&B.d_vmask, B.sz_vmask, size_t(n) * 8))) return r;
         if ((r = ensure(B.fixed, (void **)&B.d_cin, B.sz_cin, size_t(std::max(1u, num_cells)) * 8))) return r;
@@ -2551,7 +2554,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                                                    reinterpret_cast<unsigned long long *>(B.d_prof),
                                                    chunks ? (packed2 ? 2u : 1u) : 0u, cell_lg);
     }
-    if (vmode) {   // lane masks by position -> one bitmap row per lane over the original ids
+    if (A.vbits) {   // lane masks by position -> one bitmap row per lane over the original ids
         const uint32_t W = (n + 63) / 64;
         k_vmask_out<<<dim3((n + 255) / 256), dim3(256), 0, s>>>(B.d_vmask, d_pos, n, W, A.lanes, A.vbits);
     }

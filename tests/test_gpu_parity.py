@@ -186,9 +186,9 @@ def test_road1m_config():
 def test_road18m_benchmark_batch_sampled():
     """The benchmark's workload at full size in the benchmark's launch configuration: the first
     128 queries of its timed region through iso_query_batch_device (two 64-query sweeps overlapping on two
-    streams, default tuning, edges left in device memory); sampled lanes of both sweeps equal the
+    streams, default tuning, edges left in device memory); 18 sampled lanes of both sweeps equal the
     oracle exactly, two lanes equal single queries in both modes, every lane's output is sorted,
-    unique and in range.  Then the vertex output of the first 64 queries: sampled lanes equal the
+    unique and in range, and two plain sweeps give every vertex its exact distance.  Then the vertex output of the first 64 queries: sampled lanes equal the
     oracle's vertices in range, and for every lane each isochrone edge has exactly one endpoint
     in the set."""
     import os
@@ -222,10 +222,14 @@ def test_road18m_benchmark_batch_sampled():
         for mode in (iso.MODE_CELLS, iso.MODE_PLAIN):
             np.testing.assert_array_equal(G.query(int(src[j]), int(tau[j]), mode), out[j], err_msg=f"lane {j}")
     orc = Oracle.from_graph(g)
-    for j in (0, 63, 64, 127):
+    for j in list(range(0, 128, 8)) + [63, 127]:   # 18 lanes of both sweeps
         say(f"oracle lane {j} (tau {int(tau[j])} ms)")
         want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
         np.testing.assert_array_equal(out[j], want, err_msg=f"lane {j}")
+    for j in (5, 70):   # every distance of a plain sweep
+        say(f"oracle distances lane {j}")
+        d, _ = G.distances(int(src[j]), int(tau[j]), iso.MODE_PLAIN)
+        np.testing.assert_array_equal(d, clamp_u32(orc.distances(int(src[j]))), err_msg=f"distances lane {j}")
     # vertices in range
     W = (g.n + 63) // 64
     bits = torch.full((64, W), -1, dtype=torch.int64, device="cuda:0")
