@@ -241,9 +241,10 @@ KERNELS = {"cell_sweep": ("k_cell_chunks", "cell_ms", "cell_launches", "cell_byt
            "core_levels": ("k_core_level64", "level_ms", "level_launches", "level_bytes", "level_bytes")}
 
 
-def roofline_of(prof, prof_iso, steps):
+def roofline_of(prof, prof_iso, steps, names=None):
     def entry(p, key):
         name, t, n, b_survey, b_hbm = KERNELS[key]
+        name = (names or {}).get(key, name)
         ms, launches = p[t], max(1, p[n])
         if ms <= 0:
             return None
@@ -503,7 +504,9 @@ def main():
     prof_plain = G.profile_read()
     G.profile_enable(False)
     # the plain sweep (every cell for every query): the same two kernels with their own bytes
-    plain_phases = roofline_of(prof_plain, None, np_steps)["kernels"]
+    # (at 64 queries per sweep the plain mode sweeps the cells as a stream of levels)
+    plain_names = {"cell_sweep": "k_plain_level64"} if lanes == 64 and G.get_tuning()["plain_sweep"] == 0 else None
+    plain_phases = roofline_of(prof_plain, None, np_steps, plain_names)["kernels"]
     log(f"plain batched (device output): {qps_plain:.1f} queries/s; kernels {plain_phases}")
 
     # the other output of Section 3: vertices in range, as one bitmap row per query over the

@@ -313,8 +313,8 @@ int iso_debug_read(iso_graph *g, uint64_t counts[8]);
 
 /*
  * Tuning knobs of the device sweep (the autotuner measures them; when never set:
- * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, cell_stage 2,
- * cell_block 0, table_max 0, stall 1, edge_cap 0).  lanes_per_launch: queries per sweep in
+ * lanes_per_launch 64, block 256, cell_lds_kb 64, use_graph 1, core_mode 0, cell_stage 2,
+ * cell_block 0, table_max 0, stall 1, edge_cap 0, overlap_cells 0, plain_sweep 0).  lanes_per_launch: queries per sweep in
  * iso_query_batch (1..64); block: threads per workgroup of the core level
  * kernel (64..1024, multiple of 64); cell_lds_kb: LDS budget of one cell
  * workgroup in KiB (16..160), which sets how many queries' labels a cell
@@ -360,6 +360,12 @@ typedef struct {
                                    moves memory against repeated sweeps; the answer is the same */
     uint32_t overlap_cells;     /* resident cell workgroups per compute unit while two sweeps of one call
                                    overlap on two streams (0 = 2; at most what fits, at most 16) */
+    uint32_t plain_sweep;       /* ISO_MODE_PLAIN with 64 queries per sweep: 0 = the cells' internal vertices
+                                   as one launch per level counted from the top of each cell, across all
+                                   cells, one wavefront per vertex and the 64 queries' labels in device
+                                   memory (default; needs 4 * 64 * n bytes per sweep context); 1 = cell by
+                                   cell as in ISO_MODE_CELLS.  Other widths, the distance and vertex
+                                   outputs use the latter.  The answer is the same */
 } iso_tuning;
 int iso_set_tuning(iso_graph *g, const iso_tuning *t);
 int iso_get_tuning(const iso_graph *g, iso_tuning *t);

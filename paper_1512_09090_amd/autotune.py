@@ -1,8 +1,9 @@
 """Autotuner for the device sweep: queries per launch, core-kernel block size, LDS budget per
-cell workgroup (which sets the queries per cell work item), the cell-kernel variant (level
-pipeline or whole cell in LDS), hipGraph replay and the level-merge threshold (how many
-vertices of the top core levels are merged into one distance-table product instead of one
-launch per level).
+cell workgroup, the cell-kernel variant (one workgroup per active cell, or work items of a
+cell and some of its queries with a level pipeline or the whole cell in LDS), resident cell
+workgroups per compute unit while two sweeps overlap, hipGraph replay and the level-merge
+threshold (how many vertices of the top core levels are merged into one distance-table
+product instead of one launch per level).
 
 Coordinate search: starting from the defaults, each knob in turn is set to every candidate
 value while the others stay fixed; the best throughput (queries/s of iso_query_batch on a
@@ -20,16 +21,17 @@ import numpy as np
 from .binding import MODE_CELLS, Graph
 
 SPACE = {
-    "cell_stage": [0, 1],
-    "cell_block": [0, 256, 512],
-    "lanes_per_launch": [8, 16, 32, 64],
+    "cell_stage": [2, 0, 1],
+    "overlap_cells": [0, 1, 3],
+    "lanes_per_launch": [16, 32, 64],
     "block": [128, 256, 512],
-    "cell_lds_kb": [24, 40, 64, 96],
+    "cell_lds_kb": [40, 64, 96],
     "use_graph": [0, 1],
-    "table_max": [0, 1024, 4096, 8192],
+    "table_max": [0, 4096, 8192],
 }
-DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "cell_stage": 0, "cell_block": 0,
-           "table_max": 0, "stall": 1}
+# the library's defaults (include/iso.h), the search's starting point
+DEFAULT = {"lanes_per_launch": 64, "block": 256, "cell_lds_kb": 64, "use_graph": 1, "core_mode": 0, "cell_stage": 2,
+           "cell_block": 0, "table_max": 0, "stall": 1, "edge_cap": 0, "overlap_cells": 0, "plain_sweep": 0}
 
 
 def measure(G: Graph, sources, taus, mode=MODE_CELLS, repeats: int = 2) -> float:

@@ -53,7 +53,7 @@ class Tuning(C.Structure):
     _fields_ = [("lanes_per_launch", C.c_uint32), ("block", C.c_uint32), ("cell_lds_kb", C.c_uint32),
                 ("use_graph", C.c_uint32), ("core_mode", C.c_uint32), ("cell_stage", C.c_uint32),
                 ("cell_block", C.c_uint32), ("table_max", C.c_uint32), ("stall", C.c_uint32),
-                ("edge_cap", C.c_uint32), ("overlap_cells", C.c_uint32)]
+                ("edge_cap", C.c_uint32), ("overlap_cells", C.c_uint32), ("plain_sweep", C.c_uint32)]
 
 
 _U32P = C.POINTER(C.c_uint32)
@@ -419,9 +419,9 @@ class Graph:
         return {f: getattr(s, f) for f, _ in QueryStats._fields_}
 
     def set_tuning(self, lanes_per_launch=64, block=256, cell_lds_kb=64, use_graph=1, core_mode=0, cell_stage=2,
-                   cell_block=0, table_max=0, stall=1, edge_cap=0, overlap_cells=0):
+                   cell_block=0, table_max=0, stall=1, edge_cap=0, overlap_cells=0, plain_sweep=0):
         t = Tuning(lanes_per_launch, block, cell_lds_kb, use_graph, core_mode, cell_stage, cell_block, table_max,
-                   stall, edge_cap, overlap_cells)
+                   stall, edge_cap, overlap_cells, plain_sweep)
         _check(lib().iso_set_tuning(self._h, C.byref(t)))
 
     def profile_enable(self, enable: bool = True):

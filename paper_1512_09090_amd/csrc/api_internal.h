@@ -321,7 +321,7 @@ struct iso_graph {
     int threads = 1;
     std::atomic<bool> busy{false};
     iso_query_stats last{};
-    iso_tuning tuning{64, 256, 64, 1, 0, 2, 0, 0, 1, 0, 0};   // defaults (include/iso.h)
+    iso_tuning tuning{64, 256, 64, 1, 0, 2, 0, 0, 1, 0, 0, 0};   // defaults (include/iso.h)
     UpwardGraph upg;                // packed upward graph
     std::vector<UpwardSearch> up;   // one workspace per host thread
     std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep

@@ -49,6 +49,8 @@ struct RunArgs {
     bool debug = false;          // count rare kernel branches (QueryBufs::d_dbg)
     bool core64 = true;          // 64 queries per sweep: core levels one wavefront per vertex
     bool fill_uslot = false;     // refill the slot table first (its memory is shared with other calls)
+    bool plain_stream = true;    // plain mode at 64 queries per sweep: the internal vertices as a stream of
+                                 // levels across all cells (k_plain_level64) instead of cell by cell
     size_t out_cap = 0;          // capacity of the edge-key buffer
     uint32_t table_x = 0;        // top table used: core positions [0, table_x), the first table_levels levels
     uint32_t table_levels = 0;
@@ -199,6 +201,8 @@ struct SweepCtx {
     uint32_t K = 1, lk = 0, lg = 0, lanes = 0, lane_base = 0, nlev = 0, top = 0, cell_variant = 0;
     size_t cap = 0;
     bool mode_plain = true, want_dist = false, vertex_mode = false, one_to_many = false, levels_timed = false;
+    bool pstream = false;          // the plain sweep ran as a stream of levels (k_plain_level64)
+    uint32_t plain_launches = 0;   // its launches
     uint32_t *h_counters = nullptr;   // pinned: keys produced, active cells
     int create(int device);
     void release();
@@ -219,6 +223,14 @@ struct DevGraph {
     uint2 *d_down_arc = nullptr;
     uint32_t *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
     uint32_t *d_pos = nullptr;   // original id -> position (vertex output)
+    // plain sweep as a stream of levels across all cells (k_plain_level64): internal positions by
+    // their level from the top of their cell (launch l: [plvl_ptr[l], plvl_ptr[l + 1]) of
+    // d_plvl_pos), a bit per position whose label a downward entry reads, and the internal
+    // entries and read positions for the byte accounting
+    uint32_t *d_plvl_pos = nullptr, *d_readers = nullptr;
+    std::vector<uint32_t> plvl_ptr;
+    uint64_t plain_entries = 0, plain_written = 0;
+    uint32_t plain_per_cu = 0;   // resident k_plain_level64 blocks per compute unit (occupancy query)
     // top-of-hierarchy table: X = core positions [0, TX) covering the first nlev_table levels;
     // d_table[y * TX + x] = shortest downward path y -> x inside X
     uint32_t TX = 0, nlev_table = 0;
@@ -289,7 +301,7 @@ struct DevGraph {
     int run(SweepCtx &C, const RunArgs &A, RunResult &R);
     // device bytes a context needs for k lanes and an edge capacity (admission control),
     // including the radix sort's temporary storage for that capacity
-    size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const;
+    size_t ctx_bytes(uint32_t k, size_t cap, size_t upward_entries, bool plain = false) const;
     void release();
 };
 

@@ -60,6 +60,7 @@ void build_run_args(iso_graph *g, const uint32_t *src, const uint32_t *tau, uint
     A.want_dist = want_dist;
     A.debug = g->debug;
     A.core64 = g->tuning.core_mode == 0;
+    A.plain_stream = g->tuning.plain_sweep == 0;
     const uint32_t K = A.k_pow2;
     A.taus.assign(K, 0u);   // padding lanes: every label INF > 0, so they activate no cell and emit nothing
     A.src_cell.assign(K, iso::NO_CELL);
@@ -1164,6 +1165,7 @@ int iso_set_tuning(iso_graph *g, const iso_tuning *t) {
     if (t->table_max > isodev::TABLE_MAX) return fail(ISO_EINVAL, "table_max must be at most 16384");
     if (t->stall > 1) return fail(ISO_EINVAL, "stall must be 0 or 1");
     if (t->overlap_cells > 16) return fail(ISO_EINVAL, "overlap_cells must be at most 16");
+    if (t->plain_sweep > 1) return fail(ISO_EINVAL, "plain_sweep must be 0 or 1");
     if (t->core_mode != 0 && t->core_mode != 2)
         return fail(ISO_EINVAL, "core_mode must be 0 or 2 (1, a single-launch core sweep with a grid "
                                 "barrier, was removed)");

@@ -153,7 +153,8 @@ void completer_loop(iso_server *s) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 cap = std::max<size_t>(std::max(s->out_cap, f.args.out_cap * 2),
                                        size_t(R.count) + (size_t(R.count) >> 3));
-                const size_t need = g->D.ctx_bytes(s->lanes_cap, cap, size_t(s->lanes_cap) * 4096);
+                const size_t need = g->D.ctx_bytes(s->lanes_cap, cap, size_t(s->lanes_cap) * 4096,
+                                                   s->cfg.mode == ISO_MODE_PLAIN && g->tuning.plain_sweep == 0);
                 if (s->cfg.device_budget && need * s->ctxs.size() > s->cfg.device_budget) {
                     r = api_fail(ISO_ENOMEM, "the edge buffer this sweep needs exceeds the device budget");
                     break;
@@ -227,7 +228,8 @@ int iso_server_start(iso_graph *g, const iso_server_config *cfg, iso_server **ou
     s->out_cap = g->out_cap;
     // admission by device memory: fewer contexts first, then fewer lanes per sweep
     const size_t upward_per_lane = 4096;
-    auto need = [&](uint32_t k) { return g->D.ctx_bytes(k, s->out_cap, size_t(k) * upward_per_lane); };
+    const bool stream = cfg->mode == ISO_MODE_PLAIN && g->tuning.plain_sweep == 0;
+    auto need = [&](uint32_t k) { return g->D.ctx_bytes(k, s->out_cap, size_t(k) * upward_per_lane, stream); };
     uint32_t ctxs = inflight;
     if (cfg->device_budget) {
         while (ctxs > 1 && need(lanes) * ctxs > cfg->device_budget) --ctxs;

@@ -426,6 +426,126 @@ k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
     keys_end(s_keys, &s_n, &s_base, A);
 }
 
+// Vertices per wavefront of the plain sweep's stream (k_plain_level64): their loads are issued
+// together, so that a wavefront keeps several label rows in flight.
+constexpr uint32_t PV = 4;
+static_assert(2 * PV <= 64, "the header fetch uses 2 * PV lanes");
+
+// Labels of PV vertices for lane j (64 queries per sweep, rows of 64 words): dv[q] starts at
+// the vertex's upward label (or INF) and takes the minimum over its entries [beg[q], end[q]).
+// The first four entries of every vertex are loaded together (all entry words, then all tail
+// rows), then each vertex's further entries four at a time.  Every load is unconditional, its
+// index clamped to a valid one (entry 0 and row 0 always exist) and its value discarded where
+// the entry does not exist, so that the loads are issued back to back rather than each behind
+// a branch.  in / flag record, for the first 32 entries, whether the tail is in range for this
+// lane and whether the entry is flagged.
+__device__ __forceinline__ void relax64(const uint2 *__restrict__ darc, const uint32_t *__restrict__ lab,
+                                        const uint32_t (&beg)[PV], const uint32_t (&end)[PV], uint32_t (&dv)[PV],
+                                        uint32_t (&in)[PV], uint32_t (&flag)[PV], uint32_t tau, uint32_t j) {
+    uint2 a[PV][4];
+    uint32_t l[PV][4];
+#pragma unroll
+    for (uint32_t q = 0; q < PV; ++q)
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) a[q][u] = darc[beg[q] + u < end[q] ? beg[q] + u : 0u];
+#pragma unroll
+    for (uint32_t q = 0; q < PV; ++q)
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t t = beg[q] + u < end[q] ? (a[q][u].x & TAIL_MASK) : 0u;
+            l[q][u] = lab[(uint64_t(t) << 6) + j];
+        }
+#pragma unroll
+    for (uint32_t q = 0; q < PV; ++q) {
+        in[q] = 0;
+        flag[q] = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const bool ok = beg[q] + u < end[q];
+            dv[q] = min(dv[q], ok ? sat_add(l[q][u], a[q][u].y) : INF);
+            flag[q] |= uint32_t(ok && (a[q][u].x & FLAGS)) << u;
+            in[q] |= uint32_t(ok && l[q][u] <= tau) << u;
+        }
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < PV; ++q)
+        for (uint32_t e = beg[q] + 4; e < end[q]; e += 4) {
+            uint2 b[4];
+            uint32_t t[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) b[u] = darc[e + u < end[q] ? e + u : e];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) t[u] = lab[(uint64_t(b[u].x & TAIL_MASK) << 6) + j];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const bool ok = e + u < end[q];
+                dv[q] = min(dv[q], ok ? sat_add(t[u], b[u].y) : INF);
+                const uint32_t k = e - beg[q] + u;
+                if (k < 32) {
+                    flag[q] |= uint32_t(ok && (b[u].x & FLAGS)) << k;
+                    in[q] |= uint32_t(ok && t[u] <= tau) << k;
+                }
+            }
+        }
+}
+
+// The header of PV vertices (offsets, upward label): lanes fetch it for all PV vertices at
+// once (lane j reads the offset (j / PV) & 1 and the slot of vertex j mod PV), and the values
+// are read out of the lanes, so the header costs two memory round trips whatever PV is.
+// Vertex q is active iff act[q]; an inactive one gets no entries and label INF.
+__device__ __forceinline__ void header64(const CoreArgs &A, const uint32_t (&v)[PV], const bool (&act)[PV],
+                                         uint32_t (&beg)[PV], uint32_t (&end)[PV], uint32_t (&dv)[PV], uint32_t j) {
+    const uint32_t mq = j % PV;
+    uint32_t vq = v[0];
+#pragma unroll
+    for (uint32_t k = 1; k < PV; ++k) vq = mq == k ? v[k] : vq;
+    const uint32_t x = A.down_off[vq + ((j / PV) & 1u)];
+    const uint32_t y = A.uslot[vq];
+    uint32_t sl[PV];
+#pragma unroll
+    for (uint32_t q = 0; q < PV; ++q) {
+        beg[q] = uint32_t(__builtin_amdgcn_readlane(int(x), int(q)));
+        end[q] = uint32_t(__builtin_amdgcn_readlane(int(x), int(PV + q)));
+        sl[q] = uint32_t(__builtin_amdgcn_readlane(int(y), int(q)));
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < PV; ++q) {
+        const bool up = act[q] && sl[q] != NO_SLOT;
+        const uint32_t u = A.uval[(uint64_t(up ? sl[q] : 0u) << 6) + j];   // row 0 always exists
+        dv[q] = up ? u : INF;
+        if (!act[q]) end[q] = beg[q];
+    }
+}
+
+// Straddling flagged entries of vertex v (label dv, final): the first 32 entries from their
+// recorded bits, a vertex with more walks them again.  Every lane of the wavefront calls it.
+__device__ __forceinline__ void plain_extract(const CoreArgs &A, const uint2 *__restrict__ darc,
+                                              const uint32_t *__restrict__ lab, uint32_t beg, uint32_t end,
+                                              uint32_t in, uint32_t flag, uint32_t dv, uint32_t tau, uint32_t j,
+                                              uint64_t *s_keys, uint32_t *s_n) {
+    const bool vin = dv <= tau;
+    const uint32_t lane = A.lane_base + j;
+    if (end - beg <= 32) {
+        uint32_t st = flag & (vin ? ~in : in);
+        while (__any(st != 0)) {
+            const bool have = st != 0;
+            const uint32_t k = have ? uint32_t(__ffs(st) - 1) : 0u;
+            st &= st - 1u;
+            const uint32_t xw = have ? darc[beg + k].x : 0u;
+            push_key(xw & FLAG_FWD, entry_key(lane, beg + k, 0u), s_keys, s_n, A);
+            push_key(xw & FLAG_REV, entry_key(lane, beg + k, 1u), s_keys, s_n, A);
+        }
+    } else {
+        for (uint32_t e = beg; e < end; ++e) {   // uniform loop
+            const uint2 a = darc[e];
+            const bool str = (a.x & FLAGS) && ((lab[(uint64_t(a.x & TAIL_MASK) << 6) + j] <= tau) != vin);
+            if (A.dbg && str) atomicAdd(&A.dbg[2], 1ull);
+            push_key(str && (a.x & FLAG_FWD), entry_key(lane, e, 0u), s_keys, s_n, A);
+            push_key(str && (a.x & FLAG_REV), entry_key(lane, e, 1u), s_keys, s_n, A);
+        }
+    }
+}
+
 // A core level for 64 queries per sweep: one wavefront per vertex, lane j = query j.  The
 // vertex's offsets and entries are the same for the whole wavefront (scalar loads), and each
 // entry costs one coalesced 256-byte load of its tail's label row.  The first 32 entries'
@@ -497,6 +617,54 @@ __global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, uint32_t vbeg,
                 push_key(str && (a.x & FLAG_REV), entry_key(lane, e, 1u), s_keys, &s_n, A);
             }
         }
+    }
+    keys_end(s_keys, &s_n, &s_base, A);
+}
+
+// The plain sweep's internal vertices for 64 queries per sweep, one launch per level counted
+// from the top of each cell (Section 2, PHAST: levels in descending order).  A cell's level l
+// reads only the core and the cell's own higher levels, so the l-th levels of all cells form
+// one launch, and the internal vertices become a stream of about 20 launches of up to millions
+// of vertices each.  Labels are rows of 64 words in HBM (the core's rows, then the internal
+// positions'), as in k_core_level64: lane j = query j, entries read by scalar loads, one
+// coalesced 256-byte row per entry.  A wavefront takes PV consecutive vertices of the list at
+// a time and issues the loads of their first four entries together, so that each wavefront
+// keeps up to 4 * PV rows in flight (one vertex at a time left the stream bound by load
+// latency).  The grid is resident (a few blocks per compute unit): the blocks of XCD x (block
+// index mod 8) take the x-th eighth of the level's list and their wavefronts stride through
+// it, so that the vertices of one cell, consecutive in the list, meet in one XCD's L2.  A label
+// that no downward entry reads is not written back.
+__global__ void __launch_bounds__(256)
+k_plain_level64(CoreArgs A, const uint32_t *__restrict__ lpos, uint32_t lb, uint32_t le,
+                const uint32_t *__restrict__ readers) {
+    __shared__ uint64_t s_keys[CORE_KEYS];
+    __shared__ uint32_t s_n, s_base;
+    keys_begin(&s_n);
+    const uint32_t x = blockIdx.x & 7u, bx = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+    const uint32_t len = le - lb, per = (len + 7u) >> 3;
+    const uint32_t s0 = lb + min(len, x * per), s1 = lb + min(len, (x + 1u) * per);
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t w0 = bx * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = nbx * wpb;
+    const uint32_t j = __lane_id(), tau = A.taus[j];
+    const uint2 *__restrict__ darc = A.down_arc;
+    uint32_t *__restrict__ lab = A.dcore;
+    for (uint32_t i = s0 + w0 * PV; i < s1; i += nw * PV) {   // uniform over the wavefront
+        uint32_t v[PV], beg[PV], end[PV], dv[PV], in[PV], flag[PV];
+        bool act[PV];
+        const uint32_t mine = lpos[min(i + j % PV, s1 - 1u)];   // lane j: vertex j mod PV of the group
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q) {
+            act[q] = i + q < s1;
+            v[q] = uint32_t(__builtin_amdgcn_readlane(int(mine), int(q)));
+        }
+        header64(A, v, act, beg, end, dv, j);
+        relax64(darc, lab, beg, end, dv, in, flag, tau, j);
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q)
+            if (i + q < s1 && ((readers[v[q] >> 5] >> (v[q] & 31u)) & 1u)) lab[(uint64_t(v[q]) << 6) + j] = dv[q];
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q)
+            if (i + q < s1) plain_extract(A, darc, lab, beg[q], end[q], in[q], flag[q], dv[q], tau, j, s_keys, &s_n);
     }
     keys_end(s_keys, &s_n, &s_base, A);
 }
@@ -1845,11 +2013,44 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
     for (size_t i = 0; i < core_lvl.size(); ++i) core_lvl_entries[i] = P.down_off[core_lvl[i]];
     bytes = 0;
     int r;
-    // the core part of the downward graph (cells use their blobs)
-    std::vector<uint32_t> coff(P.down_off.begin(), P.down_off.begin() + n_core + 1);
-    if ((r = dev_alloc_copy(&d_down_off, coff, bytes))) return r;
-    if ((r = dev_alloc_copy((uint32_t **)&d_down_arc, P.down_arc.data(), 2 * size_t(P.down_off[n_core]), bytes)))
+    // the whole downward graph: the core levels read the core's part; the plain sweep's stream of
+    // levels (k_plain_level64) reads the rest (the cell kernels use their blobs)
+    if ((r = dev_alloc_copy(&d_down_off, P.down_off, bytes))) return r;
+    if ((r = dev_alloc_copy((uint32_t **)&d_down_arc, P.down_arc.data(), 2 * size_t(P.down_off[n]), bytes)))
         return r;
+    if (num_cells > 0) {
+        // internal positions grouped by their level counted from the top of their cell: level l of
+        // every cell is launch l of the plain sweep's stream.  A position whose label some
+        // downward entry reads is marked in `readers`.
+        uint32_t nl_max = 0;
+        for (uint32_t c = 0; c < num_cells; ++c) nl_max = std::max(nl_max, P.cell_lvl_ptr[c + 1] - P.cell_lvl_ptr[c]);
+        plvl_ptr.assign(nl_max + 1, 0);
+        std::vector<uint32_t> lpos;
+        lpos.reserve(n - n_core);
+        for (uint32_t l = 0; l < nl_max; ++l) {
+            for (uint32_t c = 0; c < num_cells; ++c) {
+                const uint32_t lp = P.cell_lvl_ptr[c], nl = P.cell_lvl_ptr[c + 1] - lp;
+                if (l >= nl) continue;
+                const uint32_t a = P.cell_lvl[lp + l], b = l + 1 < nl ? P.cell_lvl[lp + l + 1] : P.cell_off[c + 1];
+                for (uint32_t v = a; v < b; ++v) lpos.push_back(v);
+            }
+            plvl_ptr[l + 1] = uint32_t(lpos.size());
+        }
+        if (lpos.size() != size_t(n - n_core)) {
+            set_error("cell levels do not cover the internal positions");
+            return -1;
+        }
+        std::vector<uint32_t> readers((size_t(n) + 31) / 32, 0);
+        for (uint64_t e = 0; e < P.down_off[n]; ++e) {
+            const uint32_t t = P.down_arc[2 * e] & TAIL_MASK;
+            readers[t >> 5] |= 1u << (t & 31);
+        }
+        plain_entries = P.down_off[n] - P.down_off[n_core];
+        plain_written = 0;
+        for (uint32_t v = n_core; v < n; ++v) plain_written += (readers[v >> 5] >> (v & 31)) & 1u;
+        if ((r = dev_alloc_copy(&d_plvl_pos, lpos, bytes))) return r;
+        if ((r = dev_alloc_copy(&d_readers, readers, bytes))) return r;
+    }
     if ((r = dev_alloc_copy(&d_pos, P.pos, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_cell, P.core_cell, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_ecc, P.core_ecc, bytes))) return r;
@@ -2062,7 +2263,8 @@ void DevGraph::release() {
     hipSetDevice(device);
     void *ptrs[] = {d_down_off, d_down_arc, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
-                    d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair, d_blob2, d_cblob2};
+                    d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair, d_blob2, d_cblob2,
+                    d_plvl_pos, d_readers};
     for (void *p : ptrs) if (p) hipFree(p);
     (void)hipGetLastError();   // a failed free must not surface in another handle's next check
     device = -1;
@@ -2202,15 +2404,16 @@ static int ensure(bool fixed, void **p, size_t &have, size_t need) {
     return 0;
 }
 
-size_t DevGraph::ctx_bytes(uint32_t k, size_t cap, size_t upward_entries) const {
+size_t DevGraph::ctx_bytes(uint32_t k, size_t cap, size_t upward_entries, bool plain) const {
     uint32_t K = 1;
     while (K < k) K <<= 1;
+    const size_t rows = plain && K == 64 && d_plvl_pos ? n : n_core;   // the stream of levels keeps every row
     // temporary storage of the radix sort over cap keys (the size query allocates nothing)
     size_t sort_tmp = 0;
     if (hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
                                           int(std::min<size_t>(cap, size_t(INT32_MAX))), 0, 64) != hipSuccess)
         sort_tmp = cap * 8 + (1 << 20);
-    return size_t(n_core) * K * 4 + size_t(n) * 4 + upward_entries * (K + 3) * 4 + size_t(n_core) * 16 +
+    return rows * K * 4 + size_t(n) * 4 + upward_entries * (K + 3) * 4 + size_t(n_core) * 16 +
            size_t(num_cells) * (3 + MAX_LANES) * 4 + 2 * cap * 8 + sort_tmp + (1 << 20);
 }
 
@@ -2246,7 +2449,11 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         if ((r = ensure(B.fixed, (void **)&B.d_uslot, B.sz_uslot, size_t(n) * 4))) return r;
         k_fill<<<dim3(2048), dim3(256), 0, s>>>(B.d_uslot, NO_SLOT, uint64_t(n));
     }
-    size_t core_words = std::max<size_t>(1, size_t(n_core) * K);
+    // plain mode at 64 queries per sweep: the internal vertices as a stream of levels across all
+    // cells, their label rows after the core's
+    const bool pstream = A.plain_stream && A.mode_plain && K == 64 && A.core64 && num_cells > 0 && d_plvl_pos &&
+                         !A.want_dist && !A.vbits && !A.vmask_only && !A.tg && !A.core_dijkstra && !B.fixed;
+    size_t core_words = std::max<size_t>(1, size_t(pstream ? n : n_core) * K);
     if ((r = ensure(B.fixed, (void **)&B.d_dcore, B.sz_dcore, core_words * 4))) return r;
     if ((r = ensure(B.fixed, (void **)&B.d_uval, B.sz_uval, size_t(std::max(8192u, nu)) * K * 4))) return r;
     if ((r = ensure(B.fixed, (void **)&B.d_uin, B.sz_uin, size_t(std::max(1u, nu)) * 3 * 4))) return r;
@@ -2521,7 +2728,20 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             k_vmask_cells<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(B.d_cin, d_cmask, d_cell_off, num_cells,
                                                                            B.d_vmask);
         if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[2], s));
-        if (chunks) {
+        if (pstream) {
+            // a resident grid (every block starts at once: blocks stride through fixed shares of
+            // the level), a multiple of 8
+            if (!plain_per_cu) {
+                int nb = 0;
+                HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_plain_level64, 256, 0));
+                plain_per_cu = uint32_t(std::max(1, nb));
+            }
+            const uint32_t pgrid = (uint32_t(std::max(1, num_cus)) * plain_per_cu + 7u) & ~7u;
+            for (size_t l = 0; l + 1 < plvl_ptr.size(); ++l)
+                if (plvl_ptr[l + 1] > plvl_ptr[l])
+                    k_plain_level64<<<dim3(pgrid), dim3(256), 0, s>>>(CA, d_plvl_pos, plvl_ptr[l], plvl_ptr[l + 1],
+                                                                     d_readers);
+        } else if (chunks) {
             Cell2Args LA{d_clist, B.d_counters, d_blob2, d_cblob2, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot,
                          B.d_uval, d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr,
                          vmode ? B.d_vmask : nullptr, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg,
@@ -2544,7 +2764,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         HIPCHK(hipEventRecord(C.prof.ev[2], s));
     }
     if (prof_on) HIPCHK(hipEventRecord(C.prof.ev[3], s));
-    if (prof_on && num_cells > 0) {   // after the last phase event: not part of any phase's time
+    if (prof_on && num_cells > 0 && !pstream) {   // after the last phase event: not part of any phase's time
         if ((r = ensure(B.fixed, (void **)&B.d_prof, B.sz_prof, 8 * sizeof(uint64_t)))) return r;
         if (!C.prof.acc_ready) {
             k_fill<<<dim3(1), dim3(64), 0, s>>>(reinterpret_cast<uint32_t *>(B.d_prof), 0u, 16);   // 8 sums
@@ -2571,6 +2791,10 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     C.lg = lg;
     C.cell_variant = variant;
     C.levels_timed = !cd && n_core > 0;
+    C.pstream = pstream;
+    C.plain_launches = 0;
+    if (pstream)
+        for (size_t l = 0; l + 1 < plvl_ptr.size(); ++l) C.plain_launches += plvl_ptr[l + 1] > plvl_ptr[l];
     C.lanes = A.lanes;
     C.lane_base = A.lane_base;
     C.cap = cap;
@@ -2652,8 +2876,22 @@ int DevGraph::finish(SweepCtx &C, RunResult &R) {
             prof.active_ms += ms;
             HIPCHK(hipEventElapsedTime(&ms, prof.ev[2], prof.ev[3]));
             prof.cell_ms += ms;
-            prof.cell_launches++;
-            // the per-cell counts, work items and bytes are summed on the device (k_prof_cells)
+            if (C.pstream) {
+                // the stream of levels: every internal vertex for every lane.  Bytes: its list
+                // entry, offsets and slot; its entries; per lane each entry's tail label read and
+                // the label written back where an entry reads it
+                const uint64_t ni = n - n_core, ne = plain_entries, nlv = C.plain_launches;
+                prof.cell_launches += nlv;
+                prof.cell_bytes += 12ull * ni + 4ull * nlv + 8ull * ne + 4ull * K * (ne + plain_written);
+                prof.cell_bytes_survey += 4ull * (ni + 1) + 8ull * ne + 8ull * ni * C.lanes;
+                prof.cells_swept += num_cells;
+                prof.cell_lanes += uint64_t(num_cells) * C.lanes;
+                prof.cell_vertices += ni;
+                prof.cell_entries += ne;
+            } else {
+                prof.cell_launches++;
+                // the per-cell counts, work items and bytes are summed on the device (k_prof_cells)
+            }
         }
     }
     if (C.vertex_mode) {   // the vertex bitmaps are written; the edge keys are not used

@@ -136,6 +136,56 @@ def test_batch_equals_singles(road50k, k):
             np.testing.assert_array_equal(out[j], want)
 
 
+def _plain_both_ways(G, src, tau):
+    """64-query plain sweeps as a stream of levels (default) and cell by cell: lane for lane equal."""
+    G.set_tuning(plain_sweep=1)
+    ref = G.query_batch(src, tau, iso.MODE_PLAIN)
+    G.set_tuning()
+    out = G.query_batch(src, tau, iso.MODE_PLAIN)
+    for j in range(len(src)):
+        np.testing.assert_array_equal(out[j], ref[j], err_msg=f"lane {j}")
+    return out
+
+
+def test_plain_stream_of_levels(road50k):
+    """The plain sweep's stream of levels across all cells (64 queries per sweep) against the
+    cell-by-cell sweep and the oracle: a road graph (sources spread, some in one cell, limits up
+    to past every distance), a one-way graph with uncovered cells, random digraphs with random
+    cells and zero-length arcs, and a profile that counts its launches."""
+    g, orc, G = road50k
+    src, tau = synth.batch_queries(g.n, 64, seed=321, lo_min=1, hi_min=120)
+    src[:8] = src[0]
+    tau[:4] = [0, 1, 40_000_000, 3_600_000]
+    G.profile_enable(True)
+    out = _plain_both_ways(G, src, tau)
+    prof = G.profile_read()
+    G.profile_enable(False)
+    say(f"profile {prof}")
+    assert prof["cell_launches"] > prof["calls"]   # the stream: one launch per level
+    for j in (0, 1, 2, 3, 7, 31, 63):
+        want, _, _ = orc.isochrone(int(src[j]), int(tau[j]))
+        np.testing.assert_array_equal(out[j], want, err_msg=f"lane {j}")
+    g1 = synth.road_graph(30_000, 32, oneway_frac=0.3)
+    G1 = iso.Graph.from_synth(g1, num_cells=128, device=0)
+    o1 = Oracle.from_graph(g1)
+    s1, t1 = synth.batch_queries(g1.n, 64, seed=322, lo_min=1, hi_min=200)
+    out1 = _plain_both_ways(G1, s1, t1)
+    for j in (0, 21, 42, 63):
+        np.testing.assert_array_equal(out1[j], o1.isochrone(int(s1[j]), int(t1[j]))[0], err_msg=f"one-way lane {j}")
+    for seed in range(3):
+        gr = synth.random_digraph(400, 1400, seed=900 + seed, wmax=40, zero_frac=0.15)
+        rng = np.random.default_rng(seed)
+        cells = rng.integers(0, 6, size=gr.n).astype(np.uint32)
+        Gr = iso.Graph(gr.n, gr.tail, gr.head, gr.w, cell_of=cells, num_cells=6, device=0)
+        orr = Oracle.from_graph(gr)
+        sr = rng.integers(0, gr.n, size=64).astype(np.uint32)
+        tr = rng.integers(0, 200, size=64).astype(np.uint32)
+        outr = _plain_both_ways(Gr, sr, tr)
+        for j in range(0, 64, 9):
+            np.testing.assert_array_equal(outr[j], orr.isochrone(int(sr[j]), int(tr[j]))[0],
+                                          err_msg=f"digraph {seed} lane {j}")
+
+
 def test_batch_lanes_per_launch(road50k):
     g, orc, G = road50k
     src, tau = synth.batch_queries(g.n, 40, seed=9, lo_min=1, hi_min=90)
