@@ -392,8 +392,9 @@ def main():
     ap.add_argument("--cd-minutes", default="5,15,45",
                     help="limits (minutes) of the isoPHAST-CD comparison; empty to skip")
     ap.add_argument("--cd-queries", type=int, default=40)
-    ap.add_argument("--profile-only", action="store_true",
-                    help="run only the warm-up and the timed cells-mode batches (for profiler runs)")
+    ap.add_argument("--profile-only", nargs="?", const="cells", default=None, choices=["cells", "plain"],
+                    help="run only the warm-up and the timed batches, in cells mode or (plain) the plain sweep "
+                         "(for profiler runs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates profiler byte counters)")
     ap.add_argument("--cache-dir", default=os.environ.get("ISO_CACHE", "/tmp/iso_cache"))
@@ -450,7 +451,8 @@ def main():
     dev = DeviceBatches(iso, G, per_query_hint=40_000)
     log(f"warmup {args.warmup} steps of {lanes} queries")
     ws, wt = window(0, max(1, args.warmup) * lanes)
-    dev.run(ws, wt, iso.MODE_CELLS)
+    timed_mode = iso.MODE_PLAIN if args.profile_only == "plain" else iso.MODE_CELLS
+    dev.run(ws, wt, timed_mode)
     dev.hint = max(dev.hint, 2.0 * int(dev.offsets[len(ws)].item()) / len(ws))
     ts_, tt_ = window(args.warmup * lanes, args.steps * lanes)
     dev.reserve(len(ts_))   # the timed call's result buffers, allocated before the timed region
@@ -459,7 +461,7 @@ def main():
     log(f"timed {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    edges_total = dev.run(ts_, tt_, iso.MODE_CELLS)
+    edges_total = dev.run(ts_, tt_, timed_mode)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     prof = G.profile_read()
@@ -470,9 +472,12 @@ def main():
         f"{edges_total} edges; profile {prof}")
     log(f"timed call: {batch_stats}")
 
-    if args.profile_only:   # the timed cells-mode batches only (for profiler runs)
+    if args.profile_only:   # the timed batches only (for profiler runs)
+        names = {"cell_sweep": "k_plain_level64"} if (args.profile_only == "plain" and lanes == 64 and
+                                                        G.get_tuning()["plain_sweep"] == 0) else None
         print(json.dumps({"metric": METRIC, "value": round(qps, 2), "unit": "queries/s", "steps": args.steps,
-                          "profile_only": True, "profile": prof}), flush=True)
+                          "profile_only": args.profile_only, "profile": prof,
+                          "kernels": roofline_of(prof, None, args.steps, names)["kernels"]}), flush=True)
         return
 
     # the same through the host API (edges copied to host memory over PCIe): one call per batch,

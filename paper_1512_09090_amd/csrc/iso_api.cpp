@@ -1109,7 +1109,7 @@ int iso_profile_read(const iso_graph *g, iso_profile *o) {
         }
         o->core_ms += P.core_ms; o->active_ms += P.active_ms; o->cell_ms += P.cell_ms; o->sort_ms += P.sort_ms;
         o->core_launches += P.core_launches; o->cell_launches += P.cell_launches; o->calls += P.calls;
-        o->core_bytes += P.core_bytes; o->cell_bytes += P.cell_bytes;
+        o->core_bytes += P.core_bytes; o->cell_bytes += P.cell_bytes; o->cell_bytes_survey += P.cell_bytes_survey;
         o->core_entries += P.core_entries; o->cell_entries += P.cell_entries;
         o->cell_vertices += P.cell_vertices; o->cells_swept += P.cells_swept;
         o->cell_lanes += P.cell_lanes; o->cell_items += P.cell_items;
