@@ -529,6 +529,29 @@ def main():
     in_range = int(np.bitwise_count(vbits.cpu().numpy().view(np.uint64)).sum())
     log(f"vertices in range (device bitmaps): {qps_vert:.1f} queries/s; last batch {in_range} (vertex, query) pairs")
 
+    # isochrone polygons (Section 7): the embedding is built on the first call; then the same batches
+    # as the vertex output (host result: darts and cycle starts)
+    t0 = time.perf_counter()
+    G.polygon(int(vs_[0]), int(vt_[0]), iso.MODE_CELLS)
+    rot_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    darts = cycles = 0
+    for b in range(0, len(vs_), lanes):
+        dflat, _, _, coff = G.polygon_batch_raw(vs_[b:b + lanes], vt_[b:b + lanes], iso.MODE_CELLS)
+        darts += len(dflat)
+        cycles += int(coff[-1])
+    el = time.perf_counter() - t0
+    pstats = G.last_stats()
+    polygons = {"value": round(len(vs_) / el, 2), "unit": "queries/s", "ms_per_batch": round(1000 * el * lanes / len(vs_), 3),
+                "queries_per_call": lanes, "darts_per_query": round(darts / len(vs_), 1),
+                "cycles_per_query": round(cycles / len(vs_), 1), "embedding_build_s": round(rot_s, 2),
+                "last_call_ms": {"vertex_sweep": round(pstats["t_device_ms"] + pstats["t_upward_ms"], 3),
+                                 "polygon_kernels_and_copy": round(pstats["t_sort_ms"], 3)},
+                "note": "iso_query_polygon_batch on road18m's rotation system (the kNN stand-in is not planar: the "
+                        "cycles are the faces of the rotation system); paper's Section 7 context: tens of ms "
+                        "per polygon on one core"}
+    log(f"polygons: {polygons}")
+
     # one-to-many (RPHAST, the paper's Table 1 workload): a ball of 2^14 targets, sources drawn
     # from the ball, distances left in HBM (one call per batch of `lanes` sources)
     _, ball = synth.target_ball(g, 1 << 14, seed=16)
@@ -641,6 +664,7 @@ def main():
         "latency_ms": lat,
         "single_query_qps": {k: round(v, 2) for k, v in single_qps.items()},
         "batched_plain_qps": round(qps_plain, 2),
+        "polygons": polygons,
         "plain_sweep_roofline": dict(plain_phases, unit="GB/s", peak=HBM_PEAK_GBS,
                                      note="plain mode (every cell swept for every query), two overlapping "
                                           "streams, HIP events around the kernels' launches"),

@@ -89,7 +89,9 @@ typedef struct {
     const uint32_t *tail;       /* m tails, < n */
     const uint32_t *head;       /* m heads, < n */
     const uint32_t *weight;     /* m lengths, each <= 2^32 - 2 */
-    const double *xy;           /* optional, 2n coordinates (x0, y0, x1, y1, ...) for the partitioner */
+    const double *xy;           /* optional, 2n coordinates (x0, y0, x1, y1, ...): the partitioner's input
+                                   (with num_cells and no cell_of) and the embedding of the polygon output
+                                   (copied and kept with the graph) */
     const uint32_t *cell_of;    /* optional explicit single-level partition: a cell id < num_cells per vertex */
     uint32_t num_cells;         /* cells of the single-level partition (Section 5), at most 2^24; 0 = no
                                    partition: the hierarchy is a plain CH and only ISO_MODE_PLAIN is

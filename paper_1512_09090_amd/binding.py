@@ -358,10 +358,9 @@ class Graph:
         _check(lib().iso_query_batch_vertices_device(self._h, k, sp, tp, int(mode), C.c_void_p(bits.data_ptr()),
                                                      C.c_void_p(stream)))
 
-    def polygon_batch(self, sources, taus, mode: int = MODE_PLAIN) -> list[list[np.ndarray]]:
-        """Isochrone polygons of k <= 64 queries (iso_query_polygon_batch): per query a list of
-        cycles, each an (len, 2) uint32 array of boundary darts (tail in range, head not) in
-        cycle order from its smallest dart, the cycles ordered by that dart."""
+    def polygon_batch_raw(self, sources, taus, mode: int = MODE_PLAIN):
+        """iso_query_polygon_batch as flat arrays: darts (total, 2) uint32 in cycle order, dart_off
+        (k + 1), cycles (cycle starts into darts, then the total) and cycle_off (k + 1)."""
         s, sp = _u32(sources)
         t, tp = _u32(taus)
         k = s.size
@@ -371,12 +370,18 @@ class Graph:
         cp = _U64P()
         _check(lib().iso_query_polygon_batch(self._h, k, sp, tp, int(mode), C.byref(dp), doff, C.byref(cp), coff))
         try:
-            nd, nc = doff[k], coff[k]
-            cyc = np.ctypeslib.as_array(cp, shape=(nc + 1,)).copy()
+            cyc = np.ctypeslib.as_array(cp, shape=(coff[k] + 1,)).copy()
         finally:
             lib().iso_free(cp)
-        flat = _edges_to_numpy(dp, nd)
-        return [[flat[int(cyc[c]):int(cyc[c + 1])] for c in range(coff[j], coff[j + 1])] for j in range(k)]
+        darts = _edges_to_numpy(dp, doff[k])
+        return darts, np.array(doff[:], dtype=np.int64), cyc.astype(np.int64), np.array(coff[:], dtype=np.int64)
+
+    def polygon_batch(self, sources, taus, mode: int = MODE_PLAIN) -> list[list[np.ndarray]]:
+        """Isochrone polygons of k <= 64 queries (iso_query_polygon_batch): per query a list of
+        cycles, each an (len, 2) uint32 array of boundary darts (tail in range, head not) in
+        cycle order from its smallest dart, the cycles ordered by that dart."""
+        darts, doff, cyc, coff = self.polygon_batch_raw(sources, taus, mode)
+        return [[darts[cyc[c]:cyc[c + 1]] for c in range(coff[j], coff[j + 1])] for j in range(len(coff) - 1)]
 
     def polygon(self, source: int, tau: int, mode: int = MODE_PLAIN) -> list[np.ndarray]:
         """The isochrone polygon of one query (iso_query_polygon), as polygon_batch's lists."""

@@ -127,7 +127,8 @@ struct Rotation {
 
 // Work buffers of the polygon kernels (grown on demand, kept between calls).
 struct PolyBufs {
-    size_t cap = size_t(1) << 16;   // boundary-dart capacity of the enumeration
+    size_t cap = size_t(1) << 12;   // boundary-dart capacity of the enumeration (grown as calls need; small
+                                    // at first, so that the first calls take the grow-and-repeat path)
     uint64_t *d_keys = nullptr, *d_keys2 = nullptr, *d_scan = nullptr, *d_scx = nullptr;
     uint32_t *d_nxt = nullptr, *d_mn = nullptr, *d_rk = nullptr, *d_w = nullptr, *d_cyc = nullptr,
              *d_small = nullptr;

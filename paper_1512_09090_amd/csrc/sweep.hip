@@ -14,21 +14,23 @@
 //      product per query); the rest runs one launch per level.
 //   2. active cells: i and (o or uncovered), plus the source's cell (Section 4
 //      definition of an active cell; Section 5 source-cell case).
-//   3. cell sweep: one workgroup per active cell (cells are independent,
-//      Section 5 parallelisation).  Labels of the cell and of the core vertices
-//      it references live in LDS; each level's arcs are prefetched while the
-//      previous level is relaxed; levels are separated by workgroup barriers and
-//      isochrone edges are extracted as soon as a label is final.
-// In the plain mode step 2 selects every cell (a PHAST one-to-all sweep).
+//   3. cell sweep: one workgroup per active cell for all the queries that
+//      activate it (cells are independent, Section 5 parallelisation).  The
+//      cell's data and the labels of its vertices and of the core vertices it
+//      references live in LDS; levels are separated by workgroup barriers (the
+//      narrow top levels by wavefront fences) and isochrone edges are extracted
+//      as soon as a label is final.
+// In the plain mode step 2 selects every cell (a PHAST one-to-all sweep); with 64
+// queries per sweep step 3 is instead a stream of launches, one per cell level
+// across all cells, with the labels in device memory.
 //
 // k queries share one sweep: labels are stored k-interleaved (row of k uint32
-// per vertex).  In the core kernels a group of S*k lanes serves one vertex:
-// k lanes (one per query) times S sub-lanes that split the vertex's arc list,
-// combined by a shuffle-xor minimum.  Isochrone edges are collected per
-// workgroup in LDS and appended with one output reservation per workgroup as
-// 64-bit keys lane << r | rank, where rank is the arc's index among all arcs
-// ordered by (tail, head) over original ids and r = ceil(log2 m); a radix sort
-// over their r + log2 k bits orders them by (query, tail, head).
+// per vertex).  Isochrone edges are collected per workgroup in LDS and appended
+// with one output reservation per workgroup as 64-bit keys
+// lane << 33 | downward entry << 1 | direction; before the sort each key becomes
+// lane << r | rank, where rank is the arc's index among all arcs ordered by
+// (tail, head) over original ids and r = ceil(log2 m), and a radix sort over
+// r + log2 k bits orders them by (query, tail, head).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
