@@ -327,6 +327,7 @@ struct iso_graph {
     std::unique_ptr<WorkerPool> pool;   // runs the upward searches of a sweep
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> up_out;   // one search result buffer per worker
     size_t out_cap = 1 << 20;
+    double edges_per_query = 0;      // of the last multi-sweep host-result call (sizes the next result block)
     bool debug = false;              // count rare kernel branches (iso_debug_enable)
     uint64_t resweeps = 0;           // sweeps run again with a larger edge buffer
     uint64_t *vbits_dev = nullptr;   // device bitmap of iso_query_vertices (ceil(n / 64) words)

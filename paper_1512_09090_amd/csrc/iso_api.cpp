@@ -160,7 +160,7 @@ struct PinnedPool {
     std::unordered_map<void *, size_t> owned;      // every block of the pool -> capacity
     std::multimap<size_t, void *> idle;            // blocks not handed out, by capacity
     size_t idle_bytes = 0;
-    static constexpr size_t KEEP = size_t(512) << 20;   // idle pinned memory kept for reuse
+    static constexpr size_t KEEP = size_t(1) << 30;   // idle pinned memory kept for reuse
 };
 PinnedPool &pool() {
     static PinnedPool *P = new PinnedPool();   // never destroyed: blocks may outlive static teardown
@@ -451,6 +451,14 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
     out.pinned = true;
     size_t cap = 0;
     if (offsets) offsets[0] = 0;
+    if (!dev && nsweeps > 1 && g->edges_per_query > 0) {
+        // a block for the expected result at once (the last multi-sweep call's edges per query and
+        // an eighth more): growing from a small block copies the result several times over
+        const size_t want = size_t(g->edges_per_query * double(k) * 1.125) + 1024;
+        size_t got = 0;
+        out.p = (iso_edge *)pinned_get(want * sizeof(iso_edge), got);
+        cap = out.p ? got / sizeof(iso_edge) : 0;
+    }
     struct Sweep {
         isodev::RunArgs A;
         isodev::SweepCtx *C = nullptr;
@@ -557,6 +565,7 @@ static int query_many(iso_graph *g, size_t k, const uint32_t *src, const uint32_
         }
     }
     g->last.edges = out.n;
+    if (!dev && nsweeps > 1) g->edges_per_query = double(out.n) / double(k);
     if (dev) {
         g->last.t_total_ms = now_ms() - t0;
         return dev->over ? fail(ISO_ESPACE, "device edge buffer holds " + std::to_string(dev->cap) +
