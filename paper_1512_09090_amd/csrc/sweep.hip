@@ -1441,8 +1441,7 @@ k_cell_sweep(CellArgs A) {
 //   (padding to an even word), then the entries, one word each in the packed form:
 //     bits [0, LB) tail's row (internal vertex i < stored: i; core ref r: stored + r),
 //     bit LB the forward original arc, bit LB + 1 the reverse one, bits [LB + 2, 32) the length
-//     (below 2^(29 - LB); all ones for the dummy entry's infinite length, so that an arithmetic
-//     shift decodes it to INF),
+//     (below 2^(30 - LB) - 1; all ones for the dummy entry's infinite length),
 //   or two words each in the wide form (row | FWD bit 31 | REV bit 30, length), used when a
 //   length or a row index does not fit the packed word.
 // stored = lvl[nl - 1]: the rows of every level but the last.
@@ -1490,7 +1489,8 @@ __device__ __forceinline__ C2Ent c2_entry(const uint32_t *s_ent, uint32_t e, uin
         r.row = x & ((1u << lb) - 1u);
         r.fwd = (x >> lb) & 1u;
         r.rev = (x >> (lb + 1)) & 1u;
-        r.w = uint32_t(int32_t(x) >> (lb + 2));   // all ones (the dummy entry) -> INF
+        const uint32_t wc = x >> (lb + 2), wmax = 0xFFFFFFFFu >> (lb + 2);
+        r.w = wc == wmax ? INF : wc;   // all ones: the dummy entry's infinite length
     } else {
         const uint2 x = reinterpret_cast<const uint2 *>(s_ent)[e];
         r.row = x.x & LOCAL_MASK;
@@ -1946,7 +1946,7 @@ int DevGraph::upload_cell_blobs2(const iso::Prep &P, const std::vector<std::vect
         }
     }
     lb2 = std::max<uint32_t>(1, ilog2(max_rows2));
-    packed2 = lb2 <= 16 && uint64_t(wmax_seen) < (uint64_t(1) << (29 - lb2));
+    packed2 = lb2 <= 16 && uint64_t(wmax_seen) < (uint64_t(1) << (30 - lb2)) - 1;
     std::vector<uint32_t> cblob2(std::max<uint32_t>(1, num_cells), 0);
     uint64_t total = 0;
     max_blob2_words = 0;
