@@ -221,6 +221,7 @@ struct DevGraph {
     std::vector<uint32_t> core_lvl;
     std::vector<uint32_t> core_lvl_entries;   // down_off at each core level boundary
     uint32_t *d_down_off = nullptr;
+    uint2 *d_core_rec = nullptr;   // per core vertex: entry offsets and its first entries (k_core_level64)
     uint2 *d_down_arc = nullptr;
     uint32_t *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
     uint32_t *d_pos = nullptr;   // original id -> position (vertex output)

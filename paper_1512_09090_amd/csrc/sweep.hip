@@ -548,13 +548,18 @@ __device__ __forceinline__ void plain_extract(const CoreArgs &A, const uint2 *__
     }
 }
 
-// A core level for 64 queries per sweep: one wavefront per vertex, lane j = query j.  The
-// vertex's offsets and entries are the same for the whole wavefront (scalar loads), and each
-// entry costs one coalesced 256-byte load of its tail's label row.  The first 32 entries'
-// "tail in range" bits give the straddling entries once the label is final (a vertex with
-// more entries walks them again).  Block b of the grid takes the (b mod 8)-th eighth of the
-// level, as in k_core_level.
-__global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, uint32_t vbeg, uint32_t vend) {
+// A core level for 64 queries per sweep: one wavefront per vertex, lane j = query j.  A core
+// vertex's record (CORE_REC uint2 words: its entry offsets, then its first CORE_REC - 1 entries)
+// is read by the wavefront's lanes in one coalesced load, together with its slot in the upward
+// table, so that its entries' tail rows (one coalesced 256-byte load each, all issued together)
+// follow after one memory round trip instead of two.  Entries beyond the record come from the
+// downward CSR, eight at a time.  The first 32 entries' "tail in range" bits give the straddling
+// entries once the label is final (a vertex with more entries walks them again).  Block b of
+// the grid takes the (b mod 8)-th eighth of the level, as in k_core_level.
+constexpr uint32_t CORE_REC = 16;
+
+__global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, const uint2 *__restrict__ rec, uint32_t vbeg,
+                                                      uint32_t vend) {
     __shared__ uint64_t s_keys[CORE_KEYS];
     __shared__ uint32_t s_n, s_base;
     keys_begin(&s_n);
@@ -564,13 +569,36 @@ __global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, uint32_t vbeg,
     const uint32_t j = __lane_id();
     if (v < vend) {
         const uint32_t tau = A.taus[j];
-        const uint32_t beg = A.down_off[v], end = A.down_off[v + 1];
+        const uint2 r = rec[(uint64_t(v) * CORE_REC) + (j & (CORE_REC - 1))];   // lane u: record word u
         const uint32_t sl = A.uslot[v];
+        const uint32_t beg = uint32_t(__builtin_amdgcn_readlane(int(r.x), 0));
+        const uint32_t end = uint32_t(__builtin_amdgcn_readlane(int(r.y), 0));
         uint32_t dv = sl != NO_SLOT ? A.uval[(sl << 6) + j] : INF;
         uint32_t in = 0, flag = 0;   // per entry k < 32: tail in range (this lane), entry flagged
         const uint2 *__restrict__ darc = A.down_arc;
         const uint32_t *__restrict__ dc = A.dcore;
-        for (uint32_t e = beg; e < end; e += 8) {
+        {   // the record's entries: words 1 .. CORE_REC - 1 (padding: tail 0, length INF, no flags)
+            uint32_t tx[CORE_REC - 1], tw[CORE_REC - 1], l[CORE_REC - 1];
+#pragma unroll
+            for (uint32_t u = 0; u < CORE_REC - 1; ++u) {
+                tx[u] = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(u + 1)));
+                tw[u] = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(u + 1)));
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < CORE_REC - 1; ++u) l[u] = dc[((tx[u] & TAIL_MASK) << 6) + j];
+#pragma unroll
+            for (uint32_t u = 0; u < CORE_REC - 1; ++u) {
+                dv = min(dv, sat_add(l[u], tw[u]));
+                flag |= ((tx[u] & FLAGS) ? 1u : 0u) << u;
+                in |= uint32_t(l[u] <= tau) << u;
+            }
+            // the padding words' bits: cleared
+            const uint32_t nrec = min(end - beg, CORE_REC - 1);
+            const uint32_t keep = nrec >= 32 ? ~0u : ((1u << nrec) - 1u);
+            in &= keep;
+            flag &= keep;
+        }
+        for (uint32_t e = beg + CORE_REC - 1; e < end; e += 8) {
             uint2 a[8];
             uint32_t l[8];
 #pragma unroll
@@ -2053,6 +2081,18 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
         if ((r = dev_alloc_copy(&d_plvl_pos, lpos, bytes))) return r;
         if ((r = dev_alloc_copy(&d_readers, readers, bytes))) return r;
     }
+    {   // per core vertex its record: entry offsets, then its first CORE_REC - 1 entries
+        std::vector<uint2> rec(std::max<size_t>(1, size_t(n_core) * CORE_REC), make_uint2(0u, INF));
+        for (uint32_t v = 0; v < n_core; ++v) {
+            uint2 *w = rec.data() + size_t(v) * CORE_REC;
+            w[0] = make_uint2(P.down_off[v], P.down_off[v + 1]);
+            for (uint32_t u = 0; u + 1 < CORE_REC && P.down_off[v] + u < P.down_off[v + 1]; ++u) {
+                const uint64_t e = uint64_t(P.down_off[v]) + u;
+                w[u + 1] = make_uint2(P.down_arc[2 * e], P.down_arc[2 * e + 1]);
+            }
+        }
+        if ((r = dev_alloc_copy(&d_core_rec, rec, bytes))) return r;
+    }
     if ((r = dev_alloc_copy(&d_pos, P.pos, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_cell, P.core_cell, bytes))) return r;
     if ((r = dev_alloc_copy(&d_core_ecc, P.core_ecc, bytes))) return r;
@@ -2266,7 +2306,7 @@ void DevGraph::release() {
     void *ptrs[] = {d_down_off, d_down_arc, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
                     d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair, d_blob2, d_cblob2,
-                    d_plvl_pos, d_readers};
+                    d_plvl_pos, d_readers, d_core_rec};
     for (void *p : ptrs) if (p) hipFree(p);
     (void)hipGetLastError();   // a failed free must not surface in another handle's next check
     device = -1;
@@ -2690,7 +2730,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                 uint32_t vb = core_lvl[l], ve = core_lvl[l + 1];
                 if (K == 64 && A.core64) {   // one wavefront per vertex, 4 per workgroup
                     uint32_t grid = ((ve - vb + 3) / 4 + 7u) & ~7u;
-                    k_core_level64<<<dim3(grid), dim3(256), 0, s>>>(CA, vb, ve);
+                    k_core_level64<<<dim3(grid), dim3(256), 0, s>>>(CA, d_core_rec, vb, ve);
                     continue;
                 }
                 uint32_t ls = level_ls(ve - vb, core_lvl_entries[l + 1] - core_lvl_entries[l], K);
