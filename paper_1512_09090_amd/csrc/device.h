@@ -225,11 +225,11 @@ struct DevGraph {
     uint2 *d_down_arc = nullptr;
     uint32_t *d_core_cell = nullptr, *d_core_ecc = nullptr, *d_cell_off = nullptr;
     uint32_t *d_pos = nullptr;   // original id -> position (vertex output)
-    // plain sweep as a stream of levels across all cells (k_plain_level64): internal positions by
-    // their level from the top of their cell (launch l: [plvl_ptr[l], plvl_ptr[l + 1]) of
-    // d_plvl_pos), a bit per position whose label a downward entry reads, and the internal
-    // entries and read positions for the byte accounting
-    uint32_t *d_plvl_pos = nullptr, *d_readers = nullptr;
+    // plain sweep as a stream of levels across all cells (k_plain_level64): the internal positions'
+    // records (position, entry range, whether an entry reads the label, first entries) grouped by
+    // level from the top of their cell (launch l: records [plvl_ptr[l], plvl_ptr[l + 1])), and the
+    // internal entries and read positions for the byte accounting
+    uint2 *d_plvl_rec = nullptr;
     std::vector<uint32_t> plvl_ptr;
     uint64_t plain_entries = 0, plain_written = 0;
     uint32_t plain_per_cu = 0;   // resident k_plain_level64 blocks per compute unit (occupancy query)

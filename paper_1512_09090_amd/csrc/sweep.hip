@@ -431,93 +431,6 @@ k_core_level(CoreArgs A, uint32_t ls, uint32_t vbeg, uint32_t vend) {
 // Vertices per wavefront of the plain sweep's stream (k_plain_level64): their loads are issued
 // together, so that a wavefront keeps several label rows in flight.
 constexpr uint32_t PV = 4;
-static_assert(2 * PV <= 64, "the header fetch uses 2 * PV lanes");
-
-// Labels of PV vertices for lane j (64 queries per sweep, rows of 64 words): dv[q] starts at
-// the vertex's upward label (or INF) and takes the minimum over its entries [beg[q], end[q]).
-// The first four entries of every vertex are loaded together (all entry words, then all tail
-// rows), then each vertex's further entries four at a time.  Every load is unconditional, its
-// index clamped to a valid one (entry 0 and row 0 always exist) and its value discarded where
-// the entry does not exist, so that the loads are issued back to back rather than each behind
-// a branch.  in / flag record, for the first 32 entries, whether the tail is in range for this
-// lane and whether the entry is flagged.
-__device__ __forceinline__ void relax64(const uint2 *__restrict__ darc, const uint32_t *__restrict__ lab,
-                                        const uint32_t (&beg)[PV], const uint32_t (&end)[PV], uint32_t (&dv)[PV],
-                                        uint32_t (&in)[PV], uint32_t (&flag)[PV], uint32_t tau, uint32_t j) {
-    uint2 a[PV][4];
-    uint32_t l[PV][4];
-#pragma unroll
-    for (uint32_t q = 0; q < PV; ++q)
-#pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) a[q][u] = darc[beg[q] + u < end[q] ? beg[q] + u : 0u];
-#pragma unroll
-    for (uint32_t q = 0; q < PV; ++q)
-#pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-            const uint32_t t = beg[q] + u < end[q] ? (a[q][u].x & TAIL_MASK) : 0u;
-            l[q][u] = lab[(uint64_t(t) << 6) + j];
-        }
-#pragma unroll
-    for (uint32_t q = 0; q < PV; ++q) {
-        in[q] = 0;
-        flag[q] = 0;
-#pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-            const bool ok = beg[q] + u < end[q];
-            dv[q] = min(dv[q], ok ? sat_add(l[q][u], a[q][u].y) : INF);
-            flag[q] |= uint32_t(ok && (a[q][u].x & FLAGS)) << u;
-            in[q] |= uint32_t(ok && l[q][u] <= tau) << u;
-        }
-    }
-#pragma unroll
-    for (uint32_t q = 0; q < PV; ++q)
-        for (uint32_t e = beg[q] + 4; e < end[q]; e += 4) {
-            uint2 b[4];
-            uint32_t t[4];
-#pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) b[u] = darc[e + u < end[q] ? e + u : e];
-#pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) t[u] = lab[(uint64_t(b[u].x & TAIL_MASK) << 6) + j];
-#pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) {
-                const bool ok = e + u < end[q];
-                dv[q] = min(dv[q], ok ? sat_add(t[u], b[u].y) : INF);
-                const uint32_t k = e - beg[q] + u;
-                if (k < 32) {
-                    flag[q] |= uint32_t(ok && (b[u].x & FLAGS)) << k;
-                    in[q] |= uint32_t(ok && t[u] <= tau) << k;
-                }
-            }
-        }
-}
-
-// The header of PV vertices (offsets, upward label): lanes fetch it for all PV vertices at
-// once (lane j reads the offset (j / PV) & 1 and the slot of vertex j mod PV), and the values
-// are read out of the lanes, so the header costs two memory round trips whatever PV is.
-// Vertex q is active iff act[q]; an inactive one gets no entries and label INF.
-__device__ __forceinline__ void header64(const CoreArgs &A, const uint32_t (&v)[PV], const bool (&act)[PV],
-                                         uint32_t (&beg)[PV], uint32_t (&end)[PV], uint32_t (&dv)[PV], uint32_t j) {
-    const uint32_t mq = j % PV;
-    uint32_t vq = v[0];
-#pragma unroll
-    for (uint32_t k = 1; k < PV; ++k) vq = mq == k ? v[k] : vq;
-    const uint32_t x = A.down_off[vq + ((j / PV) & 1u)];
-    const uint32_t y = A.uslot[vq];
-    uint32_t sl[PV];
-#pragma unroll
-    for (uint32_t q = 0; q < PV; ++q) {
-        beg[q] = uint32_t(__builtin_amdgcn_readlane(int(x), int(q)));
-        end[q] = uint32_t(__builtin_amdgcn_readlane(int(x), int(PV + q)));
-        sl[q] = uint32_t(__builtin_amdgcn_readlane(int(y), int(q)));
-    }
-#pragma unroll
-    for (uint32_t q = 0; q < PV; ++q) {
-        const bool up = act[q] && sl[q] != NO_SLOT;
-        const uint32_t u = A.uval[(uint64_t(up ? sl[q] : 0u) << 6) + j];   // row 0 always exists
-        dv[q] = up ? u : INF;
-        if (!act[q]) end[q] = beg[q];
-    }
-}
 
 // Straddling flagged entries of vertex v (label dv, final): the first 32 entries from their
 // recorded bits, a vertex with more walks them again.  Every lane of the wavefront calls it.
@@ -656,17 +569,22 @@ __global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, const uint2 *_
 // reads only the core and the cell's own higher levels, so the l-th levels of all cells form
 // one launch, and the internal vertices become a stream of about 20 launches of up to millions
 // of vertices each.  Labels are rows of 64 words in HBM (the core's rows, then the internal
-// positions'), as in k_core_level64: lane j = query j, entries read by scalar loads, one
-// coalesced 256-byte row per entry.  A wavefront takes PV consecutive vertices of the list at
-// a time and issues the loads of their first four entries together, so that each wavefront
-// keeps up to 4 * PV rows in flight (one vertex at a time left the stream bound by load
-// latency).  The grid is resident (a few blocks per compute unit): the blocks of XCD x (block
-// index mod 8) take the x-th eighth of the level's list and their wavefronts stride through
-// it, so that the vertices of one cell, consecutive in the list, meet in one XCD's L2.  A label
-// that no downward entry reads is not written back.
+// positions'), as in k_core_level64: lane j = query j, one coalesced 256-byte row per entry.
+// The launch's vertices come as records in list order (PLAIN_REC uint2 words each: the
+// position and its first entry, the entry end and whether an entry reads the label, then the
+// first PLAIN_REC - 2 entries): a wavefront takes PV consecutive records with one coalesced
+// load, issues the rows of their first four entries together, and reaches the rest of the
+// entries from the record or the downward CSR.  So a vertex costs two dependent memory round
+// trips (record, rows), with its upward slot fetched beside the rows.  The grid is resident (a
+// few blocks per compute unit): the blocks of XCD x (block index mod 8) take the x-th eighth of
+// the level's list and their wavefronts stride through it, so that the vertices of one cell,
+// consecutive in the list, meet in one XCD's L2.  A label that no downward entry reads is not
+// written back.
+constexpr uint32_t PLAIN_REC = 16;
+static_assert(PV * PLAIN_REC <= 64, "a wavefront loads its PV records in one instruction");
+
 __global__ void __launch_bounds__(256)
-k_plain_level64(CoreArgs A, const uint32_t *__restrict__ lpos, uint32_t lb, uint32_t le,
-                const uint32_t *__restrict__ readers) {
+k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_t le) {
     __shared__ uint64_t s_keys[CORE_KEYS];
     __shared__ uint32_t s_n, s_base;
     keys_begin(&s_n);
@@ -679,19 +597,81 @@ k_plain_level64(CoreArgs A, const uint32_t *__restrict__ lpos, uint32_t lb, uint
     const uint2 *__restrict__ darc = A.down_arc;
     uint32_t *__restrict__ lab = A.dcore;
     for (uint32_t i = s0 + w0 * PV; i < s1; i += nw * PV) {   // uniform over the wavefront
-        uint32_t v[PV], beg[PV], end[PV], dv[PV], in[PV], flag[PV];
-        bool act[PV];
-        const uint32_t mine = lpos[min(i + j % PV, s1 - 1u)];   // lane j: vertex j mod PV of the group
+        // lane j: word j mod PLAIN_REC of the record of list entry i + j / PLAIN_REC
+        const uint32_t me = min(i + j / PLAIN_REC, s1 - 1u);
+        const uint2 r = prec[uint64_t(me) * PLAIN_REC + (j % PLAIN_REC)];
+        uint32_t v[PV], beg[PV], end[PV], wr[PV], dv[PV], in[PV], flag[PV];
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q) {
-            act[q] = i + q < s1;
-            v[q] = uint32_t(__builtin_amdgcn_readlane(int(mine), int(q)));
+            const bool act = i + q < s1;
+            v[q] = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(q * PLAIN_REC)));
+            beg[q] = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC)));
+            end[q] = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(q * PLAIN_REC + 1)));
+            wr[q] = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC + 1)));
+            if (!act) end[q] = beg[q];
         }
-        header64(A, v, act, beg, end, dv, j);
-        relax64(darc, lab, beg, end, dv, in, flag, tau, j);
+        uint32_t sl[PV];
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q) sl[q] = A.uslot[v[q]];
+        // the first four entries of every vertex, from the records: all rows issued together
+        uint32_t l[PV][4], tw[PV][4];
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q)
-            if (i + q < s1 && ((readers[v[q] >> 5] >> (v[q] & 31u)) & 1u)) lab[(uint64_t(v[q]) << 6) + j] = dv[q];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t tx = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(q * PLAIN_REC + 2 + u)));
+                tw[q][u] = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC + 2 + u)));
+                l[q][u] = lab[(uint64_t(beg[q] + u < end[q] ? (tx & TAIL_MASK) : 0u) << 6) + j];
+                if (u == 0) flag[q] = 0;
+                flag[q] |= uint32_t(beg[q] + u < end[q] && (tx & FLAGS)) << u;
+            }
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q) {
+            const bool up = sl[q] != NO_SLOT;
+            const uint32_t uv = A.uval[(uint64_t(up ? sl[q] : 0u) << 6) + j];   // row 0 always exists
+            dv[q] = up ? uv : INF;
+            in[q] = 0;
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const bool ok = beg[q] + u < end[q];
+                dv[q] = min(dv[q], ok ? sat_add(l[q][u], tw[q][u]) : INF);
+                in[q] |= uint32_t(ok && l[q][u] <= tau) << u;
+            }
+        }
+        // further entries: from the record up to PLAIN_REC - 2, then from the downward CSR
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q) {
+            const uint32_t deg = end[q] - beg[q], nrec = min(deg, PLAIN_REC - 2);
+            for (uint32_t u = 4; u < nrec; ++u) {   // uniform loop
+                const uint32_t tx = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(q * PLAIN_REC + 2 + u)));
+                const uint32_t w = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC + 2 + u)));
+                const uint32_t t = lab[(uint64_t(tx & TAIL_MASK) << 6) + j];
+                dv[q] = min(dv[q], sat_add(t, w));
+                flag[q] |= uint32_t((tx & FLAGS) != 0) << u;
+                in[q] |= uint32_t(t <= tau) << u;
+            }
+            for (uint32_t e = beg[q] + PLAIN_REC - 2; e < end[q]; e += 4) {
+                uint2 bb[4];
+                uint32_t t[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) bb[u] = darc[e + u < end[q] ? e + u : e];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) t[u] = lab[(uint64_t(bb[u].x & TAIL_MASK) << 6) + j];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const bool ok = e + u < end[q];
+                    dv[q] = min(dv[q], ok ? sat_add(t[u], bb[u].y) : INF);
+                    const uint32_t k = e - beg[q] + u;
+                    if (k < 32) {
+                        flag[q] |= uint32_t(ok && (bb[u].x & FLAGS)) << k;
+                        in[q] |= uint32_t(ok && t[u] <= tau) << k;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < PV; ++q)
+            if (i + q < s1 && wr[q]) lab[(uint64_t(v[q]) << 6) + j] = dv[q];
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q)
             if (i + q < s1) plain_extract(A, darc, lab, beg[q], end[q], in[q], flag[q], dv[q], tau, j, s_keys, &s_n);
@@ -2078,8 +2058,17 @@ int DevGraph::upload(const iso::Prep &P, int device_) {
         plain_entries = P.down_off[n] - P.down_off[n_core];
         plain_written = 0;
         for (uint32_t v = n_core; v < n; ++v) plain_written += (readers[v >> 5] >> (v & 31)) & 1u;
-        if ((r = dev_alloc_copy(&d_plvl_pos, lpos, bytes))) return r;
-        if ((r = dev_alloc_copy(&d_readers, readers, bytes))) return r;
+        // the records of the stream, in list order
+        std::vector<uint2> prec(std::max<size_t>(1, lpos.size() * PLAIN_REC), make_uint2(0u, INF));
+        for (size_t i = 0; i < lpos.size(); ++i) {
+            const uint32_t v = lpos[i], b0 = P.down_off[v], b1 = P.down_off[v + 1];
+            uint2 *w = prec.data() + i * PLAIN_REC;
+            w[0] = make_uint2(v, b0);
+            w[1] = make_uint2(b1, (readers[v >> 5] >> (v & 31)) & 1u);
+            for (uint32_t u = 0; u + 2 < PLAIN_REC && b0 + u < b1; ++u)
+                w[u + 2] = make_uint2(P.down_arc[2 * (uint64_t(b0) + u)], P.down_arc[2 * (uint64_t(b0) + u) + 1]);
+        }
+        if ((r = dev_alloc_copy(&d_plvl_rec, prec, bytes))) return r;
     }
     {   // per core vertex its record: entry offsets, then its first CORE_REC - 1 entries
         std::vector<uint2> rec(std::max<size_t>(1, size_t(n_core) * CORE_REC), make_uint2(0u, INF));
@@ -2306,7 +2295,7 @@ void DevGraph::release() {
     void *ptrs[] = {d_down_off, d_down_arc, d_pos, d_core_cell, d_core_ecc, d_cell_off, d_uncovered,
                     d_cell_core_off, d_cell_core,
                     d_table, d_blob, d_cblob, d_cmeta, d_cell_ebase, d_arc_rank, d_arc_pair, d_blob2, d_cblob2,
-                    d_plvl_pos, d_readers, d_core_rec};
+                    d_plvl_rec, d_core_rec};
     for (void *p : ptrs) if (p) hipFree(p);
     (void)hipGetLastError();   // a failed free must not surface in another handle's next check
     device = -1;
@@ -2449,7 +2438,7 @@ static int ensure(bool fixed, void **p, size_t &have, size_t need) {
 size_t DevGraph::ctx_bytes(uint32_t k, size_t cap, size_t upward_entries, bool plain) const {
     uint32_t K = 1;
     while (K < k) K <<= 1;
-    const size_t rows = plain && K == 64 && d_plvl_pos ? n : n_core;   // the stream of levels keeps every row
+    const size_t rows = plain && K == 64 && d_plvl_rec ? n : n_core;   // the stream of levels keeps every row
     // temporary storage of the radix sort over cap keys (the size query allocates nothing)
     size_t sort_tmp = 0;
     if (hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
@@ -2493,7 +2482,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
     }
     // plain mode at 64 queries per sweep: the internal vertices as a stream of levels across all
     // cells, their label rows after the core's
-    const bool pstream = A.plain_stream && A.mode_plain && K == 64 && A.core64 && num_cells > 0 && d_plvl_pos &&
+    const bool pstream = A.plain_stream && A.mode_plain && K == 64 && A.core64 && num_cells > 0 && d_plvl_rec &&
                          !A.want_dist && !A.vbits && !A.vmask_only && !A.tg && !A.core_dijkstra && !B.fixed;
     size_t core_words = std::max<size_t>(1, size_t(pstream ? n : n_core) * K);
     if ((r = ensure(B.fixed, (void **)&B.d_dcore, B.sz_dcore, core_words * 4))) return r;
@@ -2781,8 +2770,7 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
             const uint32_t pgrid = (uint32_t(std::max(1, num_cus)) * plain_per_cu + 7u) & ~7u;
             for (size_t l = 0; l + 1 < plvl_ptr.size(); ++l)
                 if (plvl_ptr[l + 1] > plvl_ptr[l])
-                    k_plain_level64<<<dim3(pgrid), dim3(256), 0, s>>>(CA, d_plvl_pos, plvl_ptr[l], plvl_ptr[l + 1],
-                                                                     d_readers);
+                    k_plain_level64<<<dim3(pgrid), dim3(256), 0, s>>>(CA, d_plvl_rec, plvl_ptr[l], plvl_ptr[l + 1]);
         } else if (chunks) {
             Cell2Args LA{d_clist, B.d_counters, d_blob2, d_cblob2, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot,
                          B.d_uval, d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr,
