@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, const uint2 *_
         const uint32_t sl = A.uslot[v];
         const uint32_t beg = uint32_t(__builtin_amdgcn_readlane(int(r.x), 0));
         const uint32_t end = uint32_t(__builtin_amdgcn_readlane(int(r.y), 0));
-        uint32_t dv = sl != NO_SLOT ? A.uval[(sl << 6) + j] : INF;
+        uint32_t dv = INF;
         uint32_t in = 0, flag = 0;   // per entry k < 32: tail in range (this lane), entry flagged
         const uint2 *__restrict__ darc = A.down_arc;
         const uint32_t *__restrict__ dc = A.dcore;
@@ -505,6 +505,8 @@ __global__ void __launch_bounds__(256) k_core_level64(CoreArgs A, const uint2 *_
                 flag |= ((tx[u] & FLAGS) ? 1u : 0u) << u;
                 in |= uint32_t(l[u] <= tau) << u;
             }
+            // the upward label, for the few vertices with a slot: a load only there
+            if (sl != NO_SLOT) dv = min(dv, A.uval[(sl << 6) + j]);
             // the padding words' bits: cleared
             const uint32_t nrec = min(end - beg, CORE_REC - 1);
             const uint32_t keep = nrec >= 32 ? ~0u : ((1u << nrec) - 1u);
@@ -627,9 +629,7 @@ k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_
             }
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q) {
-            const bool up = sl[q] != NO_SLOT;
-            const uint32_t uv = A.uval[(uint64_t(up ? sl[q] : 0u) << 6) + j];   // row 0 always exists
-            dv[q] = up ? uv : INF;
+            dv[q] = INF;
             in[q] = 0;
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u) {
@@ -637,6 +637,8 @@ k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_
                 dv[q] = min(dv[q], ok ? sat_add(l[q][u], tw[q][u]) : INF);
                 in[q] |= uint32_t(ok && l[q][u] <= tau) << u;
             }
+            // the upward label, for the few vertices with a slot (the sources' cells): a load only there
+            if (sl[q] != NO_SLOT) dv[q] = min(dv[q], A.uval[(uint64_t(sl[q]) << 6) + j]);
         }
         // further entries: from the record up to PLAIN_REC - 2, then from the downward CSR
 #pragma unroll
