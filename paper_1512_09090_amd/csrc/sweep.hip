@@ -644,13 +644,23 @@ k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q) {
             const uint32_t deg = end[q] - beg[q], nrec = min(deg, PLAIN_REC - 2);
-            for (uint32_t u = 4; u < nrec; ++u) {   // uniform loop
-                const uint32_t tx = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(q * PLAIN_REC + 2 + u)));
-                const uint32_t w = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC + 2 + u)));
-                const uint32_t t = lab[(uint64_t(tx & TAIL_MASK) << 6) + j];
-                dv[q] = min(dv[q], sat_add(t, w));
-                flag[q] |= uint32_t((tx & FLAGS) != 0) << u;
-                in[q] |= uint32_t(t <= tau) << u;
+            for (uint32_t u0 = 4; u0 < nrec; u0 += 4) {   // uniform loop, four rows in flight
+                uint32_t tx[4], w[4], t[4];
+#pragma unroll
+                for (uint32_t k = 0; k < 4; ++k) {
+                    const uint32_t u = min(u0 + k, PLAIN_REC - 3);   // a word of the record
+                    tx[k] = uint32_t(__builtin_amdgcn_readlane(int(r.x), int(q * PLAIN_REC + 2 + u)));
+                    w[k] = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC + 2 + u)));
+                }
+#pragma unroll
+                for (uint32_t k = 0; k < 4; ++k) t[k] = lab[(uint64_t(tx[k] & TAIL_MASK) << 6) + j];
+#pragma unroll
+                for (uint32_t k = 0; k < 4; ++k) {
+                    const bool ok = u0 + k < nrec;
+                    dv[q] = min(dv[q], ok ? sat_add(t[k], w[k]) : INF);
+                    flag[q] |= uint32_t(ok && (tx[k] & FLAGS)) << (u0 + k);
+                    in[q] |= uint32_t(ok && t[k] <= tau) << (u0 + k);
+                }
             }
             for (uint32_t e = beg[q] + PLAIN_REC - 2; e < end[q]; e += 4) {
                 uint2 bb[4];
