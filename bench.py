@@ -277,6 +277,8 @@ def roofline_of(prof, prof_iso, steps, names=None):
     if iso_d:
         roof["isolated"] = dict(iso_d, note="same kernel, one sweep per call (host API run), no other sweep on "
                                             "the GPU")
+        iso_k = {k: entry(prof_iso, k) for k in KERNELS}
+        roof["isolated_kernels"] = {k: v for k, v in iso_k.items() if v}
     return roof
 
 

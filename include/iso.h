@@ -333,11 +333,12 @@ typedef struct {
                                    one wavefront per core vertex (its entries read once for the 64
                                    queries), else threads per (vertex, query, share of its entries);
                                    2 = the latter at every width.  Other values give ISO_EINVAL */
-    uint32_t cell_stage;        /* 2 = one workgroup per active cell: the cell's data is copied into LDS
-                                   once and swept for all the queries that activate the cell, up to 16 at
-                                   a time, each thread holding one vertex's labels for those queries
-                                   (needs the largest cell's data and one query's labels to fit 160 KiB,
-                                   else 0 is used); 0 = work items of a cell and up to G queries, a
+    uint32_t cell_stage;        /* 2 = one workgroup per active cell (default): the cell's data is copied
+                                   into LDS once and swept for all the queries that activate the cell, in
+                                   chunks of as many queries as cell_lds_kb holds label rows for (at most
+                                   64), each thread serving one (vertex, query) slot; the workgroups claim
+                                   the active cells one at a time (needs the largest cell's data and one
+                                   query's labels to fit 160 KiB, else 0 is used); 0 = work items of a cell and up to G queries, a
                                    workgroup holds two levels' entries in LDS and loads the next level
                                    while relaxing the current one; 1 = work items as in 0, the item's
                                    whole cell data copied into LDS first (needs the largest cell's data

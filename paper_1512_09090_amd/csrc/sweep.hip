@@ -816,12 +816,23 @@ __global__ void k_rphast_out(const uint32_t *__restrict__ lab, const uint32_t *_
     out[uint64_t(j) * count + i] = lab[(uint64_t(row[i]) << lk) + j];
 }
 
-// Active cells (nonzero lane mask) in a list, and work items: the lanes of a cell are cut into
-// items of at most G = 1 << lg lanes; item c << 6 | q covers the lanes of rank [qG, qG + G) in
-// the mask.  A cell's items are consecutive in the item list.
+// Sources of the cell sweep's per-cell header records (hdr == nullptr: work items instead).
+constexpr uint32_t CELL_HDR = 16;   // words per record: cell, (cnt, nl, nrefs, ne), lanes, cb, ebase, blob
+struct CellHdrSrc {
+    const uint4 *cmeta;
+    const uint32_t *cell_off, *cell_ebase, *cblob;
+    uint32_t *hdr;
+};
+
+// Active cells (nonzero lane mask) in a list, and either work items or header records.  Items:
+// the lanes of a cell are cut into items of at most G = 1 << lg lanes; item c << 6 | q covers
+// the lanes of rank [qG, qG + G) in the mask, a cell's items consecutive in the item list.
+// Header records (for the one-workgroup-per-cell sweep): the record at a cell's list position
+// holds what its workgroup needs before it reads the cell's blob.
+
 __global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_cells, uint32_t lg,
                                uint32_t *__restrict__ list, uint32_t *__restrict__ items,
-                               uint32_t *__restrict__ counters) {
+                               uint32_t *__restrict__ counters, CellHdrSrc H) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t m = c < num_cells ? cmask[c] : 0ull;
     const bool act = m != 0;
@@ -849,7 +860,22 @@ __global__ void k_active_cells(const uint64_t *__restrict__ cmask, uint32_t num_
     }
     lbase = __shfl(lbase, 0);
     ibase = __shfl(ibase, 0);
-    if (act) {
+    if (act && H.hdr) {   // the cell sweep's header records instead of work items
+        const uint32_t pos = lbase + (uint32_t)__popcll(amask & ((1ull << lane) - 1ull));
+        list[pos] = c;
+        const uint4 meta = H.cmeta[c];
+        uint32_t *h = H.hdr + size_t(pos) * CELL_HDR;
+        h[0] = c;
+        h[1] = meta.x;
+        h[2] = meta.y;
+        h[3] = meta.z;
+        h[4] = meta.w;
+        h[5] = uint32_t(m);
+        h[6] = uint32_t(m >> 32);
+        h[7] = H.cell_off[c];
+        h[8] = H.cell_ebase[c];
+        h[9] = H.cblob[c];
+    } else if (act) {
         list[lbase + (uint32_t)__popcll(amask & ((1ull << lane) - 1ull))] = c;
         const uint32_t first = ibase + incl - nch;
         for (uint32_t q = 0; q < full; ++q) items[first + q] = (c << 8) | q;
@@ -1466,15 +1492,13 @@ k_cell_sweep(CellArgs A) {
 //   length or a row index does not fit the packed word.
 // stored = lvl[nl - 1]: the rows of every level but the last.
 
-constexpr uint32_t C2_CAND = 1024;   // candidate words in LDS
-constexpr uint32_t C2_CTL = 4;       // control words: candidate count, output base
+constexpr uint32_t C2_CAND = 1024;   // candidate words in LDS: C2_CAND / 2 output keys
+constexpr uint32_t C2_CTL = 4;       // control words: candidate count, output base, two claims
 constexpr uint32_t C2_THREADS = 512;
 
 struct Cell2Args {
-    const uint32_t *clist, *counters, *blob, *cblob, *cell_off, *cell_ebase, *dcore, *uslot, *uval, *taus,
-        *src_cell;
-    const uint64_t *cmask;
-    const uint4 *cmeta;   // (cnt, nl, nrefs, ne)
+    const uint32_t *hdr, *counters, *blob, *dcore, *uslot, *uval, *taus, *src_cell;   // hdr: CELL_HDR words per cell
+    uint32_t *claim;   // per-XCD claim counters (8 words, zero at launch)
     uint32_t *dist_out;
     uint64_t *vmask;
     uint64_t *out_keys;
@@ -1490,9 +1514,9 @@ __host__ __device__ __forceinline__ uint32_t c2_words(uint32_t cnt, uint32_t nl,
                                                       bool packed) {
     return (c2_head_words(cnt, nl, nrefs) + (packed ? ne : 2 * ne) + 3u) & ~3u;
 }
-// LDS words of a cell workgroup: the largest blob, label rows of W lanes, candidates, control.
+// LDS words of a cell workgroup: control, candidates, the largest blob, label rows of W lanes.
 __host__ __device__ __forceinline__ uint32_t c2_lds_words(uint32_t blob_words, uint32_t rows, uint32_t w) {
-    return ((blob_words + 3u) & ~3u) + ((rows * w + 3u) & ~3u) + C2_CAND + C2_CTL;
+    return ((blob_words + 3u) & ~3u) + ((rows * (w | 1u) + 3u) & ~3u) + C2_CAND + C2_CTL;
 }
 
 
@@ -1521,33 +1545,29 @@ __device__ __forceinline__ C2Ent c2_entry(const uint32_t *s_ent, uint32_t e, uin
     return r;
 }
 
-// Appends a candidate (the cell-local entry e, the lane's rank among the cell's active lanes,
-// the direction) to the LDS list, or writes it out at once when the list is full.
-__device__ __forceinline__ void c2_push(const Cell2Args &A, uint32_t *s_cand, uint32_t *s_ctl, uint32_t e,
-                                        uint32_t rank, uint32_t rev, uint32_t lane, uint32_t ebase) {
+// Appends a candidate's output key (lane, entry, direction) to the workgroup's LDS list, which
+// outlives a cell, or writes it out at once when the list is full.
+__device__ __forceinline__ void c2_push(const Cell2Args &A, uint64_t *s_cand, uint32_t *s_ctl, uint32_t lane,
+                                        uint32_t entry, uint32_t rev) {
     const uint32_t k = atomicAdd(&s_ctl[0], 1u);
-    if (k < C2_CAND) {
-        s_cand[k] = e | (rank << 25) | (rev << 31);
+    if (k < C2_CAND / 2) {
+        s_cand[k] = entry_key(lane, entry, rev);
     } else {
         if (A.dbg) atomicAdd(&A.dbg[0], 1ull);
         const uint32_t idx = atomicAdd(A.out_count, 1u);
-        if (idx < A.out_cap) A.out_keys[idx] = entry_key(lane, ebase + e, rev);
+        if (idx < A.out_cap) A.out_keys[idx] = entry_key(lane, entry, rev);
     }
 }
 
-// Writes the listed candidates with one output reservation and empties the list.  Every thread
-// calls it with the same n (read between two barriers); it ends with a barrier.
-__device__ __forceinline__ void c2_flush(const Cell2Args &A, uint32_t n, uint32_t *s_cand, uint32_t *s_ctl,
-                                         uint64_t lanes, uint32_t ebase) {
+// Writes the listed keys with one output reservation and empties the list.  Every thread calls
+// it with the same n (read between two barriers); it ends with a barrier.
+__device__ __forceinline__ void c2_flush(const Cell2Args &A, uint32_t n, const uint64_t *s_cand, uint32_t *s_ctl) {
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_ctl[1] = atomicAdd(A.out_count, n);
     __syncthreads();
     const uint32_t base = s_ctl[1];
-    for (uint32_t k = tid; k < n; k += blockDim.x) {
-        const uint32_t w = s_cand[k];
-        const uint32_t lane = A.lane_base + nth_set_bit(lanes, (w >> 25) & 63u);
-        if (base + k < A.out_cap) A.out_keys[base + k] = entry_key(lane, ebase + (w & 0x1FFFFFFu), w >> 31);
-    }
+    for (uint32_t k = tid; k < n; k += blockDim.x)
+        if (base + k < A.out_cap) A.out_keys[base + k] = s_cand[k];
     __syncthreads();
     if (tid == 0) s_ctl[0] = 0;
     __syncthreads();
@@ -1561,8 +1581,8 @@ template <bool PACKED>
 __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t i, uint32_t j, uint32_t W, uint32_t lw,
                                           const uint32_t *s_off, const uint32_t *s_ent, uint32_t *s_lab,
                                           uint32_t stored, uint32_t tau, bool live, bool up, uint32_t lane,
-                                          uint32_t cb, uint32_t rank, uint32_t *s_cand, uint32_t *s_ctl,
-                                          uint32_t ebase, uint32_t lb) {
+                                          uint32_t cb, uint64_t *s_cand, uint32_t *s_ctl, uint32_t ebase,
+                                          uint32_t lb) {
     uint32_t dv = INF, e0 = 0, e1 = 0;
     if (act) {
         if (up) {   // a source in the cell: its upward label (host search) starts the label
@@ -1587,7 +1607,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
             fl[k] = valid && (x.fwd || x.rev);
         }
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k) t[k] = s_lab[(row[k] << lw) + j];
+        for (uint32_t k = 0; k < 4; ++k) t[k] = s_lab[row[k] * (W | 1u) + j];
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
             dv = min(dv, sat_add(t[k], w[k]));
@@ -1597,7 +1617,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
     }
     const bool vin = dv <= tau;
     if (act) {
-        if (i < stored) s_lab[(i << lw) + j] = dv;
+        if (i < stored) s_lab[i * (W | 1u) + j] = dv;
         if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << A.lk) + lane] = dv;
     }
     if (A.vmask) {   // lanes in range, ORed over the vertex's W slots (consecutive threads)
@@ -1610,50 +1630,79 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
     if (!(act && live && (vin ? fout : fin))) return;
     for (uint32_t e = e0; e < e1; ++e) {
         const C2Ent x = c2_entry<PACKED>(s_ent, e, lb);
-        if (!(x.fwd || x.rev) || ((s_lab[(x.row << lw) + j] <= tau) == vin)) continue;
-        if (x.fwd) c2_push(A, s_cand, s_ctl, e, rank, 0u, A.lane_base + lane, ebase);
-        if (x.rev) c2_push(A, s_cand, s_ctl, e, rank, 1u, A.lane_base + lane, ebase);
+        if (!(x.fwd || x.rev) || ((s_lab[x.row * (W | 1u) + j] <= tau) == vin)) continue;
+        if (x.fwd) c2_push(A, s_cand, s_ctl, A.lane_base + lane, ebase + e, 0u);
+        if (x.rev) c2_push(A, s_cand, s_ctl, A.lane_base + lane, ebase + e, 1u);
     }
 }
 
-// Sweep of one lane chunk: ranks [q0, q0 + W) of the cell's active lanes (W a power of two).
-// Thread t serves lane slot t mod W of vertex slot t / W.  The leading levels that fit
-// wavefront 0 (64 / W vertices) are swept by it alone, with wavefront-scope fences between
-// them; the other wavefronts join at the first wider level.
-template <bool PACKED>
-__device__ __forceinline__ void c2_chunk(const Cell2Args &A, uint32_t *smem, uint32_t c, uint32_t q0, uint32_t W,
-                                         uint64_t lanes, uint32_t L, uint32_t cnt, uint32_t nl, uint32_t nrefs,
-                                         uint32_t words, uint32_t stored, uint32_t cb, uint32_t ebase) {
-    const uint32_t tid = threadIdx.x, T = blockDim.x;
-    const uint32_t lw = __builtin_ctz(W);
-    const uint32_t *s_off = smem, *s_lvl = smem + cnt + 1, *s_refs = s_lvl + nl + 1;
-    const uint32_t *s_ent = smem + c2_head_words(cnt, nl, nrefs);
-    uint32_t *s_lab = smem + ((words + 3u) & ~3u);
-    uint32_t *s_cand = s_lab + ((size_t(stored + nrefs) * (1u << A.lgmax) + 3u) & ~3u);
-    uint32_t *s_ctl = s_cand + C2_CAND;
-    const uint32_t j = tid & (W - 1);
-    const uint32_t rank = q0 + j;
-    const bool live = rank < L;
-    const uint32_t lane = nth_set_bit(lanes, live ? rank : q0);
-    const uint32_t tau = A.taus[lane];
-    const bool up = live && A.src_cell[lane] == c;
-    // the referenced core vertices' final labels, one (ref, slot) pair per thread
-    for (uint32_t r = tid >> lw; r < nrefs; r += T >> lw)
-        s_lab[((stored + r) << lw) + j] = A.dcore[(s_refs[r] << A.lk) + lane];
+// A lane chunk of a staged cell: ranks [q0, q0 + W) of the cell's active lanes (W a power of
+// two).  Thread t serves lane slot j = t mod W of vertex slot t / W; live (a real lane), lane
+// (the batch lane), tau, up (its source lies in the cell: the upward labels start the vertex's
+// label).  The label rows follow the blob, W + 1 words apart (W > 1) so that the vertex slots'
+// reads spread over the LDS banks.
+struct C2Lane {
+    uint32_t W, lw, j, lane, tau;
+    bool live, up;
+};
+
+__device__ __forceinline__ C2Lane c2_lane(const Cell2Args &A, uint32_t c, uint64_t lanes, uint32_t L, uint32_t q0,
+                                          uint32_t W) {
+    C2Lane r;
+    r.W = W;
+    r.lw = __builtin_ctz(W);
+    r.j = threadIdx.x & (W - 1);
+    const uint32_t rank = q0 + r.j;
+    r.live = rank < L;
+    r.lane = nth_set_bit(lanes, r.live ? rank : q0);
+    r.tau = A.taus[r.lane];
+    r.up = r.live && A.src_cell[r.lane] == c;
+    return r;
+}
+
+// The referenced core vertices' final labels of the chunk's lanes into their LDS rows, one
+// (ref, slot) pair per thread, four rows of a thread in flight before their stores; ends with a
+// barrier.
+__device__ __forceinline__ void c2_rows(const Cell2Args &A, const C2Lane &q, const uint32_t *s_refs, uint32_t nrefs,
+                                        uint32_t *s_lab, uint32_t stored) {
+    const uint32_t step = blockDim.x >> q.lw, S = q.W | 1u;
+    for (uint32_t r = threadIdx.x >> q.lw; r < nrefs; r += 4 * step) {
+        uint32_t v[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+            const uint32_t x = r + k * step;
+            v[k] = x < nrefs ? A.dcore[(s_refs[x] << A.lk) + q.lane] : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+            if (r + k * step < nrefs) s_lab[(stored + r + k * step) * S + q.j] = v[k];
+    }
     __syncthreads();
-    const uint32_t wslots = 64u >> lw;   // vertex slots of one wavefront
+}
+
+// The chunk's levels.  The leading levels that fit wavefront 0 (64 / W vertices) are swept by
+// it alone, with wavefront-scope fences between them; the other wavefronts join at the first
+// wider level.
+template <bool PACKED>
+__device__ __forceinline__ void c2_levels(const Cell2Args &A, const C2Lane &q, uint32_t *s_ctl, uint64_t *s_cand,
+                                          const uint32_t *blob, uint32_t *s_lab, uint32_t cnt, uint32_t nl,
+                                          uint32_t nrefs, uint32_t stored, uint32_t cb, uint32_t ebase) {
+    const uint32_t tid = threadIdx.x, T = blockDim.x;
+    const uint32_t *s_off = blob, *s_lvl = blob + cnt + 1;
+    const uint32_t *s_ent = blob + c2_head_words(cnt, nl, nrefs);
+    const uint32_t wslots = 64u >> q.lw;   // vertex slots of one wavefront
     uint32_t l0 = 0;
     while (l0 < nl && s_lvl[l0 + 1] - s_lvl[l0] <= wslots) ++l0;
-    const uint32_t per = T >> lw, wfirst = (tid & ~63u) >> lw;
+    const uint32_t per = T >> q.lw, wfirst = (tid & ~63u) >> q.lw;
     for (uint32_t l = tid < 64 ? 0u : l0; l < nl; ++l) {
         if (l == l0) __syncthreads();   // wavefront 0 done with the leading levels, the others waiting
         const uint32_t a = s_lvl[l], b = s_lvl[l + 1];
         if (A.dbg && tid == 0 && b - a > per) atomicAdd(&A.dbg[1], 1ull);
         for (uint32_t base = a; base < b; base += per) {
             if (base + wfirst >= b) break;   // whole wavefronts past the level's end
-            const uint32_t i = base + (tid >> lw);
-            c2_vertex<PACKED>(A, i < b, i, j, W, lw, s_off, s_ent, s_lab, stored, tau, live, up, lane, cb, rank, s_cand,
-                              s_ctl, ebase, A.lb);
+            const uint32_t i = base + (tid >> q.lw);
+            c2_vertex<PACKED>(A, i < b, i, q.j, q.W, q.lw, s_off, s_ent, s_lab, stored, q.tau, q.live, q.up, q.lane,
+                              cb, s_cand, s_ctl, ebase, A.lb);
         }
         if (l < l0) {
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1665,62 +1714,171 @@ __device__ __forceinline__ void c2_chunk(const Cell2Args &A, uint32_t *smem, uin
     if (l0 == nl) __syncthreads();
 }
 
+constexpr uint32_t C2_NONE = 0xFFFFFFFFu;   // no header record
+
+// A cell's header, wavefront-uniform: the cell, its sizes (cnt, nl, nrefs, ne), active lanes,
+// first vertex position, first entry index and blob offset.
+struct C2Cell {
+    uint32_t c, cnt, nl, nrefs, ne, cb, ebase, cblob;
+    uint64_t lanes;
+};
+
+// The header record at list position p (none for C2_NONE), lane l < 10 of each wavefront
+// holding its word l: a vector load, so that the barriers between its issue and its use (which
+// wait for LDS and scalar loads) do not wait for it.
+__device__ __forceinline__ uint32_t c2_head(const Cell2Args &A, uint32_t p) {
+    const uint32_t l = threadIdx.x & 63u;
+    return p != C2_NONE && l < 10u ? A.hdr[size_t(p) * CELL_HDR + l] : 0u;
+}
+
+__device__ __forceinline__ C2Cell c2_unpack(uint32_t h) {
+    C2Cell r;
+    r.c = __builtin_amdgcn_readlane(h, 0);
+    r.cnt = __builtin_amdgcn_readlane(h, 1);
+    r.nl = __builtin_amdgcn_readlane(h, 2);
+    r.nrefs = __builtin_amdgcn_readlane(h, 3);
+    r.ne = __builtin_amdgcn_readlane(h, 4);
+    r.lanes = uint64_t(uint32_t(__builtin_amdgcn_readlane(h, 5))) |
+              (uint64_t(uint32_t(__builtin_amdgcn_readlane(h, 6))) << 32);
+    r.cb = __builtin_amdgcn_readlane(h, 7);
+    r.ebase = __builtin_amdgcn_readlane(h, 8);
+    r.cblob = __builtin_amdgcn_readlane(h, 9);
+    return r;
+}
+
+// The first four rounds of a cell's blob (a round: one 16-byte word per thread), loaded ahead.
+struct C2Pf {
+    uint4 a, b, c, d;
+};
+
+// Issues the loads of the first four rounds of a cell's blob; an index past the blob reads its
+// last word, so every load stays inside it.
 template <bool PACKED>
-__device__ __forceinline__ void c2_cell(const Cell2Args &A, uint32_t *smem, uint32_t c) {
+__device__ __forceinline__ C2Pf c2_fetch(const Cell2Args &A, const C2Cell &h) {
+    const uint4 *g4 = reinterpret_cast<const uint4 *>(A.blob + h.cblob);
+    const uint32_t last = (c2_words(h.cnt, h.nl, h.nrefs, h.ne, PACKED) >> 2) - 1u;   // n4 >= 1
+    const uint32_t t = threadIdx.x, T = blockDim.x;
+    C2Pf v;
+    v.a = g4[min(t, last)];
+    v.b = g4[min(t + T, last)];
+    v.c = g4[min(t + 2 * T, last)];
+    v.d = g4[min(t + 3 * T, last)];
+    return v;
+}
+
+// Stores the fetched rounds of the cell's blob into LDS and copies the rest (blobs of more than
+// four rounds) directly, every load of a round before its stores.
+template <bool PACKED>
+__device__ __forceinline__ void c2_stage(const Cell2Args &A, const C2Cell &h, const C2Pf &v, uint32_t *smem) {
     const uint32_t tid = threadIdx.x, T = blockDim.x;
-    const uint4 meta = A.cmeta[c];
-    const uint32_t cnt = meta.x, nl = meta.y, nrefs = meta.z, ne = meta.w;
-    const uint64_t lanes = A.cmask[c];
-    const uint32_t L = uint32_t(__popcll(lanes));
-    const uint32_t words = c2_words(cnt, nl, nrefs, ne, PACKED);
-    const uint32_t cb = A.cell_off[c], ebase = A.cell_ebase[c];
-    // copy the cell's data into LDS: every 16-byte load of a round is issued before its stores
-    {
-        const uint4 *g4 = reinterpret_cast<const uint4 *>(A.blob + A.cblob[c]);
-        uint4 *s4 = reinterpret_cast<uint4 *>(smem);
-        const uint32_t n4 = words >> 2, last = n4 - 1;   // a blob holds its offsets: n4 >= 1
-        for (uint32_t i = tid; i < n4; i += 4 * T) {
-            const uint4 v0 = g4[i], v1 = g4[min(i + T, last)], v2 = g4[min(i + 2 * T, last)];
-            const uint4 v3 = g4[min(i + 3 * T, last)];
-            s4[i] = v0;
-            if (i + T < n4) s4[i + T] = v1;
-            if (i + 2 * T < n4) s4[i + 2 * T] = v2;
-            if (i + 3 * T < n4) s4[i + 3 * T] = v3;
-        }
-    }
-    __syncthreads();
-    const uint32_t stored = nl ? smem[cnt + 1 + nl - 1] : 0u;
-    uint32_t *s_lab = smem + ((words + 3u) & ~3u);
-    uint32_t *s_cand = s_lab + ((size_t(stored + nrefs) * (1u << A.lgmax) + 3u) & ~3u);
-    uint32_t *ctl = s_cand + C2_CAND;
-    if (tid == 0) ctl[0] = 0;
-    // lane chunks of up to 2^lgmax lanes; the last one as narrow as its lanes allow
-    const uint32_t G = 1u << A.lgmax;
-    for (uint32_t q0 = 0; q0 < L; q0 += G) {
-        const uint32_t rest = min(G, L - q0);
-        uint32_t W = 1;
-        while (W < rest) W <<= 1;   // the narrowest power of two that holds the chunk's lanes
-        c2_chunk<PACKED>(A, smem, c, q0, W, lanes, L, cnt, nl, nrefs, words, stored, cb, ebase);
-        // every thread passed the chunk's last barrier: the count is stable
-        const uint32_t n = ctl[0];
-        if (n > C2_CAND / 2 || (q0 + G >= L && n > 0)) c2_flush(A, min(n, C2_CAND), s_cand, ctl, lanes, ebase);
+    const uint32_t n4 = c2_words(h.cnt, h.nl, h.nrefs, h.ne, PACKED) >> 2, last = n4 - 1;
+    uint4 *s4 = reinterpret_cast<uint4 *>(smem);
+    if (tid < n4) s4[tid] = v.a;
+    if (tid + T < n4) s4[tid + T] = v.b;
+    if (tid + 2 * T < n4) s4[tid + 2 * T] = v.c;
+    if (tid + 3 * T < n4) s4[tid + 3 * T] = v.d;
+    const uint4 *g4 = reinterpret_cast<const uint4 *>(A.blob + h.cblob);
+    for (uint32_t i = tid + 4 * T; i < n4; i += 4 * T) {
+        const uint4 v0 = g4[i], v1 = g4[min(i + T, last)], v2 = g4[min(i + 2 * T, last)];
+        const uint4 v3 = g4[min(i + 3 * T, last)];
+        s4[i] = v0;
+        if (i + T < n4) s4[i + T] = v1;
+        if (i + 2 * T < n4) s4[i + 2 * T] = v2;
+        if (i + 3 * T < n4) s4[i + 3 * T] = v3;
     }
 }
 
-// The cell sweep over the active cells: XCD x (block index mod 8) takes the x-th eighth of the
-// active-cell list (neighbouring cells share core rows in that XCD's L2) and its workgroups
-// stride through it.  No workgroup waits for another.
+// The list position of claim k on the counter of XCD range (x + xs) mod 8; while that range is
+// used up, the workgroup moves on to the next XCD's range (xs + 1) with a claim there.  Returns
+// C2_NONE once all eight ranges are used up.  Every thread calls it with the same arguments.
+__device__ __forceinline__ uint32_t c2_next(const Cell2Args &A, uint32_t *s_ctl, uint32_t x, uint32_t &xs,
+                                            uint32_t rows, uint32_t total, uint32_t k) {
+    for (;;) {
+        const uint32_t lo = ((x + xs) & 7u) * rows, end = min(total, lo + rows);
+        if (k < rows && lo + k < end) return lo + k;
+        if (++xs == 8u) return C2_NONE;
+        __syncthreads();   // every thread has read the previous claim
+        if (threadIdx.x == 0) s_ctl[3] = atomicAdd(A.claim + ((x + xs) & 7u), 1u);
+        __syncthreads();
+        k = s_ctl[3];
+    }
+}
+
+// The cell sweep over the active cells.  The active-cell list is cut into eight ranges, one per
+// XCD (neighbouring cells share core rows in that XCD's L2).  The workgroups of XCD x (block
+// index mod 8) claim cells one at a time from range x's counter, so that a workgroup given heavy
+// cells takes fewer, then from the other XCDs' ranges in turn once range x is used up.  A
+// workgroup works ahead: while it sweeps a cell, the header record of the next one is read with
+// the first chunk's core rows, then that cell's blob is in flight to registers and the claim
+// after it to thread 0.  A cell's lanes are swept in chunks of up to 2^lgmax lanes, the last one
+// as narrow as its lanes allow.  No workgroup waits for another.
 template <bool PACKED>
 __global__ void __launch_bounds__(C2_THREADS) k_cell_chunks(Cell2Args A) {
     extern __shared__ uint32_t smem[];
+    // LDS: control words (candidate count, output base, two claim words), the candidate keys,
+    // then the current cell's blob and label rows
+    uint32_t *s_ctl = smem;
+    uint64_t *s_cand = reinterpret_cast<uint64_t *>(smem + C2_CTL);
+    uint32_t *s_cell = smem + C2_CTL + C2_CAND;
+    const uint32_t tid = threadIdx.x;
     const uint32_t total = A.counters[1];
+    if (total == 0) return;
     const uint32_t rows = (total + 7u) >> 3;
-    const uint32_t x = blockIdx.x & 7u, stride = gridDim.x >> 3;
-    const uint32_t end = min(total, (x + 1u) * rows);
-    for (uint32_t it = x * rows + (blockIdx.x >> 3); it < end; it += stride) {
-        c2_cell<PACKED>(A, smem, A.clist[it]);
-        __syncthreads();   // the next cell overwrites the LDS
+    const uint32_t x = blockIdx.x & 7u;
+    uint32_t xs = 0;   // claims come from range (x + xs) mod 8
+    if (tid == 0) {
+        s_ctl[0] = 0;
+        s_ctl[2] = atomicAdd(A.claim + x, 1u);
     }
+    __syncthreads();
+    const uint32_t p0 = c2_next(A, s_ctl, x, xs, rows, total, s_ctl[2]);
+    if (p0 != C2_NONE) {
+        C2Cell h = c2_unpack(c2_head(A, p0));
+        C2Pf v = c2_fetch<PACKED>(A, h);
+        __syncthreads();   // every thread has read the first claim
+        if (tid == 0) s_ctl[2] = atomicAdd(A.claim + ((x + xs) & 7u), 1u);
+        __syncthreads();
+        uint32_t pn = c2_next(A, s_ctl, x, xs, rows, total, s_ctl[2]);   // the next cell's position
+        uint32_t hn = c2_head(A, pn);
+        const uint32_t G = 1u << A.lgmax;
+        for (;;) {
+            c2_stage<PACKED>(A, h, v, s_cell);
+            const bool more = pn != C2_NONE;
+            C2Cell nxt = h;
+            uint32_t q = 0;   // thread 0: the claim after the next cell
+            __syncthreads();
+            const uint32_t L = uint32_t(__popcll(h.lanes));
+            const uint32_t words = c2_words(h.cnt, h.nl, h.nrefs, h.ne, PACKED);
+            const uint32_t stored = h.nl ? s_cell[h.cnt + 1 + h.nl - 1] : 0u;
+            const uint32_t *s_refs = s_cell + h.cnt + 1 + h.nl + 1;
+            uint32_t *s_lab = s_cell + ((words + 3u) & ~3u);
+            for (uint32_t q0 = 0; q0 < L; q0 += G) {
+                const uint32_t rest = min(G, L - q0);
+                uint32_t W = 1;
+                while (W < rest) W <<= 1;   // the narrowest power of two that holds the chunk's lanes
+                const C2Lane ql = c2_lane(A, h.c, h.lanes, L, q0, W);
+                c2_rows(A, ql, s_refs, h.nrefs, s_lab, stored);
+                if (q0 == 0 && more) {   // the rows were waited for, and with them the header record
+                    nxt = c2_unpack(hn);
+                    v = c2_fetch<PACKED>(A, nxt);
+                    if (tid == 0) q = atomicAdd(A.claim + ((x + xs) & 7u), 1u);
+                }
+                c2_levels<PACKED>(A, ql, s_ctl, s_cand, s_cell, s_lab, h.cnt, h.nl, h.nrefs, stored, h.cb, h.ebase);
+                // every thread passed the chunk's last barrier: the count is stable.  The list is
+                // written out once half full, else after the workgroup's last cell.
+                const uint32_t n = s_ctl[0];
+                if (n > C2_CAND / 4) c2_flush(A, min(n, C2_CAND / 2), s_cand, s_ctl);
+            }
+            if (tid == 0) s_ctl[2] = q;
+            __syncthreads();   // the claim is visible; the next cell overwrites the LDS
+            if (!more) break;
+            h = nxt;
+            pn = c2_next(A, s_ctl, x, xs, rows, total, s_ctl[2]);
+            hn = c2_head(A, pn);
+        }
+    }
+    const uint32_t n = s_ctl[0];
+    if (n) c2_flush(A, min(n, C2_CAND / 2), s_cand, s_ctl);
 }
 
 // Entry keys -> output keys: lane << rb | the rank of the entry's forward or reverse arc.
@@ -2615,8 +2773,9 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
         return 0;
     }
     uint64_t *vin = reinterpret_cast<uint64_t *>(B.d_flags), *vout = vin + n_core;
-    // counters: edges emitted, active cells, work items; the list buffer holds the cells' lane
-    // masks, the active cells and the work items
+    // counters: edges emitted, active cells, work items, then (words 8-15) the cell sweep's
+    // per-XCD claims; the list buffer holds the cells' lane masks, the active cells and the work
+    // items or the cells' header records
     uint32_t *out_count = B.d_counters, *n_items = B.d_counters + 2;
     uint64_t *d_cmask = reinterpret_cast<uint64_t *>(B.d_list);
     uint32_t *d_clist = B.d_list + 2 * size_t(num_cells), *d_items = d_clist + num_cells;
@@ -2765,8 +2924,10 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                                                                       d_uncovered, d_cell_off, d_src, K, num_cells,
                                                                       A.mode_plain ? 1u : 0u, d_cmask,
                                                                       vmode ? B.d_cin : nullptr);
+        // the one-workgroup-per-cell sweep reads header records where the per-item kernels read items
+        const CellHdrSrc hsrc{d_cmeta, d_cell_off, d_cell_ebase, d_cblob2, chunks ? d_items : nullptr};
         k_active_cells<<<dim3((num_cells + 255) / 256), dim3(256), 0, s>>>(d_cmask, num_cells, cell_lg, d_clist,
-                                                                          d_items, B.d_counters);
+                                                                          d_items, B.d_counters, hsrc);
         if (vmode)   // internal positions: the cells left out because they lie wholly in range
             k_vmask_cells<<<dim3((num_cells + 3) / 4), dim3(256), 0, s>>>(B.d_cin, d_cmask, d_cell_off, num_cells,
                                                                            B.d_vmask);
@@ -2784,10 +2945,9 @@ int DevGraph::launch(SweepCtx &C, const RunArgs &A) {
                 if (plvl_ptr[l + 1] > plvl_ptr[l])
                     k_plain_level64<<<dim3(pgrid), dim3(256), 0, s>>>(CA, d_plvl_rec, plvl_ptr[l], plvl_ptr[l + 1]);
         } else if (chunks) {
-            Cell2Args LA{d_clist, B.d_counters, d_blob2, d_cblob2, d_cell_off, d_cell_ebase, B.d_dcore, B.d_uslot,
-                         B.d_uval, d_taus, d_src, d_cmask, d_cmeta, A.want_dist ? B.d_dist : nullptr,
-                         vmode ? B.d_vmask : nullptr, B.d_keys, out_count, uint32_t(cap), A.lane_base, lk, lg,
-                         lb2, dbg};
+            Cell2Args LA{d_items, B.d_counters, d_blob2, B.d_dcore, B.d_uslot, B.d_uval, d_taus, d_src,
+                         B.d_counters + 8, A.want_dist ? B.d_dist : nullptr, vmode ? B.d_vmask : nullptr, B.d_keys,
+                         out_count, uint32_t(cap), A.lane_base, lk, lg, lb2, dbg};
             if (packed2)
                 k_cell_chunks<true><<<dim3(cell_grid), dim3(C2_THREADS), lds, s>>>(LA);
             else

@@ -54,7 +54,7 @@ def check_all(G, orc, src, tau, modes):
 
 def test_cell_level_wider_than_workgroup_and_full_edge_list():
     """1200 leaves on the one level of a cell (more than a cell workgroup's 512 threads), all
-    straddling the limit (2400 isochrone edges in one cell, more than the 1024-word list)."""
+    straddling the limit (2400 isochrone edges in one cell, more than the 512-key list)."""
     n, t, h, w, cells = star_cell_graph()
     G = iso.Graph(n, t, h, w, cell_of=cells, num_cells=2, device=0)
     orc = Oracle(n, t, h, w)
