@@ -362,7 +362,7 @@ typedef struct {
                                    buffer (for the serving loop, within its device budget), so this only
                                    moves memory against repeated sweeps; the answer is the same */
     uint32_t overlap_cells;     /* resident cell workgroups per compute unit while two sweeps of one call
-                                   overlap on two streams (0 = 2; at most what fits, at most 16) */
+                                   overlap on two streams (0 = 3; at most what fits, at most 16) */
     uint32_t plain_sweep;       /* ISO_MODE_PLAIN with 64 queries per sweep: 0 = the cells' internal vertices
                                    as one launch per level counted from the top of each cell, across all
                                    cells, one wavefront per vertex and the 64 queries' labels in device

@@ -22,7 +22,7 @@ from .binding import MODE_CELLS, Graph
 
 SPACE = {
     "cell_stage": [2, 0, 1],
-    "overlap_cells": [0, 1, 3],
+    "overlap_cells": [0, 1, 2],
     "lanes_per_launch": [16, 32, 64],
     "block": [128, 256, 512],
     "cell_lds_kb": [40, 64, 96],

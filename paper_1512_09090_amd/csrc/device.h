@@ -29,7 +29,7 @@ constexpr size_t FIXED_STAGE_BYTES = size_t(4) << 20;
 struct TargetSet;
 
 // Resident cell workgroups per CU for sweeps that overlap on two streams.
-constexpr uint32_t OVERLAP_CELL_PER_CU = 2;
+constexpr uint32_t OVERLAP_CELL_PER_CU = 3;
 
 struct RunArgs {
     uint32_t lanes = 1;          // real queries in this launch (<= k_pow2)

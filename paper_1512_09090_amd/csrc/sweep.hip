@@ -1516,7 +1516,7 @@ __host__ __device__ __forceinline__ uint32_t c2_words(uint32_t cnt, uint32_t nl,
 }
 // LDS words of a cell workgroup: control, candidates, the largest blob, label rows of W lanes.
 __host__ __device__ __forceinline__ uint32_t c2_lds_words(uint32_t blob_words, uint32_t rows, uint32_t w) {
-    return ((blob_words + 3u) & ~3u) + ((rows * (w | 1u) + 3u) & ~3u) + C2_CAND + C2_CTL;
+    return ((blob_words + 3u) & ~3u) + ((rows * w + 3u) & ~3u) + C2_CAND + C2_CTL;
 }
 
 
@@ -1607,7 +1607,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
             fl[k] = valid && (x.fwd || x.rev);
         }
 #pragma unroll
-        for (uint32_t k = 0; k < 4; ++k) t[k] = s_lab[row[k] * (W | 1u) + j];
+        for (uint32_t k = 0; k < 4; ++k) t[k] = s_lab[(row[k] << lw) + j];
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k) {
             dv = min(dv, sat_add(t[k], w[k]));
@@ -1617,7 +1617,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
     }
     const bool vin = dv <= tau;
     if (act) {
-        if (i < stored) s_lab[i * (W | 1u) + j] = dv;
+        if (i < stored) s_lab[(i << lw) + j] = dv;
         if (A.dist_out && live) A.dist_out[(uint64_t(cb + i) << A.lk) + lane] = dv;
     }
     if (A.vmask) {   // lanes in range, ORed over the vertex's W slots (consecutive threads)
@@ -1630,7 +1630,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
     if (!(act && live && (vin ? fout : fin))) return;
     for (uint32_t e = e0; e < e1; ++e) {
         const C2Ent x = c2_entry<PACKED>(s_ent, e, lb);
-        if (!(x.fwd || x.rev) || ((s_lab[x.row * (W | 1u) + j] <= tau) == vin)) continue;
+        if (!(x.fwd || x.rev) || ((s_lab[(x.row << lw) + j] <= tau) == vin)) continue;
         if (x.fwd) c2_push(A, s_cand, s_ctl, A.lane_base + lane, ebase + e, 0u);
         if (x.rev) c2_push(A, s_cand, s_ctl, A.lane_base + lane, ebase + e, 1u);
     }
@@ -1639,8 +1639,7 @@ __device__ __forceinline__ void c2_vertex(const Cell2Args &A, bool act, uint32_t
 // A lane chunk of a staged cell: ranks [q0, q0 + W) of the cell's active lanes (W a power of
 // two).  Thread t serves lane slot j = t mod W of vertex slot t / W; live (a real lane), lane
 // (the batch lane), tau, up (its source lies in the cell: the upward labels start the vertex's
-// label).  The label rows follow the blob, W + 1 words apart (W > 1) so that the vertex slots'
-// reads spread over the LDS banks.
+// label).  The label rows (W words each) follow the blob.
 struct C2Lane {
     uint32_t W, lw, j, lane, tau;
     bool live, up;
@@ -1665,7 +1664,7 @@ __device__ __forceinline__ C2Lane c2_lane(const Cell2Args &A, uint32_t c, uint64
 // barrier.
 __device__ __forceinline__ void c2_rows(const Cell2Args &A, const C2Lane &q, const uint32_t *s_refs, uint32_t nrefs,
                                         uint32_t *s_lab, uint32_t stored) {
-    const uint32_t step = blockDim.x >> q.lw, S = q.W | 1u;
+    const uint32_t step = blockDim.x >> q.lw;
     for (uint32_t r = threadIdx.x >> q.lw; r < nrefs; r += 4 * step) {
         uint32_t v[4];
 #pragma unroll
@@ -1675,7 +1674,7 @@ __device__ __forceinline__ void c2_rows(const Cell2Args &A, const C2Lane &q, con
         }
 #pragma unroll
         for (uint32_t k = 0; k < 4; ++k)
-            if (r + k * step < nrefs) s_lab[(stored + r + k * step) * S + q.j] = v[k];
+            if (r + k * step < nrefs) s_lab[((stored + r + k * step) << q.lw) + q.j] = v[k];
     }
     __syncthreads();
 }

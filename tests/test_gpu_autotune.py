@@ -18,7 +18,7 @@ def test_autotune_reduced_space(tmp_path):
     G = iso.Graph.from_synth(g, num_cells=256, device=0)
     src, tau = synth.batch_queries(g.n, 192, seed=17, lo_min=1, hi_min=120)
     ref = G.query_batch(src, tau, iso.MODE_CELLS)
-    space = {"lanes_per_launch": [32, 64], "cell_lds_kb": [40, 64], "use_graph": [0, 1], "overlap_cells": [0, 3]}
+    space = {"lanes_per_launch": [32, 64], "cell_lds_kb": [40, 64], "use_graph": [0, 1], "overlap_cells": [0, 2]}
     res = autotune.tune(G, src, tau, space=space,
                         log=lambda m: print(m, file=sys.stderr, flush=True))
     best = res["best"]
