@@ -598,10 +598,12 @@ k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_
     const uint32_t j = __lane_id(), tau = A.taus[j];
     const uint2 *__restrict__ darc = A.down_arc;
     uint32_t *__restrict__ lab = A.dcore;
-    for (uint32_t i = s0 + w0 * PV; i < s1; i += nw * PV) {   // uniform over the wavefront
-        // lane j: word j mod PLAIN_REC of the record of list entry i + j / PLAIN_REC
-        const uint32_t me = min(i + j / PLAIN_REC, s1 - 1u);
-        const uint2 r = prec[uint64_t(me) * PLAIN_REC + (j % PLAIN_REC)];
+    // lane j: word j mod PLAIN_REC of the record of list entry i + j / PLAIN_REC (a wavefront's
+    // next records are loaded while it works on the current ones)
+    uint32_t i = s0 + w0 * PV;
+    uint2 r = i < s1 ? prec[uint64_t(min(i + j / PLAIN_REC, s1 - 1u)) * PLAIN_REC + (j % PLAIN_REC)]
+                     : make_uint2(0u, 0u);
+    for (; i < s1; i += nw * PV) {   // uniform over the wavefront
         uint32_t v[PV], beg[PV], end[PV], wr[PV], dv[PV], in[PV], flag[PV];
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q) {
@@ -612,6 +614,8 @@ k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_
             wr[q] = uint32_t(__builtin_amdgcn_readlane(int(r.y), int(q * PLAIN_REC + 1)));
             if (!act) end[q] = beg[q];
         }
+        // the next records (past the share: its last record again, whose load stays in bounds)
+        const uint2 rn = prec[uint64_t(min(i + nw * PV + j / PLAIN_REC, s1 - 1u)) * PLAIN_REC + (j % PLAIN_REC)];
         uint32_t sl[PV];
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q) sl[q] = A.uslot[v[q]];
@@ -687,6 +691,7 @@ k_plain_level64(CoreArgs A, const uint2 *__restrict__ prec, uint32_t lb, uint32_
 #pragma unroll
         for (uint32_t q = 0; q < PV; ++q)
             if (i + q < s1) plain_extract(A, darc, lab, beg[q], end[q], in[q], flag[q], dv[q], tau, j, s_keys, &s_n);
+        r = rn;
     }
     keys_end(s_keys, &s_n, &s_base, A);
 }
